@@ -1,0 +1,40 @@
+"""FP64 CPU oracle for spherical-harmonic Sinkhorn (heat-kernel Sinkhorn on S^2).
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, plain, obviously-correct
+reference that the HIP path is checked against.  Only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
+import it.  It shares no code with ``paper_2605_18389_amd`` and imports nothing
+from it; the two meet only through seeded input arrays.
+
+Everything is float64 NumPy, written step by step from the paper:
+
+* ``grids``      -- Gauss-Legendre and Clenshaw-Curtis (equiangular with poles)
+                    latitude quadrature and area weights (App. C.1 "Discretizations
+                    of S^2", App. C.2 "Discrete OT on the Sphere").
+* ``legendre``   -- orthonormal associated Legendre functions P̄_l^m (App. B,
+                    definition of Y_lm and N_lm).
+* ``sht``        -- semi-naive SHT (rFFT in longitude, per-order Legendre
+                    projection) and HeatConv (Sec. 3.2, "Algorithm" paragraph).
+* ``dense``      -- the same operator written as a dense radial kernel via the
+                    addition theorem (Prop. 3.4 / Thm. 3.3); a test pin only.
+* ``sinkhorn``   -- Algorithm 1 (balanced and unbalanced branches), potentials,
+                    cost (App. C.2 eq. for OT^tau_{C,eps}), convergence check
+                    (App. C.3), divergence (Def. 2.3), envelope gradient (Sec. 4.2.2).
+
+Readings where the paper is silent or inconsistent are listed in the design doc
+(heat time t = eps/4 everywhere, l < L, Alg. 1 taken literally, ...).
+"""
+
+from .grids import Grid, gauss_legendre, clenshaw_curtis, make_grid
+from .legendre import legendre_table, normalised_legendre_column
+from .sht import analysis, synthesis, heat_apply, heat_multipliers
+from .dense import dense_heat_matrix, dense_heat_apply
+from .sinkhorn import sinkhorn, divergence, envelope_gradient, fd_directional
+
+__all__ = [
+    "Grid", "gauss_legendre", "clenshaw_curtis", "make_grid",
+    "legendre_table", "normalised_legendre_column",
+    "analysis", "synthesis", "heat_apply", "heat_multipliers",
+    "dense_heat_matrix", "dense_heat_apply",
+    "sinkhorn", "divergence", "envelope_gradient", "fd_directional",
+]

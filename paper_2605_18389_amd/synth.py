@@ -1,0 +1,110 @@
+"""Seeded synthetic measures on iso-latitude grids.
+
+Input generation only: nothing here evaluates the heat operator, the SHT or
+Sinkhorn.  The caller passes the grid's nodes x_j = cos(colatitude) and its
+latitude weights w_j (sum 2); normalisation uses the area weights
+a_{jk} = w_j * 2 pi / nlon so that sum_jk a_{jk} p_{jk} equals the requested mass.
+Points follow App. B's parametrisation x = (cos phi sin theta, sin phi sin theta,
+cos theta), phi_k = 2 pi k / nlon.
+
+Generators (all draws from numpy's PCG64 ``default_rng(seed)`` in a fixed order):
+
+* ``vmf_mixture``   -- equal-weight mixture of von Mises-Fisher densities
+                       kappa/(2 pi (1 - e^{-2 kappa})) e^{kappa (mu.x - 1)} plus a floor.
+                       Per measure: K centres (3 normals each, normalised), then
+                       K concentrations kappa ~ U[5, 50].
+* ``temperature_like`` -- zonal cos^2(latitude) background times
+                       (1 + sum_k amp_k e^{kappa_k (mu_k.x - 1)}), clipped at 0, plus
+                       a 1e-6 floor.  Per measure: K centres, K kappa ~ U[5, 50],
+                       K amplitudes ~ U[-0.2, 0.2].
+* ``uniform_field`` -- i.i.d. U[0, 1] per point, normalised.
+"""
+
+import math
+
+import numpy as np
+
+
+def _points(x, nlon):
+    x = np.asarray(x, dtype=np.float64)
+    st = np.sqrt(np.maximum(0.0, 1.0 - x * x))[:, None]
+    ph = 2.0 * np.pi * np.arange(nlon)[None, :] / nlon
+    return np.stack(np.broadcast_arrays(np.cos(ph) * st, np.sin(ph) * st, x[:, None] + 0 * ph), -1)
+
+
+def _centres(rng, K):
+    c = rng.standard_normal((K, 3))
+    return c / np.linalg.norm(c, axis=1, keepdims=True)
+
+
+def _normalise(f, w, nlon, total):
+    a = (np.asarray(w, dtype=np.float64) * 2.0 * np.pi / nlon)[:, None]
+    return f * (total / float((a * f).sum()))
+
+
+def vmf_mixture(rng, x, w, nlon, K=4, floor=1e-6, total=1.0):
+    X = _points(x, nlon)
+    mu = _centres(rng, K)
+    kap = rng.uniform(5.0, 50.0, K)
+    f = np.zeros(X.shape[:2])
+    for k in range(K):
+        dens = kap[k] / (2.0 * np.pi * (1.0 - math.exp(-2.0 * kap[k])))
+        f += dens * np.exp(kap[k] * (X @ mu[k] - 1.0)) / K
+    return _normalise(f + floor, w, nlon, total)
+
+
+def temperature_like(rng, x, w, nlon, K=8, floor=1e-6, total=1.0):
+    X = _points(x, nlon)
+    mu = _centres(rng, K)
+    kap = rng.uniform(5.0, 50.0, K)
+    amp = rng.uniform(-0.2, 0.2, K)
+    anom = np.ones(X.shape[:2])
+    for k in range(K):
+        anom += amp[k] * np.exp(kap[k] * (X @ mu[k] - 1.0))
+    cos2lat = (1.0 - np.asarray(x, dtype=np.float64) ** 2)[:, None]
+    f = np.maximum(cos2lat * anom, 0.0) + floor
+    return _normalise(f, w, nlon, total)
+
+
+def uniform_field(rng, x, w, nlon, total=1.0):
+    f = rng.uniform(0.0, 1.0, (len(x), nlon))
+    return _normalise(f, w, nlon, total)
+
+
+def pair_seed(config_index, pair_index):
+    """Seed of pair i of workload c: 1000 c + i."""
+    return 1000 * config_index + pair_index
+
+
+def vmf_pair(seed, x, w, nlon, K=4):
+    """Two probability measures of ``vmf_mixture``, q drawn after p from one stream."""
+    rng = np.random.default_rng(seed)
+    p = vmf_mixture(rng, x, w, nlon, K)
+    q = vmf_mixture(rng, x, w, nlon, K)
+    return p, q
+
+
+def temperature_pair(seed, x, w, nlon, K=8, q_mass=1.0):
+    """Two ``temperature_like`` measures; q is scaled to total mass ``q_mass``."""
+    rng = np.random.default_rng(seed)
+    p = temperature_like(rng, x, w, nlon, K)
+    q = temperature_like(rng, x, w, nlon, K, total=q_mass)
+    return p, q
+
+
+def batch_pair_params(seed, npairs):
+    """Per-pair (t, tau, q_mass) of the uneven batched workload.
+
+    t = 10^U[-4,-2]; even pairs balanced (tau = inf, equal masses); odd pairs
+    unbalanced with tau drawn from {0.1, 1, 10} and masses 1 vs 1.05.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(npairs):
+        t = 10.0 ** rng.uniform(-4.0, -2.0)
+        if i % 2 == 0:
+            out.append((t, math.inf, 1.0))
+        else:
+            tau = (0.1, 1.0, 10.0)[int(rng.integers(0, 3))]
+            out.append((t, tau, 1.05))
+    return out

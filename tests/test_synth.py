@@ -1,0 +1,40 @@
+"""Seeded generators: determinism, masses, positivity and draw order."""
+
+import math
+
+import numpy as np
+
+import oracle as O
+from paper_2605_18389_amd import synth
+
+
+def test_pairs_deterministic_and_normalised():
+    g = O.make_grid("gl", 18, 36, 18)
+    a = g.area
+    p1, q1 = synth.temperature_pair(7, g.x, g.w, 36, K=8, q_mass=1.05)
+    p2, q2 = synth.temperature_pair(7, g.x, g.w, 36, K=8, q_mass=1.05)
+    assert np.array_equal(p1, p2) and np.array_equal(q1, q2)
+    assert abs((a * p1).sum() - 1.0) < 1e-14
+    assert abs((a * q1).sum() - 1.05) < 1e-14
+    assert p1.min() > 0 and q1.min() > 0
+    assert not np.array_equal(p1, q1)
+    pv, qv = synth.vmf_pair(0, g.x, g.w, 36)
+    assert abs((a * pv).sum() - 1.0) < 1e-14 and pv.min() >= 1e-6 * 0.5
+
+
+def test_cc_poles_get_floor():
+    g = O.make_grid("cc", 9, 16, 8)
+    p, _ = synth.temperature_pair(1, g.x, g.w, 16)
+    # cos^2(latitude) vanishes at the pole rows; only the floor remains there
+    assert np.allclose(p[0], p[0, 0]) and p[0, 0] < 1e-4
+
+
+def test_batch_params():
+    prm = synth.batch_pair_params(3, 256)
+    assert len(prm) == 256
+    for i, (t, tau, qm) in enumerate(prm):
+        assert 1e-4 <= t <= 1e-2
+        if i % 2 == 0:
+            assert math.isinf(tau) and qm == 1.0
+        else:
+            assert tau in (0.1, 1.0, 10.0) and qm == 1.05
