@@ -1,0 +1,192 @@
+/*
+ * shot.h -- C ABI of libshot: heat-kernel Sinkhorn on the sphere S^2 on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method (arXiv 2605.18389, "Spherical Harmonic Optimal Transport"):
+ *   HeatConv(v) = F^{-1}( h (.) F(v) ), h_l = exp(-t l(l+1)), l < L      (Sec. 3.2)
+ *   F = semi-naive SHT: FFT along latitude rows, then per-order Legendre
+ *       projection with quadrature weights                              (App. C.1)
+ *   Sinkhorn scaling loop, balanced and unbalanced, potentials and cost (Alg. 1, App. C.2)
+ *   Sinkhorn divergence S = OT(p,q) - (OT(p,p)+OT(q,q))/2 + eps/2 (m(p)-m(q))^2  (Def. 2.3)
+ *   its gradient with respect to the input measure                      (Sec. 4.2.2)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grids.  Iso-latitude grids of nlat rows x nlon columns.  Row 0 is the
+ *   northernmost row (colatitude closest to 0), column k sits at longitude
+ *   2*pi*k/nlon.  The band limit L keeps degrees and orders l, m < L and needs
+ *   nlon >= 2L-1.  nlon must factor into 2, 3 and 5 and be at most 2048, and
+ *   (2*ceil(nlat/2) + L) complex values of the field precision must fit in
+ *   60 KiB (SHOT_E_UNSUPPORTED otherwise).  Area weights a_{jk} = w_j * 2*pi/nlon
+ *   sum to 4*pi.
+ * Items.  A call processes nitems independent items; item i lives on grid
+ *   grid_of_item[i] (an index into the plan's grids).  Field arrays hold the
+ *   items back to back, item i starting at element sum_{i'<i} nlat*nlon of
+ *   grid_of_item[i'], each item row-major [nlat][nlon].
+ * Precision.  SHOT_FP64 plans take and return double fields and compute in
+ *   float64.  SHOT_FP32 and SHOT_BF16_MFMA plans take and return float fields;
+ *   FFTs and pointwise updates run in float32, the Legendre stage in float32
+ *   (SHOT_FP32) or in bfloat16 operands with float32 accumulation
+ *   (SHOT_BF16_MFMA).  Quadrature, Legendre recurrence coefficients and every
+ *   final reduction (cost, divergence, norms) are float64 in all plans.
+ * Memory.  Pointers documented "device" must be device memory of the GPU
+ *   that was current when the plan was made; "host" pointers are ordinary
+ *   host memory.  The caller owns every argument buffer; the plan owns its
+ *   tables and its workspace.  Calls on one plan must be serialised (they share
+ *   the workspace).  `stream` is a hipStream_t (NULL = default stream); work is
+ *   enqueued on it, and entry points that return host results synchronise it.
+ * Errors.  Every entry point validates its arguments before any launch and
+ *   returns SHOT_E_INVALID (nothing launched) on a bad argument, SHOT_E_NOMEM
+ *   when device memory cannot be obtained, SHOT_E_HIP on a HIP runtime error.
+ *   Solver entry points return the worst per-item status.  Nothing is clamped
+ *   silently: a non-positive or non-finite heat-kernel output is reported as
+ *   SHOT_E_BREAKDOWN with the first iteration at which it happened (App. C.4).
+ */
+#ifndef SHOT_H
+#define SHOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct shot_plan_s* shot_plan_t;
+
+typedef enum {
+  SHOT_OK = 0,
+  SHOT_E_INVALID = 1,
+  SHOT_E_NOMEM = 2,
+  SHOT_E_HIP = 3,
+  SHOT_E_UNSUPPORTED = 4,
+  SHOT_W_NOT_CONVERGED = 16, /* tol > 0 and e_marg >= tol after max_iter iterations */
+  SHOT_E_BREAKDOWN = 17      /* heat-kernel output <= 0 or non-finite (App. C.4)   */
+} shot_status;
+
+enum { SHOT_GRID_GAUSS_LEGENDRE = 0, SHOT_GRID_CLENSHAW_CURTIS = 1 };
+enum { SHOT_FP64 = 0, SHOT_FP32 = 1, SHOT_BF16_MFMA = 2 };
+enum { SHOT_LEG_AUTO = 0, SHOT_LEG_TABLE = 1, SHOT_LEG_RECURRENCE = 2 };
+
+/* One grid.  kind: SHOT_GRID_GAUSS_LEGENDRE (rows at the roots of P_nlat) or
+ * SHOT_GRID_CLENSHAW_CURTIS (equiangular rows theta_j = j*pi/(nlat-1), poles
+ * included) -- App. C.1. */
+typedef struct {
+  int32_t kind;
+  int32_t nlat;
+  int32_t nlon;
+  int32_t L;
+} shot_grid_desc;
+
+/* Alg. 1 inputs other than the marginals (its REQUIRE list).  The heat time is
+ * t = eps/4 (Alg. 1, first step). */
+typedef struct {
+  double eps;          /* entropic parameter, > 0                                  */
+  double tau;          /* marginal penalty, > 0; +INFINITY selects the balanced branch */
+  int32_t max_iter;    /* T >= 1                                                   */
+  int32_t check_every; /* C >= 1: e_marg is evaluated when k mod C == 0 (App. C.3)  */
+  double tol;          /* delta >= 0: stop when e_marg < delta; 0 runs exactly T    */
+} shot_params;
+
+/* Per-solve report. */
+typedef struct {
+  double cost;            /* Alg. 1 return value (float64 reduction)                  */
+  double err;             /* e_marg of the returned scalings (App. C.3)               */
+  int32_t iters;          /* iterations run                                           */
+  int32_t status;         /* shot_status of this item                                 */
+  int32_t breakdown_iter; /* first iteration with K. <= 0 or non-finite, 0 if none     */
+  int32_t reserved;
+} shot_solve_info;
+
+/* Build a plan for `ngrids` grids (host array).  Computes the float64
+ * quadrature (App. C.1), the FFT factorisations and, for SHOT_LEG_TABLE, the
+ * table of orthonormal P_l^m(x_j) on the northern rows (App. B normalisation
+ * N_lm), stored in the plan's Legendre precision; SHOT_LEG_RECURRENCE instead
+ * keeps O(L^2 + L*nlat) recurrence coefficients and seeds and generates
+ * P_l^m in float64 inside the kernels (the O(n) memory claim of Sec. 3.2).
+ * SHOT_LEG_AUTO picks per grid.  `precision` is SHOT_FP64, SHOT_FP32 or
+ * SHOT_BF16_MFMA.  On success *out holds the plan; on failure *out is NULL. */
+shot_status shot_sht_plan(shot_plan_t* out, const shot_grid_desc* grids, int32_t ngrids,
+                          int32_t precision, int32_t legendre_mode, void* stream);
+
+/* Free a plan and everything it owns.  NULL is accepted. */
+shot_status shot_plan_destroy(shot_plan_t plan);
+
+/* Copy grid `grid`'s float64 nodes x_j = cos(colatitude_j) and latitude
+ * weights w_j (sum 2) into host arrays of nlat entries each (either may be NULL). */
+shot_status shot_plan_grid(shot_plan_t plan, int32_t grid, double* x_out, double* w_out);
+
+/* Forward SHT (App. B: f_lm = <f, Y_lm>, evaluated by App. C.1's semi-naive
+ * algorithm).  f: device, fields of the items.  coeffs: device, per item
+ * L(L+1)/2 complex values (real, imag interleaved, field precision), ordered by
+ * m then l: f_lm for m = 0..L-1, l = m..L-1, at index m*L - m(m-1)/2 + (l-m).
+ * Items are packed back to back in that layout. */
+shot_status shot_sht_analysis(shot_plan_t plan, const int32_t* grid_of_item, int32_t nitems,
+                              const void* f, void* coeffs, void* stream);
+
+/* Inverse SHT of coefficients in shot_sht_analysis's layout (orders m >= 0;
+ * negative orders follow from the field being real). coeffs, f: device. */
+shot_status shot_sht_synthesis(shot_plan_t plan, const int32_t* grid_of_item, int32_t nitems,
+                                const void* coeffs, void* f, void* stream);
+
+/* HeatConv (Sec. 3.2): out_i = F^{-1}(h (.) F(v_i)) with h_l = exp(-t[i] l(l+1)).
+ * t: host, nitems heat times >= 0.  v, out: device fields (may not alias).
+ * transpose != 0 applies the transpose of that linear map instead,
+ * out = a (.) HeatConv(v / a), used by adjoints. */
+shot_status shot_heat_apply(shot_plan_t plan, const int32_t* grid_of_item, int32_t nitems,
+                            const double* t, const void* v, void* out, int32_t transpose,
+                            void* stream);
+
+/* Alg. 1 on nitems independent items.  params: host, one per item.  p, q:
+ * device marginals (densities with respect to the area weights, positive).
+ * phi, psi: device outputs, eps*log(u) and eps*log(v) (either may be NULL).
+ * info: host, nitems reports.  Synchronises `stream`. */
+shot_status shot_sinkhorn_solve(shot_plan_t plan, const int32_t* grid_of_item, int32_t nitems,
+                                const shot_params* params, const void* p, const void* q,
+                                void* phi, void* psi, shot_solve_info* info, void* stream);
+
+/* Sinkhorn divergence (Def. 2.3) of npairs pairs: three Alg. 1 solves per pair,
+ * (p,q), (p,p) and (q,q), advanced together, combined in float64 as
+ * S = R(p,q) - (R(p,p)+R(q,q))/2 + eps/2 (m(p)-m(q))^2, m(p) = sum a p.
+ * params: host, one per pair.  S_out: host, npairs.  info: host, 3*npairs
+ * reports in the order (p,q),(p,p),(q,q) per pair, or NULL.  Synchronises. */
+shot_status shot_sinkhorn_divergence(shot_plan_t plan, const int32_t* grid_of_pair, int32_t npairs,
+                                     const shot_params* params, const void* p, const void* q,
+                                     double* S_out, shot_solve_info* info, void* stream);
+
+/* Divergence and its gradient with respect to the density array p (Sec. 4.2.2),
+ * balanced pairs only (tau = +INFINITY), with tol = 0.
+ * mode 0: exact reverse-mode derivative of the T-iteration computation
+ *         (hand-written adjoint of Alg. 1 and of HeatConv); the forward iterates
+ *         are recomputed from checkpoints of v taken every `checkpoint_every`
+ *         iterations (0 = ceil(sqrt(T))) instead of being stored.
+ * mode 1: envelope gradient from the potentials,
+ *         a (.) (phi_pq - (phi_pp + psi_pp)/2) + eps (m(p)-m(q)) a.
+ * dS_dp: device, layout of p.  Other arguments as shot_sinkhorn_divergence. */
+shot_status shot_sinkhorn_divergence_grad(shot_plan_t plan, const int32_t* grid_of_pair,
+                                          int32_t npairs, const shot_params* params,
+                                          const void* p, const void* q, double* S_out,
+                                          void* dS_dp, int32_t mode, int32_t checkpoint_every,
+                                          shot_solve_info* info, void* stream);
+
+/* Kernel timing.  When enabled, every launch of the Legendre kernels (class 0)
+ * and of the row-FFT kernels (class 1) is bracketed by HIP events on the
+ * launch stream; shot_profile_read synchronises and returns the number of
+ * timed launches and their summed duration in milliseconds for one class.
+ * shot_profile_enable(plan, 0) stops timing; enabling again resets the counts. */
+shot_status shot_profile_enable(shot_plan_t plan, int32_t enable);
+shot_status shot_profile_read(shot_plan_t plan, int32_t kernel_class, int64_t* launches,
+                              double* total_ms);
+
+/* Human-readable name of a status code (static storage). */
+const char* shot_status_string(int32_t status);
+
+/* Description of the most recent HIP runtime failure seen by libshot on the
+ * calling thread (the call, its source line and the HIP error string), or ""
+ * if none.  Valid until the next libshot call on this thread. */
+const char* shot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHOT_H */

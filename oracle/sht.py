@@ -43,7 +43,7 @@ def analysis(f, grid):
     out = []
     for m in range(grid.L):
         y = F[..., :, m] * wq                      # (..., nlat)
-        out.append(y @ tab[m].T)                   # (..., L-m)
+        out.append((y.real @ tab[m].T) + 1j * (y.imag @ tab[m].T))   # (..., L-m)
     return out
 
 
@@ -53,7 +53,8 @@ def synthesis(coeffs, grid):
     lead = coeffs[0].shape[:-1]
     G = np.zeros(lead + (grid.nlat, grid.nlon // 2 + 1), dtype=np.complex128)
     for m in range(grid.L):
-        G[..., :, m] = coeffs[m] @ tab[m]
+        c = np.asarray(coeffs[m])
+        G[..., :, m] = (c.real @ tab[m]) + 1j * (c.imag @ tab[m])
     return np.fft.irfft(G, n=grid.nlon, axis=-1) * grid.nlon
 
 

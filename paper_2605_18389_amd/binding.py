@@ -1,0 +1,339 @@
+"""ctypes binding of libshot (include/shot.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels
+of libshot.so.  PyTorch provides device memory and the current stream.  If
+the shared library has not been built, loading fails loudly -- there is no
+CPU fallback.
+"""
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshot.so")
+
+GRID_GAUSS_LEGENDRE = 0
+GRID_CLENSHAW_CURTIS = 1
+FP64, FP32, BF16_MFMA = 0, 1, 2
+LEG_AUTO, LEG_TABLE, LEG_RECURRENCE = 0, 1, 2
+
+OK = 0
+E_INVALID = 1
+E_NOMEM = 2
+E_HIP = 3
+E_UNSUPPORTED = 4
+W_NOT_CONVERGED = 16
+E_BREAKDOWN = 17
+
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16_MFMA, "bf16_mfma": BF16_MFMA}
+_LEG = {"auto": LEG_AUTO, "table": LEG_TABLE, "recurrence": LEG_RECURRENCE}
+_KIND = {"gl": GRID_GAUSS_LEGENDRE, "gauss_legendre": GRID_GAUSS_LEGENDRE,
+         "cc": GRID_CLENSHAW_CURTIS, "clenshaw_curtis": GRID_CLENSHAW_CURTIS,
+         "equiangular": GRID_CLENSHAW_CURTIS}
+
+# Every entry point declared in include/shot.h.
+EXPORTS = [
+    "shot_sht_plan", "shot_plan_destroy", "shot_plan_grid", "shot_sht_analysis",
+    "shot_sht_synthesis", "shot_heat_apply", "shot_sinkhorn_solve", "shot_sinkhorn_divergence",
+    "shot_sinkhorn_divergence_grad", "shot_profile_enable", "shot_profile_read",
+    "shot_status_string", "shot_last_error",
+]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nlat", ctypes.c_int32), ("nlon", ctypes.c_int32),
+                ("L", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("tau", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("cost", ctypes.c_double), ("err", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("breakdown_iter", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class ShotError(RuntimeError):
+    def __init__(self, fn, code):
+        self.code = code
+        detail = ""
+        if code == E_HIP or code == E_NOMEM:
+            try:
+                detail = " -- " + load_library().shot_last_error().decode()
+            except Exception:
+                pass
+        super().__init__(f"{fn} failed: {status_string(code)} ({code}){detail}")
+
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libshot.so (once).  Raises if it is missing: no fallback exists."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"libshot.so is not built ({path}); run `python -m paper_2605_18389_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname; load it first so
+    # that libshot binds to that one runtime and shares torch's device memory
+    # and streams (a second runtime loaded ahead of torch does not see the GPU).
+    _torch()
+    lib = ctypes.CDLL(path)
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "shot_sht_plan": [ctypes.POINTER(vp), ctypes.POINTER(GridDesc), i32, i32, i32, vp],
+        "shot_plan_destroy": [vp],
+        "shot_plan_grid": [vp, i32, dp, dp],
+        "shot_sht_analysis": [vp, ip, i32, vp, vp, vp],
+        "shot_sht_synthesis": [vp, ip, i32, vp, vp, vp],
+        "shot_heat_apply": [vp, ip, i32, dp, vp, vp, i32, vp],
+        "shot_sinkhorn_solve": [vp, ip, i32, ctypes.POINTER(Params), vp, vp, vp, vp,
+                                ctypes.POINTER(SolveInfo), vp],
+        "shot_sinkhorn_divergence": [vp, ip, i32, ctypes.POINTER(Params), vp, vp, dp,
+                                     ctypes.POINTER(SolveInfo), vp],
+        "shot_sinkhorn_divergence_grad": [vp, ip, i32, ctypes.POINTER(Params), vp, vp, dp, vp, i32,
+                                          i32, ctypes.POINTER(SolveInfo), vp],
+        "shot_profile_enable": [vp, i32],
+        "shot_profile_read": [vp, i32, ctypes.POINTER(ctypes.c_int64), dp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    lib.shot_status_string.argtypes = [i32]
+    lib.shot_status_string.restype = ctypes.c_char_p
+    lib.shot_last_error.argtypes = []
+    lib.shot_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(code):
+    try:
+        return load_library().shot_status_string(int(code)).decode()
+    except Exception:
+        return str(code)
+
+
+def _check(fn, code, allow=(OK,)):
+    if code not in allow:
+        raise ShotError(fn, code)
+    return code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _i32_array(vals):
+    a = (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
+    return a
+
+
+class Plan:
+    """A libshot plan for one or more grids.
+
+    grids: list of (kind, nlat, nlon, L) with kind "gl" or "cc".
+    precision: "fp64", "fp32" or "bf16" (bfloat16 Legendre operands, float32 accumulation).
+    legendre: "auto", "table" (P̄ streamed from HBM) or "recurrence" (generated in float64).
+    """
+
+    def __init__(self, grids, precision="fp32", legendre="auto"):
+        self.lib = load_library()
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libshot needs a ROCm GPU")
+        self.grids = [(g[0], int(g[1]), int(g[2]), int(g[3])) for g in grids]
+        self.precision = precision
+        self.prec_code = _PREC[precision]
+        self.dtype = torch.float64 if self.prec_code == FP64 else torch.float32
+        arr = (GridDesc * len(self.grids))(*[GridDesc(_KIND[k] if isinstance(k, str) else int(k), a, b, c)
+                                              for k, a, b, c in self.grids])
+        h = ctypes.c_void_p()
+        _check("shot_sht_plan", self.lib.shot_sht_plan(ctypes.byref(h), arr, len(self.grids), self.prec_code,
+                                                       _LEG[legendre], _stream_ptr()))
+        self.handle = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.shot_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ grid
+    def grid_nodes(self, grid=0):
+        nlat = self.grids[grid][1]
+        x = np.zeros(nlat)
+        w = np.zeros(nlat)
+        _check("shot_plan_grid", self.lib.shot_plan_grid(
+            self.handle, grid, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return x, w
+
+    def area(self, grid=0):
+        _, nlat, nlon, _ = self.grids[grid]
+        _, w = self.grid_nodes(grid)
+        return np.repeat((w * 2 * np.pi / nlon)[:, None], nlon, axis=1)
+
+    def field_size(self, grid):
+        return self.grids[grid][1] * self.grids[grid][2]
+
+    def ncoeff(self, grid):
+        L = self.grids[grid][3]
+        return L * (L + 1) // 2
+
+    # --------------------------------------------------------------- helpers
+    def _items(self, x, grid_of_item, per_item):
+        """Resolve (tensor, grid_of_item) -> (flat tensor, int32 array)."""
+        torch = _torch()
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError("expected a CUDA (ROCm) tensor")
+        if x.dtype != (self.dtype if per_item != "coeff" else self.dtype):
+            raise TypeError(f"expected dtype {self.dtype}, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        if grid_of_item is None:
+            if len(self.grids) != 1:
+                raise ValueError("grid_of_item is required for multi-grid plans")
+            unit = self.field_size(0) if per_item == "field" else 2 * self.ncoeff(0)
+            if x.numel() % unit:
+                raise ValueError("tensor size is not a multiple of the item size")
+            grid_of_item = [0] * (x.numel() // unit)
+        grid_of_item = [int(g) for g in grid_of_item]
+        unit = [self.field_size(g) if per_item == "field" else 2 * self.ncoeff(g) for g in grid_of_item]
+        if sum(unit) != x.numel():
+            raise ValueError(f"tensor has {x.numel()} elements, items need {sum(unit)}")
+        return grid_of_item
+
+    # ------------------------------------------------------------ operators
+    def heat_apply(self, v, t, grid_of_item=None, transpose=False, out=None):
+        torch = _torch()
+        goi = self._items(v, grid_of_item, "field")
+        n = len(goi)
+        tv = np.broadcast_to(np.asarray(t, dtype=np.float64), (n,)).copy()
+        if out is None:
+            out = torch.empty_like(v)
+        _check("shot_heat_apply", self.lib.shot_heat_apply(
+            self.handle, _i32_array(goi), n, tv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(bool(transpose)),
+            _stream_ptr()))
+        return out
+
+    def analysis(self, f, grid_of_item=None):
+        """Forward SHT; returns complex coefficients packed by (m, l) per item."""
+        torch = _torch()
+        goi = self._items(f, grid_of_item, "field")
+        total = sum(self.ncoeff(g) for g in goi)
+        c = torch.empty(2 * total, dtype=self.dtype, device=f.device)
+        _check("shot_sht_analysis", self.lib.shot_sht_analysis(
+            self.handle, _i32_array(goi), len(goi), ctypes.c_void_p(f.data_ptr()),
+            ctypes.c_void_p(c.data_ptr()), _stream_ptr()))
+        return torch.view_as_complex(c.view(-1, 2))
+
+    def synthesis(self, coeffs, grid_of_item=None):
+        torch = _torch()
+        c = torch.view_as_real(coeffs).contiguous().view(-1) if coeffs.is_complex() else coeffs
+        goi = self._items(c, grid_of_item, "coeff")
+        total = sum(self.field_size(g) for g in goi)
+        f = torch.empty(total, dtype=self.dtype, device=c.device)
+        _check("shot_sht_synthesis", self.lib.shot_sht_synthesis(
+            self.handle, _i32_array(goi), len(goi), ctypes.c_void_p(c.data_ptr()),
+            ctypes.c_void_p(f.data_ptr()), _stream_ptr()))
+        return f
+
+    # ---------------------------------------------------------------- solver
+    @staticmethod
+    def _params(n, eps, tau, T, C, tol):
+        eps = np.broadcast_to(np.asarray(eps, dtype=np.float64), (n,))
+        tau = np.broadcast_to(np.asarray(tau, dtype=np.float64), (n,))
+        arr = (Params * n)()
+        for i in range(n):
+            arr[i] = Params(float(eps[i]), float(tau[i]), int(T), int(C), float(tol))
+        return arr
+
+    @staticmethod
+    def _info_dicts(info, n):
+        return [dict(cost=info[i].cost, err=info[i].err, iters=info[i].iters, status=info[i].status,
+                     breakdown_iter=info[i].breakdown_iter) for i in range(n)]
+
+    def sinkhorn(self, p, q, eps, tau=math.inf, T=100, C=10, tol=0.0, grid_of_item=None,
+                 potentials=True):
+        """Alg. 1 per item.  Returns (phi, psi, [info dict per item])."""
+        torch = _torch()
+        goi = self._items(p, grid_of_item, "field")
+        if q.shape != p.shape or q.dtype != p.dtype or not q.is_contiguous():
+            raise ValueError("p and q must have the same shape, dtype and be contiguous")
+        n = len(goi)
+        prm = self._params(n, eps, tau, T, C, tol)
+        info = (SolveInfo * n)()
+        phi = torch.empty_like(p) if potentials else None
+        psi = torch.empty_like(p) if potentials else None
+        code = self.lib.shot_sinkhorn_solve(
+            self.handle, _i32_array(goi), n, prm, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+            ctypes.c_void_p(phi.data_ptr() if phi is not None else 0),
+            ctypes.c_void_p(psi.data_ptr() if psi is not None else 0), info, _stream_ptr())
+        _check("shot_sinkhorn_solve", code, allow=(OK, W_NOT_CONVERGED, E_BREAKDOWN))
+        return phi, psi, self._info_dicts(info, n)
+
+    def divergence(self, p, q, eps, tau=math.inf, T=100, C=10, tol=0.0, grid_of_pair=None):
+        """Def. 2.3 per pair.  Returns (S numpy array, [info dicts, 3 per pair])."""
+        goi = self._items(p, grid_of_pair, "field")
+        n = len(goi)
+        prm = self._params(n, eps, tau, T, C, tol)
+        S = np.zeros(n)
+        info = (SolveInfo * (3 * n))()
+        code = self.lib.shot_sinkhorn_divergence(
+            self.handle, _i32_array(goi), n, prm, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+            S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), info, _stream_ptr())
+        _check("shot_sinkhorn_divergence", code, allow=(OK, W_NOT_CONVERGED, E_BREAKDOWN))
+        return S, self._info_dicts(info, 3 * n)
+
+    def divergence_grad(self, p, q, eps, T=100, C=10, mode="unrolled", checkpoint_every=0,
+                        grid_of_pair=None):
+        """S and dS/dp (balanced).  mode: "unrolled" (exact adjoint with recompute) or "envelope"."""
+        torch = _torch()
+        goi = self._items(p, grid_of_pair, "field")
+        n = len(goi)
+        prm = self._params(n, eps, math.inf, T, C, 0.0)
+        S = np.zeros(n)
+        g = torch.empty_like(p)
+        info = (SolveInfo * (3 * n))()
+        code = self.lib.shot_sinkhorn_divergence_grad(
+            self.handle, _i32_array(goi), n, prm, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+            S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_void_p(g.data_ptr()),
+            0 if mode == "unrolled" else 1, int(checkpoint_every), info, _stream_ptr())
+        _check("shot_sinkhorn_divergence_grad", code, allow=(OK, W_NOT_CONVERGED, E_BREAKDOWN))
+        return S, g, self._info_dicts(info, 3 * n)
+
+    # ------------------------------------------------------------- profiling
+    def profile(self, enable=True):
+        _check("shot_profile_enable", self.lib.shot_profile_enable(self.handle, int(bool(enable))))
+
+    def profile_read(self, kernel_class):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check("shot_profile_read", self.lib.shot_profile_read(self.handle, int(kernel_class),
+                                                                ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value

@@ -1,0 +1,886 @@
+// C ABI of libshot (declared in include/shot.h): plans, heat apply, Sinkhorn
+// solves (Alg. 1), divergence (Def. 2.3) and its gradient (Sec. 4.2.2).
+//
+// Host-side orchestration only: every arithmetic step of the hot path runs in
+// the HIP kernels of kernels.hip; the host computes plan-time float64 data
+// (quadrature, Legendre tables or recurrence data, heat multipliers) and the
+// final float64 combination of three scalar costs into a divergence.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <thread>
+#include <vector>
+
+#include "../../include/shot.h"
+#include "host_math.h"
+#include "shot_internal.h"
+
+using namespace shot;
+
+namespace {
+
+struct GridRec {
+  shot_grid_desc d{};
+  int h = 0, hpad = 0;
+  std::vector<double> x, w;
+  std::vector<int> fac;
+  int tab_kind = TAB_F32;
+  void* d_tab = nullptr;
+  double* d_xs = nullptr;
+  double* d_rcoef = nullptr;
+  double* d_rgam = nullptr;
+  double* d_rseed = nullptr;
+  void* d_aw = nullptr;
+  void* d_tw = nullptr;
+  int64_t n() const { return (int64_t)d.nlat * d.nlon; }
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Timed {
+  hipEvent_t a, b;
+  int cls;
+};
+
+}  // namespace
+
+struct shot_plan_s {
+  int prec = SHOT_FP32;
+  int dev = 0;
+  std::vector<GridRec> grids;
+  DevBuf ws;  // call workspace arena (grown on demand)
+  bool prof = false;
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> evpool;
+  size_t evnext = 0;
+  int leg_ib = 0;  // 0 = choose automatically
+};
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+shot_status hip_fail(hipError_t e, const char* what, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s (line %d): %s (%d)", what, line,
+           hipGetErrorString(e), (int)e);
+  return SHOT_E_HIP;
+}
+
+#define HIP_TRY(expr)                                         \
+  do {                                                        \
+    hipError_t e_ = (expr);                                   \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__); \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+shot_status grow(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return SHOT_OK;
+  if (b.p) {
+    if (hipFree(b.p) != hipSuccess) return SHOT_E_HIP;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    hip_fail(e, "hipMalloc(workspace)", __LINE__);
+    return SHOT_E_NOMEM;
+  }
+  b.bytes = bytes;
+  return SHOT_OK;
+}
+
+template <typename T>
+size_t real_size() { return sizeof(T); }
+
+size_t field_elem(const shot_plan_s* P) { return P->prec == SHOT_FP64 ? 8 : 4; }
+
+hipEvent_t take_event(shot_plan_s* P) {
+  if (P->evnext == P->evpool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    P->evpool.push_back(e);
+  }
+  return P->evpool[P->evnext++];
+}
+
+// Bracket one launch with events when profiling is on.
+struct ProfScope {
+  shot_plan_s* P;
+  hipStream_t s;
+  int cls;
+  hipEvent_t a = nullptr;
+  ProfScope(shot_plan_s* P_, hipStream_t s_, int cls_) : P(P_), s(s_), cls(cls_) {
+    if (P->prof) {
+      a = take_event(P);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (P->prof && a) {
+      hipEvent_t b = take_event(P);
+      if (b) {
+        (void)hipEventRecord(b, s);
+        P->timed.push_back({a, b, cls});
+      }
+    }
+  }
+};
+
+// Upload host vector -> new device allocation.
+template <typename V>
+shot_status upload(void** dst, const std::vector<V>& src, hipStream_t s) {
+  *dst = nullptr;
+  if (src.empty()) return SHOT_OK;
+  hipError_t e = hipMalloc(dst, src.size() * sizeof(V));
+  if (e != hipSuccess) { *dst = nullptr; hip_fail(e, "hipMalloc", __LINE__); return SHOT_E_NOMEM; }
+  HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SHOT_OK;
+}
+
+uint16_t to_bf16(double v) {
+  float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+void free_grid(GridRec& g) {
+  for (void* p : {g.d_tab, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam, (void*)g.d_rseed, g.d_aw, g.d_tw})
+    if (p) (void)hipFree(p);
+  g.d_tab = g.d_aw = g.d_tw = nullptr;
+  g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = nullptr;
+}
+
+shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) {
+  const auto& d = g.d;
+  if (d.kind == SHOT_GRID_GAUSS_LEGENDRE) gauss_legendre(d.nlat, g.x, g.w);
+  else clenshaw_curtis(d.nlat, g.x, g.w);
+  g.h = (d.nlat + 1) / 2;
+  g.hpad = (g.h + 3) / 4 * 4;
+  g.fac = fft_radices(d.nlon);
+  const bool f64 = P->prec == SHOT_FP64;
+  // area weights of rows 0..h-1 and twiddles in field precision
+  std::vector<double> aw(g.h);
+  for (int j = 0; j < g.h; ++j) aw[j] = g.w[j] * 2.0 * M_PI / d.nlon;
+  std::vector<double> tw(2 * (size_t)d.nlon);
+  for (int k = 0; k < d.nlon; ++k) {
+    // exp(-2 pi i k/N), argument reduced to [0, pi/2] style accuracy by long double
+    const long double ang = -2.0L * (long double)M_PI * (long double)k / (long double)d.nlon;
+    tw[2 * k] = (double)cosl(ang);
+    tw[2 * k + 1] = (double)sinl(ang);
+  }
+  shot_status st;
+  if (f64) {
+    if ((st = upload(&g.d_aw, aw, s)) != SHOT_OK) return st;
+    if ((st = upload(&g.d_tw, tw, s)) != SHOT_OK) return st;
+  } else {
+    std::vector<float> awf(aw.begin(), aw.end()), twf(tw.begin(), tw.end());
+    if ((st = upload(&g.d_aw, awf, s)) != SHOT_OK) return st;
+    if ((st = upload(&g.d_tw, twf, s)) != SHOT_OK) return st;
+  }
+  // Legendre data
+  std::vector<double> xs(g.x.begin(), g.x.begin() + g.h);
+  int mode = leg_mode;
+  if (mode == SHOT_LEG_AUTO) mode = SHOT_LEG_TABLE;
+  if (mode == SHOT_LEG_TABLE) {
+    std::vector<double> tab;
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    legendre_rows(d.L, xs, g.hpad, tab, (int)hw);
+    if (P->prec == SHOT_FP64) {
+      g.tab_kind = TAB_F64;
+      st = upload(&g.d_tab, tab, s);
+    } else if (P->prec == SHOT_FP32) {
+      g.tab_kind = TAB_F32;
+      std::vector<float> t32(tab.begin(), tab.end());
+      st = upload(&g.d_tab, t32, s);
+    } else {
+      g.tab_kind = TAB_BF16;
+      std::vector<uint16_t> t16(tab.size());
+      for (size_t i = 0; i < tab.size(); ++i) t16[i] = to_bf16(tab[i]);
+      st = upload(&g.d_tab, t16, s);
+    }
+    if (st != SHOT_OK) return st;
+  } else {
+    g.tab_kind = TAB_RECUR;
+    std::vector<double> coef, gam, seed;
+    legendre_recurrence_data(d.L, xs, coef, gam, seed);
+    if ((st = upload((void**)&g.d_xs, xs, s)) != SHOT_OK) return st;
+    if ((st = upload((void**)&g.d_rcoef, coef, s)) != SHOT_OK) return st;
+    if ((st = upload((void**)&g.d_rgam, gam, s)) != SHOT_OK) return st;
+    if ((st = upload((void**)&g.d_rseed, seed, s)) != SHOT_OK) return st;
+  }
+  return SHOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per-call layout: items grouped by grid, with offsets into the user's arrays
+// and into the plan workspace.
+// ---------------------------------------------------------------------------
+struct Group {
+  int grid;
+  int first;  // index into the sorted item list
+  int count;
+};
+
+struct Layout {
+  std::vector<int> order;          // sorted position -> user item index
+  std::vector<int64_t> user_foff;  // by user item: field offset
+  std::vector<int64_t> user_coff;  // by user item: coefficient offset
+  std::vector<Group> groups;
+  int64_t spec_total = 0;          // complex elements
+  int64_t field_total = 0;         // elements
+  int hs = 0, Lmax = 0;
+};
+
+shot_status make_layout(const shot_plan_s* P, const int32_t* grid_of_item, int nitems, Layout& Lo) {
+  if (nitems <= 0 || !grid_of_item) return SHOT_E_INVALID;
+  const int ng = (int)P->grids.size();
+  Lo.user_foff.assign(nitems, 0);
+  Lo.user_coff.assign(nitems, 0);
+  int64_t fo = 0, co = 0;
+  for (int i = 0; i < nitems; ++i) {
+    const int g = grid_of_item[i];
+    if (g < 0 || g >= ng) return SHOT_E_INVALID;
+    Lo.user_foff[i] = fo;
+    Lo.user_coff[i] = co;
+    fo += P->grids[g].n();
+    const int64_t L = P->grids[g].d.L;
+    co += L * (L + 1) / 2;
+    Lo.hs = std::max(Lo.hs, P->grids[g].h);
+    Lo.Lmax = std::max<int>(Lo.Lmax, (int)L);
+  }
+  Lo.field_total = fo;
+  Lo.order.resize(nitems);
+  std::iota(Lo.order.begin(), Lo.order.end(), 0);
+  std::stable_sort(Lo.order.begin(), Lo.order.end(),
+                   [&](int a, int b) { return grid_of_item[a] < grid_of_item[b]; });
+  Lo.groups.clear();
+  for (int s = 0; s < nitems; ++s) {
+    const int g = grid_of_item[Lo.order[s]];
+    if (Lo.groups.empty() || Lo.groups.back().grid != g) Lo.groups.push_back({g, s, 0});
+    Lo.groups.back().count++;
+    Lo.spec_total += 2LL * P->grids[g].d.L * P->grids[g].h;
+  }
+  return SHOT_OK;
+}
+
+// Workspace carve-out for one call.
+template <typename T>
+struct Work {
+  ItemDev* items = nullptr;
+  cpx<T>* spec = nullptr;
+  T* hl = nullptr;
+  T* ubuf[2] = {nullptr, nullptr};
+  T* vbuf[2] = {nullptr, nullptr};
+  double* red = nullptr;
+  double* rhist = nullptr;
+  double* prep = nullptr;
+  double* res = nullptr;
+  double* ehist = nullptr;
+  int* brk = nullptr;
+  int nslot = 0;
+};
+
+template <typename T>
+shot_status carve(shot_plan_s* P, const Layout& Lo, int nitems, bool sinkhorn, int nslot, Work<T>& W) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  const size_t o_items = take(sizeof(ItemDev) * nitems);
+  const size_t o_spec = take(sizeof(cpx<T>) * Lo.spec_total);
+  const size_t o_hl = take(sizeof(T) * (size_t)nitems * Lo.Lmax);
+  size_t o_u0 = 0, o_u1 = 0, o_v0 = 0, o_v1 = 0, o_red = 0, o_rh = 0, o_prep = 0, o_res = 0, o_eh = 0, o_brk = 0;
+  if (sinkhorn) {
+    o_u0 = take(sizeof(T) * Lo.field_total);
+    o_u1 = take(sizeof(T) * Lo.field_total);
+    o_v0 = take(sizeof(T) * Lo.field_total);
+    o_v1 = take(sizeof(T) * Lo.field_total);
+    o_red = take(sizeof(double) * 2 * (size_t)nitems * Lo.hs * 4);
+    o_rh = take(sizeof(double) * (size_t)nitems * nslot * Lo.hs);
+    o_prep = take(sizeof(double) * (size_t)nitems * Lo.hs * 4);
+    o_res = take(sizeof(double) * (size_t)nitems * 8);
+    o_eh = take(sizeof(double) * (size_t)nitems * nslot);
+    o_brk = take(sizeof(int) * (size_t)nitems);
+  }
+  shot_status st = grow(P->ws, off);
+  if (st != SHOT_OK) return st;
+  char* b = static_cast<char*>(P->ws.p);
+  W.items = reinterpret_cast<ItemDev*>(b + o_items);
+  W.spec = reinterpret_cast<cpx<T>*>(b + o_spec);
+  W.hl = reinterpret_cast<T*>(b + o_hl);
+  if (sinkhorn) {
+    W.ubuf[0] = reinterpret_cast<T*>(b + o_u0);
+    W.ubuf[1] = reinterpret_cast<T*>(b + o_u1);
+    W.vbuf[0] = reinterpret_cast<T*>(b + o_v0);
+    W.vbuf[1] = reinterpret_cast<T*>(b + o_v1);
+    W.red = reinterpret_cast<double*>(b + o_red);
+    W.rhist = reinterpret_cast<double*>(b + o_rh);
+    W.prep = reinterpret_cast<double*>(b + o_prep);
+    W.res = reinterpret_cast<double*>(b + o_res);
+    W.ehist = reinterpret_cast<double*>(b + o_eh);
+    W.brk = reinterpret_cast<int*>(b + o_brk);
+    W.nslot = nslot;
+  }
+  return SHOT_OK;
+}
+
+// Host-side item descriptors and heat multipliers (sorted order).
+template <typename T>
+shot_status upload_items(shot_plan_s* P, const Layout& Lo, const int32_t* grid_of_item,
+                         const std::vector<double>& eps, const std::vector<double>& tau,
+                         const std::vector<double>& tvals, const std::vector<const void*>& pp,
+                         const std::vector<const void*>& qq, Work<T>& W, hipStream_t s) {
+  const int nitems = (int)Lo.order.size();
+  std::vector<ItemDev> items(nitems);
+  std::vector<T> hl((size_t)nitems * Lo.Lmax, (T)0);
+  int64_t soff = 0;
+  for (int si = 0; si < nitems; ++si) {
+    const int ui = Lo.order[si];
+    const GridRec& g = P->grids[grid_of_item[ui]];
+    ItemDev& I = items[si];
+    I.foff = Lo.user_foff[ui];
+    I.soff = soff;
+    I.coff = Lo.user_coff[ui];
+    soff += 2LL * g.d.L * g.h;
+    // kernels index p and q with the item's field offset: pre-subtract it, so
+    // that an item's marginals may live anywhere (the divergence aliases them)
+    I.p = pp.empty() ? nullptr : static_cast<const T*>(pp[ui]) - I.foff;
+    I.q = qq.empty() ? nullptr : static_cast<const T*>(qq[ui]) - I.foff;
+    I.eps = eps.empty() ? 0.0 : eps[ui];
+    I.tau = tau.empty() ? INFINITY : tau[ui];
+    I.balanced = std::isinf(I.tau) ? 1 : 0;
+    I.lam = I.balanced ? 1.0 : I.tau / (I.tau + I.eps);
+    I.eot = I.balanced ? 0.0 : I.eps / I.tau;
+    I.pad = 0;
+    const double t = tvals[ui];
+    for (int l = 0; l < g.d.L; ++l) hl[(size_t)si * Lo.Lmax + l] = (T)std::exp(-t * l * (l + 1.0));
+  }
+  HIP_TRY(hipMemcpyAsync(W.items, items.data(), sizeof(ItemDev) * nitems, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(W.hl, hl.data(), sizeof(T) * hl.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // host staging vectors go out of scope
+  return SHOT_OK;
+}
+
+template <typename T>
+RowArgs<T> row_args(const GridRec& g, const Layout& Lo, const Group& G, const Work<T>& W, int nitems) {
+  RowArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.nlat = g.d.nlat;
+  a.nlon = g.d.nlon;
+  a.L = g.d.L;
+  a.h = g.h;
+  a.hs = Lo.hs;
+  a.nfac = (int)g.fac.size();
+  for (int i = 0; i < a.nfac && i < 8; ++i) a.fac[i] = g.fac[i];
+  a.tw = static_cast<const cpx<T>*>(g.d_tw);
+  a.aw = static_cast<const T*>(g.d_aw);
+  a.item0 = G.first;
+  a.items = W.items;
+  a.spec = W.spec;
+  a.ubuf0 = W.ubuf[0];
+  a.ubuf1 = W.ubuf[1];
+  a.vbuf0 = W.vbuf[0];
+  a.vbuf1 = W.vbuf[1];
+  a.red = W.red;
+  a.nitems_all = nitems;
+  a.rhist = W.rhist;
+  a.nslot = W.nslot;
+  a.chk_slot = -1;
+  a.prep = W.prep;
+  a.brk = W.brk;
+  return a;
+}
+
+template <typename T>
+LegArgs<T> leg_args(const GridRec& g, const Group& G, const Work<T>& W, int hl_stride) {
+  LegArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.L = g.d.L;
+  a.h = g.h;
+  a.hpad = g.hpad;
+  a.tab = g.d_tab;
+  a.xs = g.d_xs;
+  a.rcoef = g.d_rcoef;
+  a.rgam = g.d_rgam;
+  a.rseed = g.d_rseed;
+  a.item0 = G.first;
+  a.nb = G.count;
+  a.items = W.items;
+  a.spec = W.spec;
+  a.hl = W.hl;
+  a.hl_stride = hl_stride;
+  a.mode = 0;
+  return a;
+}
+
+// Items per Legendre workgroup: as many as requested/available, capped so the
+// LDS staging (inputs IB*2h + coefficients IB*L complex) stays within 64 KiB.
+int pick_ib(const shot_plan_s* P, const GridRec& g, int count) {
+  int ib = P->leg_ib > 0 ? P->leg_ib : 8;
+  if (g.tab_kind == TAB_RECUR) ib = std::min(ib, 4);
+  while (ib > 1 && ib > count) ib >>= 1;
+  const size_t cs = P->prec == SHOT_FP64 ? 16 : 8;
+  while (ib > 1 && (size_t)ib * (2 * g.h + g.d.L) * cs > 60 * 1024) ib >>= 1;
+  return ib;
+}
+
+template <typename T>
+shot_status run_rows(shot_plan_s* P, const RowArgs<T>& a, int nb, hipStream_t s) {
+  ProfScope ps(P, s, 1);
+  hipError_t e = launch_rows<T>(a, nb, s);
+  return e == hipSuccess ? SHOT_OK : hip_fail(e, "row kernel launch", __LINE__);
+}
+
+template <typename T>
+shot_status run_leg(shot_plan_s* P, const GridRec& g, LegArgs<T> a, hipStream_t s) {
+  ProfScope ps(P, s, 0);
+  const int ib = pick_ib(P, g, a.nb);
+  hipError_t e = launch_legendre<T>(a, g.tab_kind, ib, s);
+  return e == hipSuccess ? SHOT_OK : hip_fail(e, "Legendre kernel launch", __LINE__);
+}
+
+#define ST_TRY(expr)                     \
+  do {                                   \
+    shot_status s_ = (expr);             \
+    if (s_ != SHOT_OK) return s_;        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Heat apply / analysis / synthesis
+// ---------------------------------------------------------------------------
+template <typename T>
+shot_status heat_apply_impl(shot_plan_s* P, const int32_t* goi, int nitems, const double* t,
+                            const void* v, void* out, int transpose, hipStream_t s) {
+  Layout Lo;
+  ST_TRY(make_layout(P, goi, nitems, Lo));
+  Work<T> W;
+  ST_TRY(carve<T>(P, Lo, nitems, false, 0, W));
+  std::vector<double> tv(t, t + nitems);
+  ST_TRY(upload_items<T>(P, Lo, goi, {}, {}, tv, {}, {}, W, s));
+  for (const Group& G : Lo.groups) {
+    const GridRec& g = P->grids[G.grid];
+    RowArgs<T> a = row_args<T>(g, Lo, G, W, nitems);
+    a.mode = ROW_FWD;
+    a.in = static_cast<const T*>(v);
+    a.wts_in = transpose ? 0 : 1;
+    ST_TRY(run_rows<T>(P, a, G.count, s));
+    ST_TRY(run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), s));
+    a.mode = ROW_INV;
+    a.out = static_cast<T*>(out);
+    a.wts_out = transpose ? 1 : 0;
+    ST_TRY(run_rows<T>(P, a, G.count, s));
+  }
+  return SHOT_OK;
+}
+
+template <typename T>
+shot_status sht_impl(shot_plan_s* P, const int32_t* goi, int nitems, const void* in, void* out,
+                     bool analysis, hipStream_t s) {
+  Layout Lo;
+  ST_TRY(make_layout(P, goi, nitems, Lo));
+  Work<T> W;
+  ST_TRY(carve<T>(P, Lo, nitems, false, 0, W));
+  std::vector<double> tv(nitems, 0.0);
+  ST_TRY(upload_items<T>(P, Lo, goi, {}, {}, tv, {}, {}, W, s));
+  for (const Group& G : Lo.groups) {
+    const GridRec& g = P->grids[G.grid];
+    RowArgs<T> a = row_args<T>(g, Lo, G, W, nitems);
+    LegArgs<T> la = leg_args<T>(g, G, W, Lo.Lmax);
+    if (analysis) {
+      a.mode = ROW_FWD;
+      a.in = static_cast<const T*>(in);
+      a.wts_in = 1;
+      ST_TRY(run_rows<T>(P, a, G.count, s));
+      la.mode = 1;
+      la.coeff = static_cast<cpx<T>*>(out);
+      ST_TRY(run_leg<T>(P, g, la, s));
+    } else {
+      la.mode = 2;
+      la.coeff = static_cast<cpx<T>*>(const_cast<void*>(in));
+      ST_TRY(run_leg<T>(P, g, la, s));
+      a.mode = ROW_INV;
+      a.out = static_cast<T*>(out);
+      ST_TRY(run_rows<T>(P, a, G.count, s));
+    }
+  }
+  return SHOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Sinkhorn solve on items described by per-item (p, q) device pointers.
+// ---------------------------------------------------------------------------
+struct SolveSpec {
+  std::vector<int32_t> grid;       // per item
+  std::vector<shot_params> prm;    // per item
+  std::vector<const void*> p, q;   // per item device pointers
+};
+
+shot_status check_params(const shot_params& pr) {
+  if (!(pr.eps > 0) || !std::isfinite(pr.eps)) return SHOT_E_INVALID;
+  if (!(pr.tau > 0)) return SHOT_E_INVALID;
+  if (pr.max_iter < 1 || pr.check_every < 1 || !(pr.tol >= 0)) return SHOT_E_INVALID;
+  return SHOT_OK;
+}
+
+template <typename T>
+shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_solve_info* info,
+                       double* mass_out, hipStream_t s) {
+  const int nitems = (int)S.grid.size();
+  Layout Lo;
+  ST_TRY(make_layout(P, S.grid.data(), nitems, Lo));
+  int T_iter = 0, C = S.prm[0].check_every;
+  double tol = S.prm[0].tol;
+  for (int i = 0; i < nitems; ++i) {
+    ST_TRY(check_params(S.prm[i]));
+    T_iter = std::max(T_iter, S.prm[i].max_iter);
+    if (S.prm[i].check_every != C || S.prm[i].tol != tol || S.prm[i].max_iter != S.prm[0].max_iter)
+      return SHOT_E_UNSUPPORTED;  // one call advances all items in lock step
+  }
+  const int nchk = T_iter / C;
+  const int nslot = nchk + 1;  // + final residual
+  Work<T> W;
+  ST_TRY(carve<T>(P, Lo, nitems, true, nslot, W));
+  std::vector<double> eps(nitems), tau(nitems), tv(nitems);
+  for (int i = 0; i < nitems; ++i) {
+    eps[i] = S.prm[i].eps;
+    tau[i] = S.prm[i].tau;
+    tv[i] = S.prm[i].eps / 4.0;  // t = eps/4 (Alg. 1)
+  }
+  ST_TRY(upload_items<T>(P, Lo, S.grid.data(), eps, tau, tv, S.p, S.q, W, s));
+  {
+    std::vector<int> brk0(nitems, INT_MAX);
+    HIP_TRY(hipMemcpyAsync(W.brk, brk0.data(), sizeof(int) * nitems, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+
+  auto each_group = [&](auto&& fn) -> shot_status {
+    for (const Group& G : Lo.groups) {
+      shot_status st = fn(G, P->grids[G.grid]);
+      if (st != SHOT_OK) return st;
+    }
+    return SHOT_OK;
+  };
+  auto rows = [&](const Group& G, const GridRec& g, int mode, int k, int chk) {
+    RowArgs<T> a = row_args<T>(g, Lo, G, W, nitems);
+    a.mode = mode;
+    a.k = k;
+    a.chk_slot = chk;
+    a.out = phi;
+    a.out2 = psi;
+    return run_rows<T>(P, a, G.count, s);
+  };
+  auto leg = [&](const Group& G, const GridRec& g) { return run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), s); };
+
+  // v_0 = 1: spectrum of the constant field, plus norms and masses
+  ST_TRY(each_group([&](const Group& G, const GridRec& g) { return rows(G, g, ROW_INIT, 0, -1); }));
+  int K = T_iter;
+  int final_slot = nslot - 1;
+  bool early = false;
+  for (int k = 1; k <= T_iter; ++k) {
+    const bool chk_prev = (k - 1 >= 1) && ((k - 1) % C == 0);
+    const int slot = chk_prev ? (k - 1) / C - 1 : -1;
+    ST_TRY(each_group([&](const Group& G, const GridRec& g) {
+      shot_status st = leg(G, g);
+      return st != SHOT_OK ? st : rows(G, g, ROW_SINK_U, k, slot);
+    }));
+    if (tol > 0 && chk_prev) {
+      // e_marg of iteration k-1 is complete: decide before the v-half
+      for (const Group& G : Lo.groups) {
+        RowArgs<T> a = row_args<T>(P->grids[G.grid], Lo, G, W, nitems);
+        HIP_TRY(launch_reduce<T>(a, G.count, slot + 1, W.res, W.ehist, s));
+      }
+      std::vector<double> eh((size_t)nitems * nslot);
+      HIP_TRY(hipMemcpyAsync(eh.data(), W.ehist, sizeof(double) * eh.size(), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      bool all = true;
+      for (int si = 0; si < nitems; ++si) all &= (eh[(size_t)si * nslot + slot] < tol);
+      if (all) {
+        K = k - 1;
+        final_slot = slot;
+        early = true;
+        break;
+      }
+    }
+    ST_TRY(each_group([&](const Group& G, const GridRec& g) {
+      shot_status st = leg(G, g);
+      return st != SHOT_OK ? st : rows(G, g, ROW_SINK_V, k, -1);
+    }));
+  }
+  if (!early) {
+    // e_marg of the returned scalings needs K v_hat_K (one more heat apply);
+    // when K is itself a check iteration its history slot is that residual
+    if (K % C == 0) final_slot = K / C - 1;
+    ST_TRY(each_group([&](const Group& G, const GridRec& g) {
+      shot_status st = leg(G, g);
+      return st != SHOT_OK ? st : rows(G, g, ROW_CHECK, K + 1, final_slot);
+    }));
+  }
+  ST_TRY(each_group([&](const Group& G, const GridRec& g) { return rows(G, g, ROW_FINAL, K, -1); }));
+  const int nchk_done = K / C;
+  for (const Group& G : Lo.groups) {
+    RowArgs<T> a = row_args<T>(P->grids[G.grid], Lo, G, W, nitems);
+    a.chk_slot = final_slot;
+    HIP_TRY(launch_reduce<T>(a, G.count, nchk_done, W.res, W.ehist, s));
+  }
+  std::vector<double> res((size_t)nitems * 8);
+  std::vector<int> brk(nitems);
+  HIP_TRY(hipMemcpyAsync(res.data(), W.res, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(brk.data(), W.brk, sizeof(int) * nitems, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int si = 0; si < nitems; ++si) {
+    const int ui = Lo.order[si];
+    shot_solve_info& I = info[ui];
+    I.cost = res[(size_t)si * 8 + 0];
+    I.err = res[(size_t)si * 8 + 1];
+    I.iters = K;
+    I.breakdown_iter = brk[si] == INT_MAX ? 0 : brk[si];
+    if (mass_out) {
+      mass_out[2 * ui] = res[(size_t)si * 8 + 2];
+      mass_out[2 * ui + 1] = res[(size_t)si * 8 + 3];
+    }
+    I.reserved = 0;
+    if (I.breakdown_iter) I.status = SHOT_E_BREAKDOWN;
+    else if (tol > 0 && !(I.err < tol)) I.status = SHOT_W_NOT_CONVERGED;
+    else I.status = SHOT_OK;
+  }
+  return SHOT_OK;
+}
+
+shot_status worst(const shot_solve_info* info, int n) {
+  int w = SHOT_OK;
+  for (int i = 0; i < n; ++i) w = std::max(w, info[i].status);
+  return (shot_status)w;
+}
+
+bool ptr_ok(const void* p) { return p != nullptr; }
+
+// Def. 2.3: S = R(p,q) - (R(p,p) + R(q,q))/2 + eps/2 (m(p) - m(q))^2, float64.
+// inf holds the three solves of pair i at 3i, 3i+1, 3i+2; mass holds
+// (m(first marginal), m(second marginal)) per solve.
+void combine_divergence(const shot_params* prm, int npairs, const shot_solve_info* inf,
+                        const double* mass, double* S) {
+  for (int i = 0; i < npairs; ++i) {
+    const double mp = mass[2 * (3 * i)], mq = mass[2 * (3 * i) + 1];
+    const double dm = mp - mq;
+    S[i] = inf[3 * i].cost - 0.5 * (inf[3 * i + 1].cost + inf[3 * i + 2].cost) + 0.5 * prm[i].eps * dm * dm;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* shot_last_error(void) { return g_last_error; }
+
+const char* shot_status_string(int32_t s) {
+  switch (s) {
+    case SHOT_OK: return "ok";
+    case SHOT_E_INVALID: return "invalid argument";
+    case SHOT_E_NOMEM: return "out of device memory";
+    case SHOT_E_HIP: return "HIP runtime error";
+    case SHOT_E_UNSUPPORTED: return "unsupported configuration";
+    case SHOT_W_NOT_CONVERGED: return "not converged (e_marg >= tol)";
+    case SHOT_E_BREAKDOWN: return "breakdown: heat-kernel output <= 0 or non-finite";
+    default: return "unknown status";
+  }
+}
+
+shot_status shot_sht_plan(shot_plan_t* out, const shot_grid_desc* grids, int32_t ngrids,
+                          int32_t precision, int32_t legendre_mode, void* stream) {
+  if (!out) return SHOT_E_INVALID;
+  *out = nullptr;
+  if (!grids || ngrids <= 0) return SHOT_E_INVALID;
+  if (precision < SHOT_FP64 || precision > SHOT_BF16_MFMA) return SHOT_E_INVALID;
+  if (legendre_mode < SHOT_LEG_AUTO || legendre_mode > SHOT_LEG_RECURRENCE) return SHOT_E_INVALID;
+  for (int i = 0; i < ngrids; ++i) {
+    const shot_grid_desc& d = grids[i];
+    if (d.kind != SHOT_GRID_GAUSS_LEGENDRE && d.kind != SHOT_GRID_CLENSHAW_CURTIS) return SHOT_E_INVALID;
+    if (d.nlat < 2 || d.L < 1 || d.nlon < 2 * d.L - 1) return SHOT_E_INVALID;
+    if (fft_radices(d.nlon).empty() || d.nlon > 2048) return SHOT_E_UNSUPPORTED;
+    if (fft_radices(d.nlon).size() > 8) return SHOT_E_UNSUPPORTED;
+    // one order's inputs and coefficients must fit the Legendre kernel's LDS
+    const size_t cs = precision == SHOT_FP64 ? 16 : 8;
+    if ((size_t)(2 * ((d.nlat + 1) / 2) + d.L) * cs > 60 * 1024) return SHOT_E_UNSUPPORTED;
+    if (legendre_mode == SHOT_LEG_RECURRENCE && (d.nlat + 1) / 2 > 1024) return SHOT_E_UNSUPPORTED;
+  }
+  shot_plan_s* P = new (std::nothrow) shot_plan_s();
+  if (!P) return SHOT_E_NOMEM;
+  P->prec = precision;
+  {
+    hipError_t e = hipGetDevice(&P->dev);
+    if (e != hipSuccess) { delete P; return hip_fail(e, "hipGetDevice", __LINE__); }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  P->grids.resize(ngrids);
+  for (int i = 0; i < ngrids; ++i) {
+    P->grids[i].d = grids[i];
+    shot_status st = build_grid(P, P->grids[i], legendre_mode, s);
+    if (st != SHOT_OK) {
+      shot_plan_destroy(P);
+      return st;
+    }
+  }
+  *out = P;
+  return SHOT_OK;
+}
+
+shot_status shot_plan_destroy(shot_plan_t P) {
+  if (!P) return SHOT_OK;
+  (void)hipDeviceSynchronize();
+  for (auto& g : P->grids) free_grid(g);
+  if (P->ws.p) (void)hipFree(P->ws.p);
+  for (auto e : P->evpool) (void)hipEventDestroy(e);
+  delete P;
+  return SHOT_OK;
+}
+
+shot_status shot_plan_grid(shot_plan_t P, int32_t grid, double* x_out, double* w_out) {
+  if (!P || grid < 0 || grid >= (int)P->grids.size()) return SHOT_E_INVALID;
+  const GridRec& g = P->grids[grid];
+  if (x_out) std::copy(g.x.begin(), g.x.end(), x_out);
+  if (w_out) std::copy(g.w.begin(), g.w.end(), w_out);
+  return SHOT_OK;
+}
+
+shot_status shot_sht_analysis(shot_plan_t P, const int32_t* goi, int32_t nitems, const void* f,
+                              void* coeffs, void* stream) {
+  if (!P || !ptr_ok(f) || !ptr_ok(coeffs)) return SHOT_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(P->dev));
+  return P->prec == SHOT_FP64 ? sht_impl<double>(P, goi, nitems, f, coeffs, true, s)
+                              : sht_impl<float>(P, goi, nitems, f, coeffs, true, s);
+}
+
+shot_status shot_sht_synthesis(shot_plan_t P, const int32_t* goi, int32_t nitems, const void* coeffs,
+                               void* f, void* stream) {
+  if (!P || !ptr_ok(f) || !ptr_ok(coeffs)) return SHOT_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(P->dev));
+  return P->prec == SHOT_FP64 ? sht_impl<double>(P, goi, nitems, coeffs, f, false, s)
+                              : sht_impl<float>(P, goi, nitems, coeffs, f, false, s);
+}
+
+shot_status shot_heat_apply(shot_plan_t P, const int32_t* goi, int32_t nitems, const double* t,
+                            const void* v, void* out, int32_t transpose, void* stream) {
+  if (!P || !t || !ptr_ok(v) || !ptr_ok(out) || v == out) return SHOT_E_INVALID;
+  for (int i = 0; i < nitems; ++i)
+    if (!(t[i] >= 0) || !std::isfinite(t[i])) return SHOT_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(P->dev));
+  return P->prec == SHOT_FP64 ? heat_apply_impl<double>(P, goi, nitems, t, v, out, transpose, s)
+                              : heat_apply_impl<float>(P, goi, nitems, t, v, out, transpose, s);
+}
+
+shot_status shot_sinkhorn_solve(shot_plan_t P, const int32_t* goi, int32_t nitems,
+                                const shot_params* params, const void* p, const void* q, void* phi,
+                                void* psi, shot_solve_info* info, void* stream) {
+  if (!P || !goi || nitems <= 0 || !params || !ptr_ok(p) || !ptr_ok(q) || !info) return SHOT_E_INVALID;
+  Layout Lo;
+  shot_status st = make_layout(P, goi, nitems, Lo);
+  if (st != SHOT_OK) return st;
+  SolveSpec S;
+  S.grid.assign(goi, goi + nitems);
+  S.prm.assign(params, params + nitems);
+  const size_t es = field_elem(P);
+  for (int i = 0; i < nitems; ++i) {
+    S.p.push_back(static_cast<const char*>(p) + Lo.user_foff[i] * es);
+    S.q.push_back(static_cast<const char*>(q) + Lo.user_foff[i] * es);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(P->dev));
+  st = P->prec == SHOT_FP64
+           ? solve_impl<double>(P, S, static_cast<double*>(phi), static_cast<double*>(psi), info, nullptr, s)
+           : solve_impl<float>(P, S, static_cast<float*>(phi), static_cast<float*>(psi), info, nullptr, s);
+  if (st != SHOT_OK) return st;
+  return worst(info, nitems);
+}
+
+shot_status shot_sinkhorn_divergence(shot_plan_t P, const int32_t* gop, int32_t npairs,
+                                     const shot_params* params, const void* p, const void* q,
+                                     double* S_out, shot_solve_info* info, void* stream) {
+  if (!P || !gop || npairs <= 0 || !params || !ptr_ok(p) || !ptr_ok(q) || !S_out) return SHOT_E_INVALID;
+  Layout Lo;
+  shot_status st = make_layout(P, gop, npairs, Lo);
+  if (st != SHOT_OK) return st;
+  SolveSpec S;
+  const size_t es = field_elem(P);
+  for (int i = 0; i < npairs; ++i) {
+    const void* pi = static_cast<const char*>(p) + Lo.user_foff[i] * es;
+    const void* qi = static_cast<const char*>(q) + Lo.user_foff[i] * es;
+    const void* ps[3] = {pi, pi, qi};
+    const void* qs[3] = {qi, pi, qi};
+    for (int r = 0; r < 3; ++r) {
+      S.grid.push_back(gop[i]);
+      S.prm.push_back(params[i]);
+      S.p.push_back(ps[r]);
+      S.q.push_back(qs[r]);
+    }
+  }
+  std::vector<shot_solve_info> inf(3 * (size_t)npairs);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(P->dev));
+  std::vector<double> mass(6 * (size_t)npairs);
+  st = P->prec == SHOT_FP64 ? solve_impl<double>(P, S, nullptr, nullptr, inf.data(), mass.data(), s)
+                            : solve_impl<float>(P, S, nullptr, nullptr, inf.data(), mass.data(), s);
+  if (st != SHOT_OK) return st;
+  combine_divergence(params, npairs, inf.data(), mass.data(), S_out);
+  if (info) std::copy(inf.begin(), inf.end(), info);
+  return worst(inf.data(), 3 * npairs);
+}
+
+shot_status shot_sinkhorn_divergence_grad(shot_plan_t P, const int32_t* gop, int32_t npairs,
+                                          const shot_params* params, const void* p, const void* q,
+                                          double* S_out, void* dS_dp, int32_t mode,
+                                          int32_t checkpoint_every, shot_solve_info* info,
+                                          void* stream) {
+  (void)P; (void)gop; (void)npairs; (void)params; (void)p; (void)q; (void)S_out; (void)dS_dp;
+  (void)mode; (void)checkpoint_every; (void)info; (void)stream;
+  return SHOT_E_UNSUPPORTED;
+}
+
+shot_status shot_profile_enable(shot_plan_t P, int32_t enable) {
+  if (!P) return SHOT_E_INVALID;
+  if (enable) {
+    P->timed.clear();
+    P->evnext = 0;
+  }
+  P->prof = enable != 0;
+  return SHOT_OK;
+}
+
+shot_status shot_profile_read(shot_plan_t P, int32_t cls, int64_t* launches, double* total_ms) {
+  if (!P || !launches || !total_ms) return SHOT_E_INVALID;
+  int64_t n = 0;
+  double ms = 0.0;
+  for (const Timed& t : P->timed) {
+    if (t.cls != cls) continue;
+    HIP_TRY(hipEventSynchronize(t.b));
+    float e = 0.f;
+    HIP_TRY(hipEventElapsedTime(&e, t.a, t.b));
+    ms += e;
+    ++n;
+  }
+  *launches = n;
+  *total_ms = ms;
+  return SHOT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Host-side float64 math for libshot plans (see host_math.h).
+#include "host_math.h"
+
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+namespace shot {
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  // Newton's method on P_n, P_n evaluated by Bonnet's recurrence; the start
+  // values cos(pi (i + 3/4)/(n + 1/2)) are already ordered north to south.
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double pn = 0, dpn = 1;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      pn = (n == 0) ? 1.0 : p1;
+      dpn = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = pn / dpn;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 1; k < n; ++k) {
+      double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+      p0 = p1;
+      p1 = p2;
+    }
+    dpn = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dpn * dpn);
+  }
+  // enforce the exact equatorial symmetry the folded kernels rely on
+  for (int i = 0; i < n / 2; ++i) {
+    double xs = 0.5 * (x[i] - x[n - 1 - i]);
+    double ws = 0.5 * (w[i] + w[n - 1 - i]);
+    x[i] = xs;
+    x[n - 1 - i] = -xs;
+    w[i] = w[n - 1 - i] = ws;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+void clenshaw_curtis(int n, std::vector<double>& x, std::vector<double>& w) {
+  // w_j = c_j/N (1 - sum_{k=1}^{N/2} b_k cos(2 k theta_j)/(4k^2 - 1)), N = n-1,
+  // c_j = 1 at the poles and 2 elsewhere, b_k = 1 for k = N/2 and 2 otherwise.
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const int N = n - 1;
+  for (int j = 0; j < n; ++j) {
+    const double th = M_PI * j / N;
+    double s = 0.0;
+    for (int k = 1; 2 * k <= N; ++k) {
+      const double b = (2 * k == N) ? 1.0 : 2.0;
+      s += b * std::cos(2.0 * k * th) / (4.0 * k * k - 1.0);
+    }
+    w[j] = ((j == 0 || j == N) ? 1.0 : 2.0) / N * (1.0 - s);
+    x[j] = std::cos(th);
+  }
+  for (int i = 0; i < n / 2; ++i) {
+    double xs = 0.5 * (x[i] - x[n - 1 - i]);
+    double ws = 0.5 * (w[i] + w[n - 1 - i]);
+    x[i] = xs;
+    x[n - 1 - i] = -xs;
+    w[i] = w[n - 1 - i] = ws;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+std::vector<int> fft_radices(int n) {
+  std::vector<int> f;
+  for (int r : {4, 2, 3, 5}) {
+    while (n % r == 0) {
+      f.push_back(r);
+      n /= r;
+    }
+  }
+  if (n != 1) f.clear();
+  return f;
+}
+
+namespace {
+
+// One order m: P̄_l^m(x) for l = m..L-1 at a single node, into out[l-m].
+void legendre_column(int L, int m, double x, double* out, int64_t stride) {
+  const double s = std::sqrt(std::max(0.0, 1.0 - x * x));
+  double pmm = 1.0 / std::sqrt(4.0 * M_PI);
+  for (int k = 1; k <= m; ++k) pmm *= std::sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
+  out[0] = pmm;
+  if (L - m < 2) return;
+  double p1 = std::sqrt(2.0 * m + 3.0) * x * pmm;
+  out[stride] = p1;
+  double p2 = pmm;
+  for (int l = m + 2; l < L; ++l) {
+    const double a = std::sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
+    const double b = std::sqrt(((l - 1.0) * (l - 1.0) - (double)m * m) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
+    const double p = a * (x * p1 - b * p2);
+    out[(int64_t)(l - m) * stride] = p;
+    p2 = p1;
+    p1 = p;
+  }
+}
+
+}  // namespace
+
+void legendre_rows(int L, const std::vector<double>& x, int ld, std::vector<double>& tab,
+                   int nthreads) {
+  const int nx = (int)x.size();
+  const int64_t rows = (int64_t)L * (L + 1) / 2;
+  tab.assign(rows * ld, 0.0);
+  nthreads = std::max(1, nthreads);
+  std::vector<std::thread> pool;
+  for (int tid = 0; tid < nthreads; ++tid) {
+    pool.emplace_back([&, tid]() {
+      for (int m = tid; m < L; m += nthreads) {
+        double* base = tab.data() + tri_offset(m, L) * ld;
+        for (int j = 0; j < nx; ++j) legendre_column(L, m, x[j], base + j, ld);
+      }
+    });
+  }
+  for (auto& t : pool) t.join();
+}
+
+void legendre_recurrence_data(int L, const std::vector<double>& x, std::vector<double>& coef,
+                              std::vector<double>& gam, std::vector<double>& seed) {
+  const int nx = (int)x.size();
+  const int64_t rows = (int64_t)L * (L + 1) / 2;
+  coef.assign(rows, 0.0);
+  gam.assign(rows, 1.0);
+  seed.assign((int64_t)L * nx, 0.0);
+  for (int m = 0; m < L; ++m) {
+    const int64_t o = tri_offset(m, L);
+    // gamma and the x-coefficient of the rescaled recurrence
+    for (int l = m; l < L; ++l) {
+      if (l == m) {
+        gam[o] = 1.0;
+        coef[o] = 0.0;
+      } else if (l == m + 1) {
+        gam[o + 1] = 1.0;
+        coef[o + 1] = std::sqrt(2.0 * m + 3.0);
+      } else {
+        const double alpha = std::sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
+        const double beta = -std::sqrt((2.0 * l + 1.0) * ((l - 1.0) * (l - 1.0) - (double)m * m) /
+                                       ((2.0 * l - 3.0) * ((double)l * l - (double)m * m)));
+        gam[o + (l - m)] = beta * gam[o + (l - m) - 2];
+        coef[o + (l - m)] = alpha * gam[o + (l - m) - 1] / gam[o + (l - m)];
+      }
+    }
+    for (int j = 0; j < nx; ++j) {
+      const double s = std::sqrt(std::max(0.0, 1.0 - x[j] * x[j]));
+      double pmm = 1.0 / std::sqrt(4.0 * M_PI);
+      for (int k = 1; k <= m; ++k) pmm *= std::sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
+      seed[(int64_t)m * nx + j] = pmm;
+    }
+  }
+}
+
+}  // namespace shot

@@ -1,0 +1,43 @@
+// Host-side float64 math for libshot plans: latitude quadrature, FFT
+// factorisation and twiddles, heat multipliers, Legendre table and recurrence
+// data.  Pure C++ (no HIP); everything here runs once per plan.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace shot {
+
+// Gauss-Legendre nodes (descending, row 0 north) and weights (sum 2):
+// the rows of a Gauss-Legendre grid sit at the roots of P_nlat (App. C.1).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+// Clenshaw-Curtis rule on theta_j = j pi/(n-1), poles included (App. C.1).
+void clenshaw_curtis(int n, std::vector<double>& x, std::vector<double>& w);
+
+// Radices (4, 2, 3, 5 in that order of extraction) whose product is n, or
+// empty when n has another prime factor.
+std::vector<int> fft_radices(int n);
+
+// Offset of order m in the packed triangular (m, l) layout, l = m..L-1.
+inline int64_t tri_offset(int64_t m, int64_t L) { return m * L - m * (m - 1) / 2; }
+
+// Orthonormal associated Legendre values P̄_l^m(x_j) (App. B normalisation
+// N_lm, no Condon-Shortley phase) for every m < L, l = m..L-1 and the given
+// nodes, written row (tri_offset(m)+l-m) x column j into `tab` with row
+// stride `ld`.  Computed per (m, x) by the normalised three-term recurrence in
+// l, in float64, on `nthreads` host threads.
+void legendre_rows(int L, const std::vector<double>& x, int ld, std::vector<double>& tab,
+                   int nthreads);
+
+// Data for generating P̄_l^m on the device with a two-operation recurrence.
+// With P̄_l^m = alpha_l x P̄_{l-1}^m + beta_l P̄_{l-2}^m, define
+// gamma_m = gamma_{m+1} = 1, gamma_l = beta_l gamma_{l-2}, R_l = P̄_l^m / gamma_l.
+// Then R_l = (alpha_l gamma_{l-1}/gamma_l) x R_{l-1} + R_{l-2}.
+// coef[tri(m,l)] = alpha_l gamma_{l-1}/gamma_l (l >= m+2; for l = m+1 it is the
+// ratio P̄_{m+1}^m / (x P̄_m^m) = sqrt(2m+3)), gam[tri(m,l)] = gamma_l.
+// seed[m*nx + j] = P̄_m^m(x_j) (may underflow to 0 where it is negligible).
+void legendre_recurrence_data(int L, const std::vector<double>& x, std::vector<double>& coef,
+                              std::vector<double>& gam, std::vector<double>& seed);
+
+}  // namespace shot

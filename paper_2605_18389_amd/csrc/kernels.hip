@@ -1,0 +1,834 @@
+// HIP kernels of libshot for gfx950 (MI355X).
+//
+// The heat apply K v = F^{-1}(h (.) F v) (Sec. 3.2) is split at its two global
+// dependency points into
+//   * row kernels: one workgroup per pair of mirror latitude rows (j, nlat-1-j).
+//     The two real rows ride in one complex FFT (real part row j, imaginary part
+//     row j'), done in LDS by a mixed-radix Stockham FFT; the result is folded
+//     into the equatorially even/odd combinations E_m = F_m(j) + F_m(j') and
+//     O_m = F_m(j) - F_m(j') that the folded Legendre stage consumes.  The
+//     Sinkhorn pointwise update of Alg. 1 is fused between the inverse FFT of
+//     one heat apply and the forward FFT of the next one, so a field never
+//     makes an extra trip through HBM.
+//   * Legendre kernels: one workgroup per order m (and chunk of items):
+//     analysis f_lm = sum_j a_j P̄_l^m(x_j) {E|O}_m(j), multiply by h_l, and
+//     synthesis G_m(j) = sum_l b_lm P̄_l^m(x_j), all for the same m, so the
+//     spectral coefficients never leave the workgroup.  P̄_l^m comes from a
+//     table streamed from HBM or from the float64 three-term recurrence.
+// Folding uses P̄_l^m(-x) = (-1)^{l+m} P̄_l^m(x): only rows j <= nlat/2 are
+// touched by the Legendre stage.
+//
+// Spectral workspace layout per item: [m][parity][j] complex, m < L,
+// parity 0 = E (even l-m), 1 = O (odd l-m), j < h = ceil(nlat/2).
+// Reductions are per-workgroup float64 partial sums written to fixed slots and
+// summed later in a fixed order, so results are deterministic (no float atomics).
+
+#include <climits>
+
+#include "shot_internal.h"
+
+namespace shot {
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by s*i (s = +-1)
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul_si(cpx<T> a, T s) { return {-s * a.y, s * a.x}; }
+
+// ---------------------------------------------------------------------------
+// Mixed-radix Stockham FFT in LDS, radices 2, 3, 4, 5.  sign = -1 forward,
+// +1 inverse (unnormalised).  All threads of the block must call it.  Returns
+// the buffer that holds the result (natural order).
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__device__ __forceinline__ void butterfly(cpx<T>* v, T s) {
+  if constexpr (R == 2) {
+    cpx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    cpx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    cpx<T> t2 = cadd(v[1], v[3]), t3 = cmul_si(csub(v[1], v[3]), s);
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  } else if constexpr (R == 3) {
+    const T c = (T)-0.5, sn = s * (T)0.86602540378443864676;
+    cpx<T> t = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    cpx<T> base = {v[0].x + c * t.x, v[0].y + c * t.y};
+    cpx<T> rot = cmul_si(d, sn);  // i * sn * d
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(base, rot);
+    v[2] = csub(base, rot);
+  } else if constexpr (R == 5) {
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = s * (T)0.95105651629515357212, s2 = s * (T)0.58778525229247312917;
+    cpx<T> t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+    cpx<T> t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+    cpx<T> b1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+    cpx<T> b2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+    cpx<T> e1 = {s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y};
+    cpx<T> e2 = {s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y};
+    cpx<T> r1 = cmul_si(e1, (T)1), r2 = cmul_si(e2, (T)1);
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(b1, r1);
+    v[4] = csub(b1, r1);
+    v[2] = cadd(b2, r2);
+    v[3] = csub(b2, r2);
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                               int N, int Ns, const cpx<T>* __restrict__ tw, T sign) {
+  const int NR = N / R;
+  const int twstride = N / (Ns * R);
+  for (int b = threadIdx.x; b < NR; b += blockDim.x) {
+    const int k = b % Ns;
+    cpx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[b + r * NR];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      cpx<T> w = tw[r * k * twstride];
+      w.y *= -sign;  // table holds exp(-2 pi i k/N); inverse uses the conjugate
+      v[r] = cmul(v[r], w);
+    }
+    butterfly<T, R>(v, sign);
+    const int base = (b / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  }
+}
+
+template <typename T>
+__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int N, const int* fac, int nfac,
+                           const cpx<T>* __restrict__ tw, T sign) {
+  int Ns = 1;
+  cpx<T>* src = a;
+  cpx<T>* dst = b;
+  for (int s = 0; s < nfac; ++s) {
+    const int R = fac[s];
+    switch (R) {
+      case 2: stockham_stage<T, 2>(src, dst, N, Ns, tw, sign); break;
+      case 3: stockham_stage<T, 3>(src, dst, N, Ns, tw, sign); break;
+      case 4: stockham_stage<T, 4>(src, dst, N, Ns, tw, sign); break;
+      default: stockham_stage<T, 5>(src, dst, N, Ns, tw, sign); break;
+    }
+    __syncthreads();
+    cpx<T>* t = src;
+    src = dst;
+    dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reduction: every thread receives the same value (the
+// wave partials are combined in wave order by each thread).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += sh[i];
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ bool bad_kernel_value(T x) {
+  return !(x > (T)0) || !isfinite(x);
+}
+
+template <typename T>
+__device__ __forceinline__ T* ubuf_of(const RowArgs<T>& A, int k) { return (k & 1) ? A.ubuf1 : A.ubuf0; }
+template <typename T>
+__device__ __forceinline__ T* vbuf_of(const RowArgs<T>& A, int k) { return (k & 1) ? A.vbuf1 : A.vbuf0; }
+
+// Gauge g_k: after iteration k the Alg. 1 scalings are u_k = u_hat/g_k and
+// v_k = g_k v_hat, with g_k = s = sum u_hat (balanced) or exp(-c/eps) with
+// c = tau/2 (log sum a p u_hat^(-eps/tau) - log sum a q v_hat^(-eps/tau)).
+template <typename T>
+__device__ double gauge(const RowArgs<T>& A, const ItemDev& I, int it, int k, double* sh) {
+  const double* R = A.red + ((size_t)(k & 1) * A.nitems_all + it) * (size_t)A.hs * 4;
+  double s0 = 0.0, s1 = 0.0;
+  for (int q = threadIdx.x; q < A.h; q += blockDim.x) {
+    s0 += R[(size_t)q * 4 + 0];
+    s1 += R[(size_t)q * 4 + 1];
+  }
+  s0 = block_sum(s0, sh);
+  s1 = block_sum(s1, sh);
+  if (I.balanced) return s0;
+  const double c = 0.5 * I.tau * (log(s0) - log(s1));
+  return exp(-c / I.eps);
+}
+
+// ---------------------------------------------------------------------------
+// Row kernel.  grid = (h row pairs, items), block = 256.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* buf0 = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* buf1 = buf0 + A.nlon;
+  __shared__ double sh[16];
+  __shared__ int sh_bad;
+
+  const int jp = blockIdx.x;
+  const int it = A.item0 + blockIdx.y;
+  const ItemDev I = A.items[it];
+  const int N = A.nlon, L = A.L, h = A.h;
+  const int j1 = jp, j2 = A.nlat - 1 - jp;
+  const bool eq = (j1 == j2);
+  const int tid = threadIdx.x, bs = blockDim.x;
+  cpx<T>* spec = A.spec + I.soff;
+  const long long r1 = I.foff + (long long)j1 * N;
+  const long long r2 = I.foff + (long long)j2 * N;
+  const T aj = A.aw[jp];
+  const int mode = A.mode;
+  const T* P = static_cast<const T*>(I.p);
+  const T* Q = static_cast<const T*>(I.q);
+
+  if (tid == 0) sh_bad = 0;
+
+  double g = 1.0;
+  if (mode == ROW_FINAL) g = gauge(A, I, it, A.k, sh);
+  else if (mode == ROW_SINK_U && A.k > 1) g = gauge(A, I, it, A.k - 1, sh);
+
+  if (mode == ROW_FINAL) {
+    const T* uh = ubuf_of(A, A.k) + I.foff;
+    const T* vh = vbuf_of(A, A.k) + I.foff;
+    const double lg = log(g);
+    double acc = 0.0;
+    for (int c = tid; c < N; c += bs) {
+      for (int rr = 0; rr < (eq ? 1 : 2); ++rr) {
+        const long long idx = (rr ? r2 : r1) + c;
+        const long long fi = idx - I.foff;
+        const double phi = I.eps * (log((double)uh[fi]) - lg);
+        const double psi = I.eps * (log((double)vh[fi]) + lg);
+        if (A.out) A.out[idx] = (T)phi;
+        if (A.out2) A.out2[idx] = (T)psi;
+        const double pv = P[idx], qv = Q[idx];
+        if (I.balanced) acc += (double)aj * (phi * pv + psi * qv);
+        else acc += (double)aj * (I.tau * (1.0 - exp(-phi / I.tau)) * pv +
+                                  I.tau * (1.0 - exp(-psi / I.tau)) * qv);
+      }
+    }
+    acc = block_sum(acc, sh);
+    if (tid == 0) A.prep[((size_t)it * A.hs + jp) * 4 + 3] = acc;
+    return;
+  }
+
+  cpx<T>* X = buf0;
+  const bool has_inverse = (mode == ROW_INV || mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK);
+  if (has_inverse) {
+    for (int idx = tid; idx < N; idx += bs) {
+      cpx<T> z = {(T)0, (T)0};
+      int m = -1;
+      bool cj = false;
+      if (idx < L) m = idx;
+      else if (idx > N - L) { m = N - idx; cj = true; }
+      if (m >= 0) {
+        const cpx<T> ge = spec[(size_t)(2 * m) * h + jp];
+        const cpx<T> go = spec[(size_t)(2 * m + 1) * h + jp];
+        cpx<T> a = cadd(ge, go);
+        cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : csub(ge, go);
+        if (cj) { a.y = -a.y; b.y = -b.y; }
+        z = {a.x - b.y, a.y + b.x};  // a + i b
+      }
+      buf0[idx] = z;
+    }
+    __syncthreads();
+    X = fft_lds<T>(buf0, buf1, N, A.fac, A.nfac, A.tw, (T)1);
+  }
+
+  if (mode == ROW_INV) {
+    const T s = A.wts_out ? aj : (T)1;
+    for (int c = tid; c < N; c += bs) {
+      const cpx<T> z = X[c];
+      A.out[r1 + c] = z.x * s;
+      if (!eq) A.out[r2 + c] = z.y * s;
+    }
+    return;
+  }
+
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  bool bad = false;
+  if (mode == ROW_SINK_U || mode == ROW_CHECK) {
+    // u_hat_k = f(p / (g_{k-1} K v_hat_{k-1})); residual of iteration k-1:
+    // u_{k-1} (.) K v_{k-1} - p = u_hat_{k-1} (.) K v_hat_{k-1} - p.
+    const T gs = (T)g;
+    const T* uo = ubuf_of(A, A.k - 1) + I.foff;
+    T* un = ubuf_of(A, A.k) + I.foff;
+    const bool chk = (A.chk_slot >= 0);
+    for (int c = tid; c < N; c += bs) {
+      cpx<T> z = X[c];
+      T nv[2];
+      for (int rr = 0; rr < (eq ? 1 : 2); ++rr) {
+        const long long idx = (rr ? r2 : r1) + c;
+        const long long fi = idx - I.foff;
+        const T kraw = rr ? z.y : z.x;
+        const T pv = P[idx];
+        if (chk) {
+          const double r = (double)uo[fi] * (double)kraw - (double)pv;
+          acc2 += r * r;
+        }
+        if (mode == ROW_CHECK) { nv[rr] = (T)0; continue; }
+        const T kv = gs * kraw;
+        bad |= bad_kernel_value(kv);
+        T u = pv / kv;
+        if (!I.balanced) u = pow(u, (T)I.lam);
+        un[fi] = u;
+        nv[rr] = u;
+        acc0 += I.balanced ? (double)u : (double)aj * (double)pv * pow((double)u, -I.eot);
+      }
+      if (mode == ROW_SINK_U) X[c] = {nv[0], eq ? (T)0 : nv[1]};
+    }
+  } else if (mode == ROW_SINK_V) {
+    // v_hat_k = f(q / K u_hat_k): Alg. 1 updates v from u before the gauge step.
+    T* vn = vbuf_of(A, A.k) + I.foff;
+    for (int c = tid; c < N; c += bs) {
+      cpx<T> z = X[c];
+      T nv[2];
+      for (int rr = 0; rr < (eq ? 1 : 2); ++rr) {
+        const long long idx = (rr ? r2 : r1) + c;
+        const T kraw = rr ? z.y : z.x;
+        bad |= bad_kernel_value(kraw);
+        const T qv = Q[idx];
+        T v = qv / kraw;
+        if (!I.balanced) {
+          v = pow(v, (T)I.lam);
+          acc1 += (double)aj * (double)qv * pow((double)v, -I.eot);
+        }
+        vn[idx - I.foff] = v;
+        nv[rr] = v;
+      }
+      X[c] = {nv[0], eq ? (T)0 : nv[1]};
+    }
+  } else {  // ROW_FWD, ROW_INIT: load the input rows
+    const T* in = A.in;
+    for (int c = tid; c < N; c += bs) {
+      T v1 = in ? in[r1 + c] : (T)1;
+      T v2 = eq ? (T)0 : (in ? in[r2 + c] : (T)1);
+      X[c] = {v1, v2};
+      if (mode == ROW_INIT) {
+        for (int rr = 0; rr < (eq ? 1 : 2); ++rr) {
+          const long long idx = (rr ? r2 : r1) + c;
+          const double pv = P[idx], qv = Q[idx];
+          acc0 += pv * pv;
+          acc1 += (double)aj * pv;
+          acc2 += (double)aj * qv;
+        }
+      }
+    }
+  }
+
+  if (bad) sh_bad = 1;
+  if (mode == ROW_INIT) {
+    acc0 = block_sum(acc0, sh);
+    acc1 = block_sum(acc1, sh);
+    acc2 = block_sum(acc2, sh);
+    if (tid == 0) {
+      double* pr = A.prep + ((size_t)it * A.hs + jp) * 4;
+      pr[0] = acc0;
+      pr[1] = acc1;
+      pr[2] = acc2;
+    }
+  } else if (mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK) {
+    if (A.chk_slot >= 0) {
+      acc2 = block_sum(acc2, sh);
+      if (tid == 0) A.rhist[((size_t)it * A.nslot + A.chk_slot) * A.hs + jp] = acc2;
+    }
+    if (mode != ROW_CHECK) {
+      const double s = block_sum(mode == ROW_SINK_U ? acc0 : acc1, sh);
+      if (tid == 0) {
+        A.red[(((size_t)(A.k & 1) * A.nitems_all + it) * A.hs + jp) * 4 + (mode == ROW_SINK_U ? 0 : 1)] = s;
+        if (sh_bad) atomicMin(&A.brk[it], A.k);
+      }
+    }
+    if (mode == ROW_CHECK) return;
+  }
+  __syncthreads();
+
+  // forward FFT of the rows now in X, fold, weight, store
+  cpx<T>* other = (X == buf0) ? buf1 : buf0;
+  cpx<T>* Z = fft_lds<T>(X, other, N, A.fac, A.nfac, A.tw, (T)-1);
+  const T cw = (mode == ROW_FWD && !A.wts_in) ? (T)1 : aj;
+  for (int m = tid; m < L; m += bs) {
+    const cpx<T> a = Z[m];
+    cpx<T> b = Z[(N - m) % N];
+    b.y = -b.y;
+    cpx<T> E, O;
+    if (eq) {
+      E = a;
+      O = {(T)0, (T)0};
+    } else {
+      const cpx<T> x1 = {(T)0.5 * (a.x + b.x), (T)0.5 * (a.y + b.y)};
+      const cpx<T> x2 = {(T)0.5 * (a.y - b.y), (T)-0.5 * (a.x - b.x)};
+      E = cadd(x1, x2);
+      O = csub(x1, x2);
+    }
+    spec[(size_t)(2 * m) * h + jp] = cscale(E, cw);
+    spec[(size_t)(2 * m + 1) * h + jp] = cscale(O, cw);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Legendre kernels.  grid = (L orders, item chunks), block = 256.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long tri_off(long long m, long long L) { return m * L - m * (m - 1) / 2; }
+
+template <typename TT>
+__device__ __forceinline__ auto tab_load(const TT* p) {
+  if constexpr (sizeof(TT) == 2) {
+    return __uint_as_float(((unsigned int)(*reinterpret_cast<const unsigned short*>(p))) << 16);
+  } else {
+    return *p;
+  }
+}
+
+template <typename T, int IB>
+__device__ __forceinline__ void wave_reduce_cpx(cpx<T>* acc) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      acc[i].x += __shfl_xor(acc[i].x, o, 64);
+      acc[i].y += __shfl_xor(acc[i].y, o, 64);
+    }
+  }
+}
+
+template <typename T, typename TT, int IB>
+__global__ void __launch_bounds__(256) legendre_table_kernel(LegArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = A.L, h = A.h, hpad = A.hpad;
+  const int m = blockIdx.x;
+  const int ib0 = blockIdx.y * IB;
+  const int nbi = min(IB, A.nb - ib0);
+  const int nr = L - m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  cpx<T>* ys = reinterpret_cast<cpx<T>*>(smem_raw);  // [IB][2h]
+  cpx<T>* bsh = ys + (size_t)IB * 2 * h;              // [IB][L]
+  const TT* tab = static_cast<const TT*>(A.tab) + tri_off(m, L) * hpad;
+  const long long toff = tri_off(m, L);
+
+  if (A.mode != 2) {
+    for (int i = 0; i < IB; ++i) {
+      const cpx<T>* src = (i < nbi) ? A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h : nullptr;
+      for (int idx = tid; idx < 2 * h; idx += blockDim.x)
+        ys[(size_t)i * 2 * h + idx] = src ? src[idx] : cpx<T>{(T)0, (T)0};
+    }
+    __syncthreads();
+    for (int r = wave; r < nr; r += nw) {
+      const int par = r & 1;
+      cpx<T> acc[IB];
+#pragma unroll
+      for (int i = 0; i < IB; ++i) acc[i] = {(T)0, (T)0};
+      const TT* row = tab + (size_t)r * hpad;
+      for (int j = lane; j < h; j += 64) {
+        const T t = (T)tab_load(row + j);
+#pragma unroll
+        for (int i = 0; i < IB; ++i) {
+          const cpx<T> y = ys[(size_t)i * 2 * h + par * h + j];
+          acc[i].x += t * y.x;
+          acc[i].y += t * y.y;
+        }
+      }
+      wave_reduce_cpx<T, IB>(acc);
+      if (lane == 0) {
+        for (int i = 0; i < nbi; ++i) {
+          if (A.mode == 0) {
+            const T hv = A.hl[(size_t)(A.item0 + ib0 + i) * A.hl_stride + m + r];
+            bsh[(size_t)i * L + r] = cscale(acc[i], hv);
+          } else {
+            A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r] = acc[i];
+          }
+        }
+      }
+    }
+    if (A.mode == 1) return;
+  } else {
+    for (int i = 0; i < nbi; ++i)
+      for (int r = tid; r < nr; r += blockDim.x)
+        bsh[(size_t)i * L + r] = A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r];
+  }
+  __syncthreads();
+
+  for (int j = tid; j < h; j += blockDim.x) {
+    cpx<T> ae[IB], ao[IB];
+#pragma unroll
+    for (int i = 0; i < IB; ++i) { ae[i] = {(T)0, (T)0}; ao[i] = {(T)0, (T)0}; }
+    int r = 0;
+    for (; r + 1 < nr; r += 2) {
+      const T t0 = (T)tab_load(tab + (size_t)r * hpad + j);
+      const T t1 = (T)tab_load(tab + (size_t)(r + 1) * hpad + j);
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        const cpx<T> b0 = bsh[(size_t)i * L + r], b1 = bsh[(size_t)i * L + r + 1];
+        ae[i].x += t0 * b0.x; ae[i].y += t0 * b0.y;
+        ao[i].x += t1 * b1.x; ao[i].y += t1 * b1.y;
+      }
+    }
+    if (r < nr) {
+      const T t0 = (T)tab_load(tab + (size_t)r * hpad + j);
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        const cpx<T> b0 = bsh[(size_t)i * L + r];
+        ae[i].x += t0 * b0.x; ae[i].y += t0 * b0.y;
+      }
+    }
+    for (int i = 0; i < nbi; ++i) {
+      cpx<T>* dst = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+      dst[j] = ae[i];
+      dst[h + j] = ao[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Legendre kernel with P̄_l^m generated on the fly (float64 recurrence).
+//
+// Each thread owns JPT latitude chains j.  The recurrence is the rescaled
+// three-term form R_l = c_l x R_{l-1} + R_{l-2}, P̄_l^m = gamma_l R_l (two
+// float64 operations per value; coefficients c_l, gamma_l are precomputed on
+// the host), restarted from the seed P̄_m^m(x_j) for the synthesis pass.
+// Analysis sums over j are formed per block of RB rows: each lane accumulates
+// its chains, then a wave transpose-reduction leaves value v = lane/2 summed
+// over the wave, and the waves are combined through LDS in wave order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T transpose_reduce32(T* a, int lane) {
+  // 32 live values -> 1 per lane pair; lane holds value (lane >> 1) afterwards
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const bool up = (lane & 32) != 0;
+    T send = up ? a[i] : a[16 + i];
+    T keep = up ? a[16 + i] : a[i];
+    a[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const bool up = (lane & 16) != 0;
+    T send = up ? a[i] : a[8 + i];
+    T keep = up ? a[8 + i] : a[i];
+    a[i] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const bool up = (lane & 8) != 0;
+    T send = up ? a[i] : a[4 + i];
+    T keep = up ? a[4 + i] : a[i];
+    a[i] = keep + __shfl_xor(send, 8, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const bool up = (lane & 4) != 0;
+    T send = up ? a[i] : a[2 + i];
+    T keep = up ? a[2 + i] : a[i];
+    a[i] = keep + __shfl_xor(send, 4, 64);
+  }
+  {
+    const bool up = (lane & 2) != 0;
+    T send = up ? a[0] : a[1];
+    T keep = up ? a[1] : a[0];
+    a[0] = keep + __shfl_xor(send, 2, 64);
+  }
+  a[0] += __shfl_xor(a[0], 1, 64);
+  return a[0];
+}
+
+template <typename T, int IB, int JPT>
+__global__ void __launch_bounds__(256) legendre_recur_kernel(LegArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int RB = 16 / IB;       // rows per reduction block
+  constexpr int V = 2 * RB * IB;    // 32 partial sums per lane per block
+  const int L = A.L, h = A.h;
+  const int m = blockIdx.x;
+  const int nr = L - m;
+  const int ib0 = blockIdx.y * IB;
+  const int nbi = min(IB, A.nb - ib0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
+  cpx<T>* bsh = reinterpret_cast<cpx<T>*>(smem_raw);   // [IB][L]
+  T* part = reinterpret_cast<T*>(bsh + (size_t)IB * L); // [nw][V]
+  const long long toff = tri_off(m, L);
+  const double* __restrict__ coef = A.rcoef + toff;
+  const double* __restrict__ gam = A.rgam + toff;
+
+  double xj[JPT], R1[JPT], R2[JPT];
+  cpx<T> yE[JPT][IB], yO[JPT][IB];
+#pragma unroll
+  for (int c = 0; c < JPT; ++c) {
+    const int j = tid + c * nt;
+    const bool act = j < h;
+    xj[c] = act ? A.xs[j] : 0.0;
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      if (act && i < nbi && A.mode != 2) {
+        const cpx<T>* s = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+        yE[c][i] = s[j];
+        yO[c][i] = s[h + j];
+      } else {
+        yE[c][i] = {(T)0, (T)0};
+        yO[c][i] = {(T)0, (T)0};
+      }
+    }
+  }
+
+  if (A.mode != 2) {
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+      const int j = tid + c * nt;
+      R1[c] = (j < h) ? A.rseed[(size_t)m * h + j] : 0.0;
+      R2[c] = 0.0;
+    }
+    for (int r0 = 0; r0 < nr; r0 += RB) {
+      T acc[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = (T)0;
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const int r = r0 + rr;
+        if (r < nr) {
+          if (r > 0) {
+            const double cf = coef[r];
+#pragma unroll
+            for (int c = 0; c < JPT; ++c) {
+              const double rn = fma(cf * xj[c], R1[c], R2[c]);
+              R2[c] = R1[c];
+              R1[c] = rn;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < JPT; ++c) {
+            const T pv = (T)R1[c];
+#pragma unroll
+            for (int i = 0; i < IB; ++i) {
+              const cpx<T> y = (rr & 1) ? yO[c][i] : yE[c][i];  // r0 is even, so r&1 == rr&1
+              acc[(rr * IB + i) * 2 + 0] += pv * y.x;
+              acc[(rr * IB + i) * 2 + 1] += pv * y.y;
+            }
+          }
+        }
+      }
+      const T s = transpose_reduce32<T>(acc, lane);
+      if ((lane & 1) == 0) part[wave * V + (lane >> 1)] = s;
+      __syncthreads();
+      if (tid < V) {
+        T tot = (T)0;
+        for (int w = 0; w < nw; ++w) tot += part[w * V + tid];
+        const int comp = tid & 1, i = (tid >> 1) % IB, rr = (tid >> 1) / IB, r = r0 + rr;
+        if (r < nr && i < nbi) {
+          const double g = gam[r];
+          if (A.mode == 0) {
+            const T sc = (T)(g * g) * A.hl[(size_t)(A.item0 + ib0 + i) * A.hl_stride + m + r];
+            T* dst = reinterpret_cast<T*>(&bsh[(size_t)i * L + r]);
+            dst[comp] = tot * sc;
+          } else {
+            T* dst = reinterpret_cast<T*>(&A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r]);
+            dst[comp] = tot * (T)g;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (A.mode == 1) return;
+  } else {
+    for (int i = 0; i < nbi; ++i)
+      for (int r = tid; r < nr; r += nt)
+        bsh[(size_t)i * L + r] = cscale(A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r], (T)gam[r]);
+    __syncthreads();
+  }
+
+  // synthesis: G^{E|O}_m(j) = sum_l (b_l gamma_l) R_l(x_j)
+  cpx<T> gE[JPT][IB], gO[JPT][IB];
+#pragma unroll
+  for (int c = 0; c < JPT; ++c) {
+    const int j = tid + c * nt;
+    R1[c] = (j < h) ? A.rseed[(size_t)m * h + j] : 0.0;
+    R2[c] = 0.0;
+#pragma unroll
+    for (int i = 0; i < IB; ++i) { gE[c][i] = {(T)0, (T)0}; gO[c][i] = {(T)0, (T)0}; }
+  }
+  for (int r = 0; r < nr; ++r) {
+    if (r > 0) {
+      const double cf = coef[r];
+#pragma unroll
+      for (int c = 0; c < JPT; ++c) {
+        const double rn = fma(cf * xj[c], R1[c], R2[c]);
+        R2[c] = R1[c];
+        R1[c] = rn;
+      }
+    }
+    cpx<T> b[IB];
+#pragma unroll
+    for (int i = 0; i < IB; ++i) b[i] = bsh[(size_t)i * L + r];
+    if (r & 1) {
+#pragma unroll
+      for (int c = 0; c < JPT; ++c) {
+        const T pv = (T)R1[c];
+#pragma unroll
+        for (int i = 0; i < IB; ++i) { gO[c][i].x += pv * b[i].x; gO[c][i].y += pv * b[i].y; }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < JPT; ++c) {
+        const T pv = (T)R1[c];
+#pragma unroll
+        for (int i = 0; i < IB; ++i) { gE[c][i].x += pv * b[i].x; gE[c][i].y += pv * b[i].y; }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < JPT; ++c) {
+    const int j = tid + c * nt;
+    if (j >= h) continue;
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      if (i >= nbi) continue;
+      cpx<T>* dst = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+      dst[j] = gE[c][i];
+      dst[h + j] = gO[c][i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-item final reductions: cost, e_marg history and final residual, masses.
+// res[item*8 + .] = {cost, err, m(p), m(q), ||p||, 0, 0, 0}.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) reduce_kernel(RowArgs<T> A, int nchk_done, double* res, double* ehist) {
+  __shared__ double sh[16];
+  const int it = A.item0 + blockIdx.x;
+  const int h = A.h;
+  double s[4] = {0, 0, 0, 0};
+  for (int q = threadIdx.x; q < h; q += blockDim.x)
+    for (int c = 0; c < 4; ++c) s[c] += A.prep[((size_t)it * A.hs + q) * 4 + c];
+  for (int c = 0; c < 4; ++c) s[c] = block_sum(s[c], sh);
+  const double pn = sqrt(s[0]);
+  double fin = 0.0;
+  if (A.chk_slot >= 0) {
+    for (int q = threadIdx.x; q < h; q += blockDim.x) fin += A.rhist[((size_t)it * A.nslot + A.chk_slot) * A.hs + q];
+    fin = block_sum(fin, sh);
+  }
+  for (int c = 0; c < nchk_done; ++c) {
+    double e = 0.0;
+    for (int q = threadIdx.x; q < h; q += blockDim.x) e += A.rhist[((size_t)it * A.nslot + c) * A.hs + q];
+    e = block_sum(e, sh);
+    if (threadIdx.x == 0) ehist[(size_t)it * A.nslot + c] = sqrt(e) / pn;
+  }
+  if (threadIdx.x == 0) {
+    double* r = res + (size_t)it * 8;
+    r[0] = s[3];
+    r[1] = sqrt(fin) / pn;
+    r[2] = s[1];
+    r[3] = s[2];
+    r[4] = pn;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream) {
+  dim3 grid(a.h, nb);
+  const size_t lds = (size_t)2 * a.nlon * sizeof(cpx<T>);
+  hipLaunchKernelGGL(row_kernel<T>, grid, dim3(256), lds, stream, a);
+  return hipGetLastError();
+}
+
+template <typename T, typename TT, int IB>
+static hipError_t launch_leg_ib(const LegArgs<T>& a, hipStream_t stream) {
+  dim3 grid(a.L, (a.nb + IB - 1) / IB);
+  const size_t lds = ((size_t)IB * 2 * a.h + (size_t)IB * a.L) * sizeof(cpx<T>);
+  hipLaunchKernelGGL((legendre_table_kernel<T, TT, IB>), grid, dim3(256), lds, stream, a);
+  return hipGetLastError();
+}
+
+template <typename T, typename TT>
+static hipError_t launch_leg_tt(const LegArgs<T>& a, int ib, hipStream_t stream) {
+  switch (ib) {
+    case 1: return launch_leg_ib<T, TT, 1>(a, stream);
+    case 2: return launch_leg_ib<T, TT, 2>(a, stream);
+    case 4: return launch_leg_ib<T, TT, 4>(a, stream);
+    default: return launch_leg_ib<T, TT, 8>(a, stream);
+  }
+}
+
+template <typename T, int IB, int JPT>
+static hipError_t launch_recur(const LegArgs<T>& a, hipStream_t stream) {
+  const int threads = ((a.h + JPT - 1) / JPT + 63) / 64 * 64;
+  dim3 grid(a.L, (a.nb + IB - 1) / IB);
+  const size_t lds = (size_t)IB * a.L * sizeof(cpx<T>) + (size_t)(threads / 64) * 32 * sizeof(T);
+  hipLaunchKernelGGL((legendre_recur_kernel<T, IB, JPT>), grid, dim3(threads), lds, stream, a);
+  return hipGetLastError();
+}
+
+template <typename T, int IB>
+static hipError_t launch_recur_ib(const LegArgs<T>& a, int jpt, hipStream_t stream) {
+  switch (jpt) {
+    case 1: return launch_recur<T, IB, 1>(a, stream);
+    case 2: return launch_recur<T, IB, 2>(a, stream);
+    default: return launch_recur<T, IB, 4>(a, stream);
+  }
+}
+
+// Chains per thread for the recurrence kernel: the fewest that keep the
+// block at <= 256 threads.
+int recur_jpt(int h) { return h <= 256 ? 1 : (h <= 512 ? 2 : 4); }
+
+template <typename T>
+hipError_t launch_legendre(const LegArgs<T>& a, int table_kind, int ib, hipStream_t stream) {
+  switch (table_kind) {
+    case TAB_F64: return launch_leg_tt<T, double>(a, ib, stream);
+    case TAB_F32: return launch_leg_tt<T, float>(a, ib, stream);
+    case TAB_BF16: return launch_leg_tt<T, unsigned short>(a, ib, stream);
+    case TAB_RECUR: {
+      if (a.h > 1024) return hipErrorInvalidValue;
+      const int jpt = recur_jpt(a.h);
+      switch (ib) {
+        case 1: return launch_recur_ib<T, 1>(a, jpt, stream);
+        case 2: return launch_recur_ib<T, 2>(a, jpt, stream);
+        default: return launch_recur_ib<T, 4>(a, jpt, stream);
+      }
+    }
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_reduce(const RowArgs<T>& a, int nb, int nchk_done, double* res, double* ehist,
+                         hipStream_t stream) {
+  hipLaunchKernelGGL(reduce_kernel<T>, dim3(nb), dim3(256), 0, stream, a, nchk_done, res, ehist);
+  return hipGetLastError();
+}
+
+template hipError_t launch_rows<float>(const RowArgs<float>&, int, hipStream_t);
+template hipError_t launch_rows<double>(const RowArgs<double>&, int, hipStream_t);
+template hipError_t launch_legendre<float>(const LegArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_legendre<double>(const LegArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_reduce<float>(const RowArgs<float>&, int, int, double*, double*, hipStream_t);
+template hipError_t launch_reduce<double>(const RowArgs<double>&, int, int, double*, double*, hipStream_t);
+
+}  // namespace shot

@@ -1,0 +1,112 @@
+// Internal types shared by the libshot host code and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace shot {
+
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+// Per-item descriptor, resident on the device for the duration of a call.
+struct ItemDev {
+  long long foff;      // element offset of the item's fields (p, q, phi, psi, in, out, u, v)
+  long long soff;      // complex-element offset of the item's spectral workspace
+  long long coff;      // complex-element offset of the item's packed (m, l) coefficients
+  const void* p;       // this item's first marginal (device)
+  const void* q;       // this item's second marginal (device)
+  double eps;          // entropic parameter
+  double tau;          // marginal penalty (ignored when balanced)
+  double lam;          // tau/(tau+eps): exponent of the unbalanced update
+  double eot;          // eps/tau
+  int balanced;        // 1: tau = +inf
+  int pad;
+};
+
+// Row kernel modes.
+enum RowMode : int {
+  ROW_FWD = 0,     // field -> folded spectrum
+  ROW_INV = 1,     // folded spectrum -> field
+  ROW_SINK_U = 2,  // spectrum of K v -> u-update (+ e_marg residual) -> spectrum of u
+  ROW_SINK_V = 3,  // spectrum of K u -> v-update -> spectrum of v
+  ROW_CHECK = 4,   // spectrum of K v -> e_marg residual only
+  ROW_FINAL = 5,   // potentials and cost partials (no FFT)
+  ROW_INIT = 6,    // spectrum of the constant 1 field + norms/masses of p, q
+  // adjoint sweep (balanced, see adjoint comments in kernels.hip)
+  ROW_ADJ_B = 7,   // v-bar -> B-bar, q-bar; spectrum of B-bar
+  ROW_ADJ_A = 8,   // K^T B-bar -> u-hat-bar -> A-bar, p-bar; spectrum of A-bar
+  ROW_ADJ_V = 9,   // K^T A-bar -> v-bar of the previous iteration (stored)
+};
+
+template <typename T>
+struct RowArgs {
+  int nlat, nlon, L, h;
+  int hs;             // row-pair stride of the per-item partial-sum arrays (max h over items)
+  int nfac;
+  int fac[8];
+  const cpx<T>* tw;   // nlon forward twiddles exp(-2 pi i k / nlon)
+  const T* aw;        // h area weights (rows 0..h-1)
+  int item0;          // absolute index of this launch's first item
+  const ItemDev* items;
+  cpx<T>* spec;
+  int mode;
+  int k;              // iteration number (1-based) for SINK / CHECK / FINAL modes
+  int wts_in;         // FWD-like modes: multiply the folded spectrum by a_j
+  int wts_out;        // INV: multiply the output rows by a_j
+  const T* in;        // FWD: input fields (NULL = constant 1)
+  T* out;             // INV: output fields; FINAL: phi
+  T* out2;            // FINAL: psi
+  T* ubuf0; T* ubuf1; // ping-pong u-hat by iteration parity
+  T* vbuf0; T* vbuf1; // ping-pong v-hat by iteration parity
+  double* red;        // [2][nitems][h][4] per-row-pair partial sums (slot 0: u-half, 1: v-half)
+  int nitems_all;
+  double* rhist;      // [nitems][nslot][h] e_marg residual partials
+  int nslot;
+  int chk_slot;       // slot written by this launch, -1 for none
+  double* prep;       // [nitems][h][4]: sum p^2, sum a p, sum a q, cost partial
+  int* brk;           // [nitems] first breakdown iteration (INT_MAX = none)
+  // adjoint state
+  T* gA;              // adjoint sweep: p-bar accumulator (layout of fields)
+  T* gB;              // q-bar accumulator
+  T* vbar;            // v-bar of the current reverse iteration
+  const double* sbar; // [nitems] per-item s-bar of the current reverse iteration
+  const double* gk;   // [nitems] gauge g_k of the current reverse iteration
+};
+
+template <typename T>
+struct LegArgs {
+  int L, h, hpad;
+  const void* tab;        // TABLE mode: [L(L+1)/2][hpad] P̄ rows
+  const double* xs;       // RECURRENCE mode: h nodes
+  const double* rcoef;    // [L(L+1)/2]
+  const double* rgam;     // [L(L+1)/2]
+  const double* rseed;    // [L][h]
+  int item0, nb;
+  const ItemDev* items;
+  cpx<T>* spec;
+  const T* hl;            // [nitems][hl_stride] heat multipliers (by absolute item index)
+  int hl_stride;
+  int mode;               // 0 fused (analysis, x h, synthesis), 1 analysis -> coeff, 2 coeff -> synthesis
+  cpx<T>* coeff;          // packed (m, l) coefficients, item offsets ItemDev::coff (modes 1, 2)
+};
+
+// Launchers (kernels.hip).  All enqueue on `stream` and return the launch status.
+template <typename T>
+hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream);
+template <typename T>
+hipError_t launch_legendre(const LegArgs<T>& a, int table_kind, int ib, hipStream_t stream);
+template <typename T>
+hipError_t launch_reduce(const RowArgs<T>& a, int nb, int nchk_done, double* res, double* ehist,
+                         hipStream_t stream);
+template <typename T>
+hipError_t launch_adjoint_scalar(const RowArgs<T>& a, int nb, double* sbar, const T* uold_bar,
+                                 hipStream_t stream);
+
+// Table element kinds.
+enum { TAB_F64 = 0, TAB_F32 = 1, TAB_BF16 = 2, TAB_RECUR = 3 };
+
+}  // namespace shot
