@@ -168,6 +168,20 @@ shot_status shot_sinkhorn_divergence_grad(shot_plan_t plan, const int32_t* grid_
                                           void* dS_dp, int32_t mode, int32_t checkpoint_every,
                                           shot_solve_info* info, void* stream);
 
+/* Launch configuration of grid `grid`'s Legendre kernel: items advanced per
+ * workgroup (1, 2, 4 or 8; 0 = automatic, capped by LDS) and, for
+ * SHOT_LEG_RECURRENCE grids, latitude chains per thread (1, 2 or 4 with at
+ * most 256 threads per workgroup; 0 = automatic).  SHOT_E_INVALID otherwise. */
+shot_status shot_plan_set_tuning(shot_plan_t plan, int32_t grid, int32_t items_per_block,
+                                 int32_t chains_per_thread);
+shot_status shot_plan_get_tuning(shot_plan_t plan, int32_t grid, int32_t* items_per_block,
+                                 int32_t* chains_per_thread);
+
+/* Autotuner: times every valid launch configuration of grid `grid`'s fused
+ * Legendre kernel for a batch of `nitems` items (synthetic spectrum, HIP
+ * events on `stream`) and keeps the fastest on the plan.  Synchronises. */
+shot_status shot_autotune(shot_plan_t plan, int32_t grid, int32_t nitems, void* stream);
+
 /* Kernel timing.  When enabled, every launch of the Legendre kernels (class 0)
  * and of the row-FFT kernels (class 1) is bracketed by HIP events on the
  * launch stream; shot_profile_read synchronises and returns the number of

@@ -41,8 +41,9 @@ def sinkhorn(p, q, grid, eps, tau=math.inf, T=100, delta=0.0, C=10, K=None,
 
     ``normalize=False`` skips the balanced s-rescaling (a gauge; used by a test).
     Returns a dict with u, v, phi, psi, cost, iters, e_hist [(k, e)], err (e_marg
-    of the returned u, v), breakdown (first bad iteration per item, 0 if none)
-    and kratio (min over the run of min(K.)/max(K.) per item).
+    of the returned u, v), breakdown (first bad iteration per item, 0 if none),
+    kratio (min over the run of min(K.)/max(K.) per item; -inf once non-finite)
+    and kratio_hist (that minimum per iteration).
     """
     p = np.asarray(p, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
@@ -59,6 +60,8 @@ def sinkhorn(p, q, grid, eps, tau=math.inf, T=100, delta=0.0, C=10, K=None,
     if delta > 0 and len(lead) > 0:
         raise ValueError("early exit is only defined for a single item")
 
+    kratio_hist = []   # per iteration: min over its two heat applies of min(K.)/max(K.)
+
     def watch(Kx, k):
         nonlocal kratio
         mn = Kx.min(axis=(-2, -1))
@@ -67,7 +70,12 @@ def sinkhorn(p, q, grid, eps, tau=math.inf, T=100, delta=0.0, C=10, K=None,
         new = bad & (breakdown == 0)
         breakdown[new] = k
         with np.errstate(invalid="ignore", divide="ignore"):
-            kratio = np.fmin(kratio, mn / mx)
+            ratio = np.where(np.isfinite(mn / mx), mn / mx, -np.inf)
+            kratio = np.fmin(kratio, ratio)
+        if len(kratio_hist) < k:
+            kratio_hist.append(ratio)
+        else:
+            kratio_hist[k - 1] = np.fmin(kratio_hist[k - 1], ratio)
 
     e_hist = []
     k = 0
@@ -110,7 +118,7 @@ def sinkhorn(p, q, grid, eps, tau=math.inf, T=100, delta=0.0, C=10, K=None,
             cost = _sum2(a * (tau * (1.0 - np.exp(-phi / tau)) * p
                               + tau * (1.0 - np.exp(-psi / tau)) * q))
     return dict(u=u, v=v, phi=phi, psi=psi, cost=cost, iters=k, e_hist=e_hist,
-                err=err, breakdown=breakdown, kratio=kratio)
+                err=err, breakdown=breakdown, kratio=kratio, kratio_hist=kratio_hist)
 
 
 def mass(p, grid):

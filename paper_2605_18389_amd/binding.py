@@ -39,7 +39,8 @@ EXPORTS = [
     "shot_sht_plan", "shot_plan_destroy", "shot_plan_grid", "shot_sht_analysis",
     "shot_sht_synthesis", "shot_heat_apply", "shot_sinkhorn_solve", "shot_sinkhorn_divergence",
     "shot_sinkhorn_divergence_grad", "shot_profile_enable", "shot_profile_read",
-    "shot_status_string", "shot_last_error",
+    "shot_status_string", "shot_last_error", "shot_plan_set_tuning", "shot_plan_get_tuning",
+    "shot_autotune",
 ]
 
 
@@ -103,6 +104,9 @@ def load_library(path=None):
         "shot_sinkhorn_divergence_grad": [vp, ip, i32, ctypes.POINTER(Params), vp, vp, dp, vp, i32,
                                           i32, ctypes.POINTER(SolveInfo), vp],
         "shot_profile_enable": [vp, i32],
+        "shot_plan_set_tuning": [vp, i32, i32, i32],
+        "shot_plan_get_tuning": [vp, i32, ip, ip],
+        "shot_autotune": [vp, i32, i32, vp],
         "shot_profile_read": [vp, i32, ctypes.POINTER(ctypes.c_int64), dp],
     }
     for name, args in sig.items():
@@ -326,6 +330,22 @@ class Plan:
             0 if mode == "unrolled" else 1, int(checkpoint_every), info, _stream_ptr())
         _check("shot_sinkhorn_divergence_grad", code, allow=(OK, W_NOT_CONVERGED, E_BREAKDOWN))
         return S, g, self._info_dicts(info, 3 * n)
+
+    # ---------------------------------------------------------------- tuning
+    def set_tuning(self, grid=0, items_per_block=0, chains_per_thread=0):
+        _check("shot_plan_set_tuning", self.lib.shot_plan_set_tuning(self.handle, grid, items_per_block,
+                                                                     chains_per_thread))
+
+    def get_tuning(self, grid=0):
+        ib = ctypes.c_int32()
+        jpt = ctypes.c_int32()
+        _check("shot_plan_get_tuning", self.lib.shot_plan_get_tuning(self.handle, grid, ctypes.byref(ib),
+                                                                     ctypes.byref(jpt)))
+        return ib.value, jpt.value
+
+    def autotune(self, grid=0, nitems=1):
+        _check("shot_autotune", self.lib.shot_autotune(self.handle, grid, nitems, _stream_ptr()))
+        return self.get_tuning(grid)
 
     # ------------------------------------------------------------- profiling
     def profile(self, enable=True):

@@ -37,8 +37,11 @@ struct GridRec {
   double* d_rcoef = nullptr;
   double* d_rgam = nullptr;
   double* d_rseed = nullptr;
+  double* d_rck = nullptr;
   void* d_aw = nullptr;
   void* d_tw = nullptr;
+  int tune_ib = 0;   // Legendre items per workgroup (0 = automatic)
+  int tune_jpt = 0;  // recurrence chains per thread (0 = automatic)
   int64_t n() const { return (int64_t)d.nlat * d.nlon; }
 };
 
@@ -161,10 +164,11 @@ uint16_t to_bf16(double v) {
 }
 
 void free_grid(GridRec& g) {
-  for (void* p : {g.d_tab, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam, (void*)g.d_rseed, g.d_aw, g.d_tw})
+  for (void* p : {g.d_tab, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam, (void*)g.d_rseed,
+                  (void*)g.d_rck, g.d_aw, g.d_tw})
     if (p) (void)hipFree(p);
   g.d_tab = g.d_aw = g.d_tw = nullptr;
-  g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = nullptr;
+  g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = g.d_rck = nullptr;
 }
 
 shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) {
@@ -218,8 +222,11 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
     if (st != SHOT_OK) return st;
   } else {
     g.tab_kind = TAB_RECUR;
-    std::vector<double> coef, gam, seed;
+    std::vector<double> coef, gam, seed, ck;
     legendre_recurrence_data(d.L, xs, coef, gam, seed);
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    legendre_checkpoints(d.L, xs, coef, seed, ck, (int)hw);
+    if ((st = upload((void**)&g.d_rck, ck, s)) != SHOT_OK) return st;
     if ((st = upload((void**)&g.d_xs, xs, s)) != SHOT_OK) return st;
     if ((st = upload((void**)&g.d_rcoef, coef, s)) != SHOT_OK) return st;
     if ((st = upload((void**)&g.d_rgam, gam, s)) != SHOT_OK) return st;
@@ -418,6 +425,7 @@ LegArgs<T> leg_args(const GridRec& g, const Group& G, const Work<T>& W, int hl_s
   a.rcoef = g.d_rcoef;
   a.rgam = g.d_rgam;
   a.rseed = g.d_rseed;
+  a.rck = g.d_rck;
   a.item0 = G.first;
   a.nb = G.count;
   a.items = W.items;
@@ -425,17 +433,37 @@ LegArgs<T> leg_args(const GridRec& g, const Group& G, const Work<T>& W, int hl_s
   a.hl = W.hl;
   a.hl_stride = hl_stride;
   a.mode = 0;
+  a.jpt = g.tune_jpt;
   return a;
 }
 
 // Items per Legendre workgroup: as many as requested/available, capped so the
 // LDS staging (inputs IB*2h + coefficients IB*L complex) stays within 64 KiB.
 int pick_ib(const shot_plan_s* P, const GridRec& g, int count) {
-  int ib = P->leg_ib > 0 ? P->leg_ib : 8;
-  if (g.tab_kind == TAB_RECUR) ib = std::min(ib, 4);
+  int ib = g.tune_ib > 0 ? g.tune_ib : (P->leg_ib > 0 ? P->leg_ib : 8);
   while (ib > 1 && ib > count) ib >>= 1;
+  if (g.tab_kind == TAB_RECUR) {
+    // coefficients (2 doubles) and IB double2 inputs per row, padded to 16 rows
+    const size_t npad = (g.d.L + 15) / 16 * 16;
+    ib = std::min(ib, 4);
+    while (ib > 1 && npad * 16 * (1 + ib) > 56 * 1024) ib >>= 1;
+    return ib;
+  }
   const size_t cs = P->prec == SHOT_FP64 ? 16 : 8;
   while (ib > 1 && (size_t)ib * (2 * g.h + g.d.L) * cs > 60 * 1024) ib >>= 1;
+  return ib;
+}
+
+// Row-split recurrence kernel: used unless a chains-per-thread tuning selects
+// the latitude-split kernel, when ceil(nlat/2) <= 384 and its LDS fits.
+bool use_split(const shot_plan_s* P, const GridRec& g) {
+  if (g.tab_kind != TAB_RECUR || g.tune_jpt != 0 || g.h > 384) return false;
+  return split_lds_bytes(g.d.L, g.h, 1, P->prec == SHOT_FP64 ? 8 : 4) <= 60 * 1024;
+}
+
+int split_ib(const shot_plan_s* P, const GridRec& g, int count) {
+  int ib = (g.tune_ib == 2 || (g.tune_ib == 0 && count >= 2)) ? 2 : 1;
+  if (ib == 2 && split_lds_bytes(g.d.L, g.h, 2, P->prec == SHOT_FP64 ? 8 : 4) > 60 * 1024) ib = 1;
   return ib;
 }
 
@@ -449,8 +477,14 @@ shot_status run_rows(shot_plan_s* P, const RowArgs<T>& a, int nb, hipStream_t s)
 template <typename T>
 shot_status run_leg(shot_plan_s* P, const GridRec& g, LegArgs<T> a, hipStream_t s) {
   ProfScope ps(P, s, 0);
-  const int ib = pick_ib(P, g, a.nb);
-  hipError_t e = launch_legendre<T>(a, g.tab_kind, ib, s);
+  hipError_t e;
+  if (use_split(P, g)) {
+    const int ib = split_ib(P, g, a.nb);
+    e = launch_legendre_split<T>(a, ib, s);
+  } else {
+    const int ib = pick_ib(P, g, a.nb);
+    e = launch_legendre<T>(a, g.tab_kind, ib, s);
+  }
   return e == hipSuccess ? SHOT_OK : hip_fail(e, "Legendre kernel launch", __LINE__);
 }
 
@@ -669,6 +703,68 @@ shot_status worst(const shot_solve_info* info, int n) {
 
 bool ptr_ok(const void* p) { return p != nullptr; }
 
+// Time the fused Legendre launch for each candidate (items per workgroup,
+// chains per thread) on a synthetic spectrum and keep the fastest on the grid.
+template <typename T>
+shot_status autotune_impl(shot_plan_s* P, GridRec& g, const Layout& Lo, int nitems, hipStream_t s) {
+  Work<T> W;
+  ST_TRY(carve<T>(P, Lo, nitems, false, 0, W));
+  std::vector<double> tv(nitems, 1e-3);
+  std::vector<int32_t> goi(nitems, (int32_t)(&g - P->grids.data()));
+  ST_TRY(upload_items<T>(P, Lo, goi.data(), {}, {}, tv, {}, {}, W, s));
+  {
+    std::vector<cpx<T>> fill((size_t)Lo.spec_total);
+    for (size_t i = 0; i < fill.size(); ++i) fill[i] = {(T)(1.0 / (1.0 + (double)(i % 97))), (T)0.25};
+    HIP_TRY(hipMemcpyAsync(W.spec, fill.data(), sizeof(cpx<T>) * fill.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  std::vector<std::pair<int, int>> cand;
+  for (int ib : {1, 2, 4, 8}) {
+    if (ib > nitems && ib != 1) continue;
+    if (g.tab_kind == TAB_RECUR) {
+      if (ib > 4) continue;
+      if (ib <= 2) cand.push_back({ib, 0});  // row-split kernel
+      for (int jpt : {1, 2, 4})
+        if (recur_jpt_valid(g.h, jpt)) cand.push_back({ib, jpt});
+    } else {
+      cand.push_back({ib, 0});
+    }
+  }
+  const int save_ib = g.tune_ib, save_jpt = g.tune_jpt;
+  const bool save_prof = P->prof;
+  P->prof = false;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  std::pair<int, int> bestc = {save_ib, save_jpt};
+  Group G{(int)(&g - P->grids.data()), 0, nitems};
+  for (auto c : cand) {
+    g.tune_ib = c.first;
+    g.tune_jpt = c.second;
+    if (use_split(P, g) ? split_ib(P, g, nitems) != c.first : pick_ib(P, g, nitems) != c.first)
+      continue;  // does not fit LDS
+    if (g.tab_kind == TAB_RECUR && c.second == 0 && !use_split(P, g)) continue;
+    shot_status st = SHOT_OK;
+    for (int w = 0; w < 2 && st == SHOT_OK; ++w) st = run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), s);
+    if (st != SHOT_OK) continue;
+    (void)hipEventRecord(e0, s);
+    const int reps = 5;
+    for (int r = 0; r < reps && st == SHOT_OK; ++r) st = run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), s);
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess || st != SHOT_OK) continue;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) { best = ms; bestc = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->prof = save_prof;
+  g.tune_ib = bestc.first;
+  g.tune_jpt = bestc.second;
+  return SHOT_OK;
+}
+
 // Def. 2.3: S = R(p,q) - (R(p,p) + R(q,q))/2 + eps/2 (m(p) - m(q))^2, float64.
 // inf holds the three solves of pair i at 3i, 3i+1, 3i+2; mass holds
 // (m(first marginal), m(second marginal)) per solve.
@@ -719,7 +815,9 @@ shot_status shot_sht_plan(shot_plan_t* out, const shot_grid_desc* grids, int32_t
     // one order's inputs and coefficients must fit the Legendre kernel's LDS
     const size_t cs = precision == SHOT_FP64 ? 16 : 8;
     if ((size_t)(2 * ((d.nlat + 1) / 2) + d.L) * cs > 60 * 1024) return SHOT_E_UNSUPPORTED;
-    if (legendre_mode == SHOT_LEG_RECURRENCE && (d.nlat + 1) / 2 > 1024) return SHOT_E_UNSUPPORTED;
+    if (legendre_mode == SHOT_LEG_RECURRENCE &&
+        ((d.nlat + 1) / 2 > 1024 || (size_t)(d.L + 15) / 16 * 16 * 32 > 56 * 1024))
+      return SHOT_E_UNSUPPORTED;
   }
   shot_plan_s* P = new (std::nothrow) shot_plan_s();
   if (!P) return SHOT_E_NOMEM;
@@ -854,6 +952,42 @@ shot_status shot_sinkhorn_divergence_grad(shot_plan_t P, const int32_t* gop, int
   (void)P; (void)gop; (void)npairs; (void)params; (void)p; (void)q; (void)S_out; (void)dS_dp;
   (void)mode; (void)checkpoint_every; (void)info; (void)stream;
   return SHOT_E_UNSUPPORTED;
+}
+
+shot_status shot_plan_set_tuning(shot_plan_t P, int32_t grid, int32_t items_per_block,
+                                 int32_t chains_per_thread) {
+  if (!P || grid < 0 || grid >= (int)P->grids.size()) return SHOT_E_INVALID;
+  GridRec& g = P->grids[grid];
+  if (items_per_block != 0 && items_per_block != 1 && items_per_block != 2 && items_per_block != 4 &&
+      items_per_block != 8)
+    return SHOT_E_INVALID;
+  if (chains_per_thread != 0 && (g.tab_kind != TAB_RECUR || !recur_jpt_valid(g.h, chains_per_thread)))
+    return SHOT_E_INVALID;
+  g.tune_ib = items_per_block;
+  g.tune_jpt = chains_per_thread;
+  return SHOT_OK;
+}
+
+shot_status shot_plan_get_tuning(shot_plan_t P, int32_t grid, int32_t* items_per_block,
+                                 int32_t* chains_per_thread) {
+  if (!P || grid < 0 || grid >= (int)P->grids.size()) return SHOT_E_INVALID;
+  const GridRec& g = P->grids[grid];
+  if (items_per_block) *items_per_block = g.tune_ib;
+  if (chains_per_thread) *chains_per_thread = g.tune_jpt;
+  return SHOT_OK;
+}
+
+shot_status shot_autotune(shot_plan_t P, int32_t grid, int32_t nitems, void* stream) {
+  if (!P || grid < 0 || grid >= (int)P->grids.size() || nitems <= 0) return SHOT_E_INVALID;
+  HIP_TRY(hipSetDevice(P->dev));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GridRec& g = P->grids[grid];
+  std::vector<int32_t> goi(nitems, grid);
+  Layout Lo;
+  ST_TRY(make_layout(P, goi.data(), nitems, Lo));
+  const bool f64 = P->prec == SHOT_FP64;
+  shot_status st = f64 ? autotune_impl<double>(P, g, Lo, nitems, s) : autotune_impl<float>(P, g, Lo, nitems, s);
+  return st;
 }
 
 shot_status shot_profile_enable(shot_plan_t P, int32_t enable) {

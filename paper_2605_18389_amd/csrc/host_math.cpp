@@ -164,3 +164,41 @@ void legendre_recurrence_data(int L, const std::vector<double>& x, std::vector<d
 }
 
 }  // namespace shot
+
+namespace shot {
+
+void legendre_checkpoints(int L, const std::vector<double>& x, const std::vector<double>& coef,
+                          const std::vector<double>& seed, std::vector<double>& ck, int nthreads) {
+  const int nx = (int)x.size();
+  ck.assign((size_t)L * 4 * nx * 2, 0.0);
+  nthreads = std::max(1, nthreads);
+  std::vector<std::thread> pool;
+  for (int tid = 0; tid < nthreads; ++tid) {
+    pool.emplace_back([&, tid]() {
+      for (int m = tid; m < L; m += nthreads) {
+        const int nr = L - m;
+        const double* c = coef.data() + tri_offset(m, L);
+        for (int j = 0; j < nx; ++j) {
+          double r1 = seed[(size_t)m * nx + j], r2 = 0.0;
+          int r = 0;
+          for (int w = 0; w < 4; ++w) {
+            const int r0 = split_row(nr, w);
+            if (r0 >= nr) break;
+            while (r < r0) {
+              ++r;
+              const double rn = std::fma(c[r] * x[j], r1, r2);
+              r2 = r1;
+              r1 = rn;
+            }
+            double* dst = ck.data() + (((size_t)m * 4 + w) * nx + j) * 2;
+            dst[0] = r1;
+            dst[1] = r2;
+          }
+        }
+      }
+    });
+  }
+  for (auto& t : pool) t.join();
+}
+
+}  // namespace shot

@@ -6,7 +6,23 @@
 #include <cstdint>
 #include <vector>
 
+#if defined(__HIPCC__)
+#define SHOT_HD __host__ __device__
+#else
+#define SHOT_HD
+#endif
+
 namespace shot {
+
+// Row-split of one order's nr = L - m rows over the four waves of a Legendre
+// workgroup: wave w handles rows [split_row(nr, w), split_row(nr, w + 1)),
+// boundaries on multiples of 16 rows.
+inline SHOT_HD int split_row(int nr, int w) {
+  const int nb16 = (nr + 15) / 16;
+  const int bpw = (nb16 + 3) / 4;
+  const int r = w * bpw * 16;
+  return r < nr ? r : nr;
+}
 
 // Gauss-Legendre nodes (descending, row 0 north) and weights (sum 2):
 // the rows of a Gauss-Legendre grid sit at the roots of P_nlat (App. C.1).
@@ -39,5 +55,13 @@ void legendre_rows(int L, const std::vector<double>& x, int ld, std::vector<doub
 // seed[m*nx + j] = P̄_m^m(x_j) (may underflow to 0 where it is negligible).
 void legendre_recurrence_data(int L, const std::vector<double>& x, std::vector<double>& coef,
                               std::vector<double>& gam, std::vector<double>& seed);
+
+// Recurrence checkpoints for the row-split kernel: for every order m, wave
+// w = 0..3 and node j, the pair (R_{r0}, R_{r0-1}) of the rescaled recurrence
+// at r0 = split_row(L - m, w), stored at ck[((m*4 + w)*nx + j)*2 + {0,1}]
+// ((0, 0) when the wave has no rows).  Evaluated with the same fused
+// multiply-adds as the device recurrence.
+void legendre_checkpoints(int L, const std::vector<double>& x, const std::vector<double>& coef,
+                          const std::vector<double>& seed, std::vector<double>& ck, int nthreads);
 
 }  // namespace shot

@@ -25,6 +25,7 @@
 
 #include <climits>
 
+#include "host_math.h"
 #include "shot_internal.h"
 
 namespace shot {
@@ -182,6 +183,13 @@ __device__ double gauge(const RowArgs<T>& A, const ItemDev& I, int it, int k, do
   return exp(-c / I.eps);
 }
 
+// Bijection of [0, h): workgroup b runs on XCD b % 8; XCD x gets the
+// contiguous row-pair range starting at x*(h/8) + min(x, h%8).
+__device__ __forceinline__ int xcd_row_pair(int b, int h) {
+  const int q = h >> 3, r = h & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // Row kernel.  grid = (h row pairs, items), block = 256.
 // ---------------------------------------------------------------------------
@@ -190,10 +198,14 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf0 = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* buf1 = buf0 + A.nlon;
+  cpx<T>* twl = buf1 + A.nlon;
   __shared__ double sh[16];
   __shared__ int sh_bad;
 
-  const int jp = blockIdx.x;
+  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+  // contiguous range of row pairs so that neighbouring rows' spectral entries
+  // (adjacent in memory) meet in the same L2.
+  const int jp = xcd_row_pair(blockIdx.x, A.h);
   const int it = A.item0 + blockIdx.y;
   const ItemDev I = A.items[it];
   const int N = A.nlon, L = A.L, h = A.h;
@@ -238,27 +250,42 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
     return;
   }
 
+  const cpx<T>* tws = A.tw;
+  if (A.tw_lds) {
+    for (int i = tid; i < N; i += bs) twl[i] = A.tw[i];
+    tws = twl;
+  }
   cpx<T>* X = buf0;
   const bool has_inverse = (mode == ROW_INV || mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK);
   if (has_inverse) {
-    for (int idx = tid; idx < N; idx += bs) {
-      cpx<T> z = {(T)0, (T)0};
-      int m = -1;
-      bool cj = false;
-      if (idx < L) m = idx;
-      else if (idx > N - L) { m = N - idx; cj = true; }
-      if (m >= 0) {
-        const cpx<T> ge = spec[(size_t)(2 * m) * h + jp];
-        const cpx<T> go = spec[(size_t)(2 * m + 1) * h + jp];
-        cpx<T> a = cadd(ge, go);
-        cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : csub(ge, go);
-        if (cj) { a.y = -a.y; b.y = -b.y; }
-        z = {a.x - b.y, a.y + b.x};  // a + i b
+    // G_j[m] = GE + GO, G_j'[m] = GE - GO; Z[m] = G_j[m] + i G_j'[m] and its
+    // Hermitian mirror Z[N-m] = conj(G_j[m]) + i conj(G_j'[m]); zero elsewhere.
+    // All spectral loads of a thread are issued before any is used.
+    constexpr int MAXK = 8;  // N <= 2048 = 8 * 256
+    cpx<T> ge[MAXK], go[MAXK];
+#pragma unroll
+    for (int q = 0; q < MAXK; ++q) {
+      const int m = tid + q * bs;
+      if (m < L) {
+        ge[q] = spec[(size_t)(2 * m) * h + jp];
+        go[q] = spec[(size_t)(2 * m + 1) * h + jp];
       }
-      buf0[idx] = z;
+    }
+    for (int idx = L + tid; idx <= N - L; idx += bs) buf0[idx] = {(T)0, (T)0};
+#pragma unroll
+    for (int q = 0; q < MAXK; ++q) {
+      const int m = tid + q * bs;
+      if (m < L) {
+        const cpx<T> a = cadd(ge[q], go[q]);
+        const cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : csub(ge[q], go[q]);
+        buf0[m] = {a.x - b.y, a.y + b.x};                       // a + i b
+        if (m > 0) buf0[N - m] = {a.x + b.y, -a.y + b.x};       // conj(a) + i conj(b)
+      }
     }
     __syncthreads();
-    X = fft_lds<T>(buf0, buf1, N, A.fac, A.nfac, A.tw, (T)1);
+    X = fft_lds<T>(buf0, buf1, N, A.fac, A.nfac, tws, (T)1);
+  } else {
+    __syncthreads();
   }
 
   if (mode == ROW_INV) {
@@ -371,7 +398,7 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
 
   // forward FFT of the rows now in X, fold, weight, store
   cpx<T>* other = (X == buf0) ? buf1 : buf0;
-  cpx<T>* Z = fft_lds<T>(X, other, N, A.fac, A.nfac, A.tw, (T)-1);
+  cpx<T>* Z = fft_lds<T>(X, other, N, A.fac, A.nfac, tws, (T)-1);
   const T cw = (mode == ROW_FWD && !A.wts_in) ? (T)1 : aj;
   for (int m = tid; m < L; m += bs) {
     const cpx<T> a = Z[m];
@@ -510,191 +537,249 @@ __global__ void __launch_bounds__(256) legendre_table_kernel(LegArgs<T> A) {
 //
 // Each thread owns JPT latitude chains j.  The recurrence is the rescaled
 // three-term form R_l = c_l x R_{l-1} + R_{l-2}, P̄_l^m = gamma_l R_l (two
-// float64 operations per value; coefficients c_l, gamma_l are precomputed on
-// the host), restarted from the seed P̄_m^m(x_j) for the synthesis pass.
-// Analysis sums over j are formed per block of RB rows: each lane accumulates
-// its chains, then a wave transpose-reduction leaves value v = lane/2 summed
-// over the wave, and the waves are combined through LDS in wave order.
+// float64 operations per value; c_l and gamma_l are precomputed on the host),
+// restarted from the seed P̄_m^m(x_j) for the synthesis pass.  Products and
+// per-lane accumulations are float64.  Analysis sums over j are formed per
+// block of RB rows: a wave transpose-reduction (permlane swaps for the two
+// upper lane bits, DPP mirrors/quad permutes below) leaves value v = lane/2
+// summed over the wave; waves are combined through LDS in wave order, one
+// barrier per block (double-buffered partials).  Coefficients and spectral
+// inputs are staged in LDS, zero-padded to whole blocks so the row loops need
+// no bounds tests.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T transpose_reduce32(T* a, int lane) {
-  // 32 live values -> 1 per lane pair; lane holds value (lane >> 1) afterwards
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const bool up = (lane & 32) != 0;
-    T send = up ? a[i] : a[16 + i];
-    T keep = up ? a[16 + i] : a[i];
-    a[i] = keep + __shfl_xor(send, 32, 64);
+__device__ __forceinline__ float dpp_f(float v, int ctrl_sel) {
+  int x = __float_as_int(v);
+  int r;
+  switch (ctrl_sel) {
+    case 0: r = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false); break;  // row_mirror (bit 3)
+    case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false); break;  // row_half_mirror (bit 2)
+    case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x4e, 0xf, 0xf, false); break;   // quad_perm [2,3,0,1] (bit 1)
+    default: r = __builtin_amdgcn_update_dpp(0, x, 0xb1, 0xf, 0xf, false); break;  // quad_perm [1,0,3,2] (bit 0)
   }
+  return __int_as_float(r);
+}
+
+__device__ __forceinline__ double dpp_d(double v, int ctrl_sel) {
+  const unsigned long long u = __double_as_longlong(v);
+  float lo = __int_as_float((int)(u & 0xffffffffull)), hi = __int_as_float((int)(u >> 32));
+  const unsigned long long rl = (unsigned)__float_as_int(dpp_f(lo, ctrl_sel));
+  const unsigned long long rh = (unsigned)__float_as_int(dpp_f(hi, ctrl_sel));
+  return __longlong_as_double((long long)(rl | (rh << 32)));
+}
+
+// new value = X(lane) + X(lane ^ 32) for lanes < 32, Y(lane ^ 32) + Y(lane) above.
+__device__ __forceinline__ float swap_add32(float X, float Y) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(X), __float_as_uint(Y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_add16(float X, float Y) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(X), __float_as_uint(Y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double swap_add32(double X, double Y) {
+  const unsigned long long x = __double_as_longlong(X), y = __double_as_longlong(Y);
+  auto lo = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
+  auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+  const double a = __longlong_as_double((long long)((unsigned long long)lo[0] | ((unsigned long long)hi[0] << 32)));
+  const double b = __longlong_as_double((long long)((unsigned long long)lo[1] | ((unsigned long long)hi[1] << 32)));
+  return a + b;
+}
+__device__ __forceinline__ double swap_add16(double X, double Y) {
+  const unsigned long long x = __double_as_longlong(X), y = __double_as_longlong(Y);
+  auto lo = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)y, false, false);
+  auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+  const double a = __longlong_as_double((long long)((unsigned long long)lo[0] | ((unsigned long long)hi[0] << 32)));
+  const double b = __longlong_as_double((long long)((unsigned long long)lo[1] | ((unsigned long long)hi[1] << 32)));
+  return a + b;
+}
+
+template <typename R>
+__device__ __forceinline__ R dpp_any(R v, int sel) {
+  if constexpr (sizeof(R) == 4) return dpp_f(v, sel);
+  else return dpp_d(v, sel);
+}
+
+// 32 values per lane -> lane L holds the wave sum of value (L >> 1).
+template <typename R>
+__device__ __forceinline__ R transpose_reduce32(R* a, int lane) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const bool up = (lane & 16) != 0;
-    T send = up ? a[i] : a[8 + i];
-    T keep = up ? a[8 + i] : a[i];
-    a[i] = keep + __shfl_xor(send, 16, 64);
-  }
+  for (int i = 0; i < 16; ++i) a[i] = swap_add32(a[i], a[16 + i]);   // lane bit 5
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const bool up = (lane & 8) != 0;
-    T send = up ? a[i] : a[4 + i];
-    T keep = up ? a[4 + i] : a[i];
-    a[i] = keep + __shfl_xor(send, 8, 64);
-  }
+  for (int i = 0; i < 8; ++i) a[i] = swap_add16(a[i], a[8 + i]);     // lane bit 4
+  {
+    const bool up = (lane & 8) != 0;                                  // lane bit 3
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const bool up = (lane & 4) != 0;
-    T send = up ? a[i] : a[2 + i];
-    T keep = up ? a[2 + i] : a[i];
-    a[i] = keep + __shfl_xor(send, 4, 64);
+    for (int i = 0; i < 4; ++i) {
+      const R send = up ? a[i] : a[4 + i];
+      const R keep = up ? a[4 + i] : a[i];
+      a[i] = keep + dpp_any(send, 0);
+    }
   }
   {
-    const bool up = (lane & 2) != 0;
-    T send = up ? a[0] : a[1];
-    T keep = up ? a[1] : a[0];
-    a[0] = keep + __shfl_xor(send, 2, 64);
+    const bool up = (lane & 4) != 0;                                  // lane bit 2
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const R send = up ? a[i] : a[2 + i];
+      const R keep = up ? a[2 + i] : a[i];
+      a[i] = keep + dpp_any(send, 1);
+    }
   }
-  a[0] += __shfl_xor(a[0], 1, 64);
+  {
+    const bool up = (lane & 2) != 0;                                  // lane bit 1
+    const R send = up ? a[0] : a[1];
+    const R keep = up ? a[1] : a[0];
+    a[0] = keep + dpp_any(send, 2);
+  }
+  a[0] += dpp_any(a[0], 3);                                           // lane bit 0
   return a[0];
 }
 
 template <typename T, int IB, int JPT>
 __global__ void __launch_bounds__(256) legendre_recur_kernel(LegArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int RB = 16 / IB;       // rows per reduction block
-  constexpr int V = 2 * RB * IB;    // 32 partial sums per lane per block
+  using R = T;                       // reduction type: float for float32 plans
+  constexpr int RB = 16 / IB;        // rows per block
+  constexpr int V = 2 * RB * IB;     // 32 partial sums per lane per block
   const int L = A.L, h = A.h;
   const int m = blockIdx.x;
   const int nr = L - m;
+  const int nblk = (nr + RB - 1) / RB;
+  const int npad = nblk * RB;
   const int ib0 = blockIdx.y * IB;
   const int nbi = min(IB, A.nb - ib0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
-  cpx<T>* bsh = reinterpret_cast<cpx<T>*>(smem_raw);   // [IB][L]
-  T* part = reinterpret_cast<T*>(bsh + (size_t)IB * L); // [nw][V]
+  // LDS: cf[npad], gm[npad] (double), b[IB][npad] (double2), part[2][nw][V] (R)
+  double* cf = reinterpret_cast<double*>(smem_raw);
+  double* gm = cf + npad;
+  double2* bs = reinterpret_cast<double2*>(gm + npad);
+  R* part = reinterpret_cast<R*>(bs + (size_t)IB * npad);
   const long long toff = tri_off(m, L);
-  const double* __restrict__ coef = A.rcoef + toff;
-  const double* __restrict__ gam = A.rgam + toff;
 
-  double xj[JPT], R1[JPT], R2[JPT];
-  cpx<T> yE[JPT][IB], yO[JPT][IB];
+  for (int r = tid; r < npad; r += nt) {
+    cf[r] = (r < nr && r > 0) ? A.rcoef[toff + r] : 0.0;
+    gm[r] = (r < nr) ? A.rgam[toff + r] : 0.0;
+  }
+  for (int i = 0; i < IB; ++i)
+    for (int r = tid; r < npad; r += nt) bs[(size_t)i * npad + r] = make_double2(0.0, 0.0);
+
+  double xj[JPT], R1[JPT], R2[JPT], seed[JPT];
+  double2 yE[JPT][IB], yO[JPT][IB];
 #pragma unroll
   for (int c = 0; c < JPT; ++c) {
     const int j = tid + c * nt;
     const bool act = j < h;
     xj[c] = act ? A.xs[j] : 0.0;
+    seed[c] = act ? A.rseed[(size_t)m * h + j] : 0.0;
 #pragma unroll
     for (int i = 0; i < IB; ++i) {
+      yE[c][i] = make_double2(0.0, 0.0);
+      yO[c][i] = make_double2(0.0, 0.0);
       if (act && i < nbi && A.mode != 2) {
         const cpx<T>* s = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
-        yE[c][i] = s[j];
-        yO[c][i] = s[h + j];
-      } else {
-        yE[c][i] = {(T)0, (T)0};
-        yO[c][i] = {(T)0, (T)0};
+        const cpx<T> e = s[j], o = s[h + j];
+        yE[c][i] = make_double2((double)e.x, (double)e.y);
+        yO[c][i] = make_double2((double)o.x, (double)o.y);
       }
     }
   }
+  __syncthreads();
 
   if (A.mode != 2) {
 #pragma unroll
-    for (int c = 0; c < JPT; ++c) {
-      const int j = tid + c * nt;
-      R1[c] = (j < h) ? A.rseed[(size_t)m * h + j] : 0.0;
-      R2[c] = 0.0;
-    }
-    for (int r0 = 0; r0 < nr; r0 += RB) {
-      T acc[V];
+    for (int c = 0; c < JPT; ++c) { R1[c] = seed[c]; R2[c] = 0.0; }
+    for (int blk = 0; blk < nblk; ++blk) {
+      const int r0 = blk * RB;
+      double acc[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[v] = (T)0;
+      for (int v = 0; v < V; ++v) acc[v] = 0.0;
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) {
-        const int r = r0 + rr;
-        if (r < nr) {
-          if (r > 0) {
-            const double cf = coef[r];
+        const double c0 = cf[r0 + rr];
 #pragma unroll
-            for (int c = 0; c < JPT; ++c) {
-              const double rn = fma(cf * xj[c], R1[c], R2[c]);
-              R2[c] = R1[c];
-              R1[c] = rn;
-            }
+        for (int c = 0; c < JPT; ++c) {
+          if (r0 + rr > 0) {
+            const double rn = fma(c0 * xj[c], R1[c], R2[c]);
+            R2[c] = R1[c];
+            R1[c] = rn;
           }
 #pragma unroll
-          for (int c = 0; c < JPT; ++c) {
-            const T pv = (T)R1[c];
-#pragma unroll
-            for (int i = 0; i < IB; ++i) {
-              const cpx<T> y = (rr & 1) ? yO[c][i] : yE[c][i];  // r0 is even, so r&1 == rr&1
-              acc[(rr * IB + i) * 2 + 0] += pv * y.x;
-              acc[(rr * IB + i) * 2 + 1] += pv * y.y;
-            }
+          for (int i = 0; i < IB; ++i) {
+            const double2 y = (rr & 1) ? yO[c][i] : yE[c][i];  // r0 is even
+            acc[(rr * IB + i) * 2 + 0] = fma(R1[c], y.x, acc[(rr * IB + i) * 2 + 0]);
+            acc[(rr * IB + i) * 2 + 1] = fma(R1[c], y.y, acc[(rr * IB + i) * 2 + 1]);
           }
         }
       }
-      const T s = transpose_reduce32<T>(acc, lane);
-      if ((lane & 1) == 0) part[wave * V + (lane >> 1)] = s;
+      R red[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) red[v] = (R)acc[v];
+      const R s = transpose_reduce32<R>(red, lane);
+      R* pb = part + (size_t)(blk & 1) * nw * V;
+      if ((lane & 1) == 0) pb[wave * V + (lane >> 1)] = s;
       __syncthreads();
       if (tid < V) {
-        T tot = (T)0;
-        for (int w = 0; w < nw; ++w) tot += part[w * V + tid];
+        double tot = 0.0;
+        for (int w = 0; w < nw; ++w) tot += (double)pb[w * V + tid];
         const int comp = tid & 1, i = (tid >> 1) % IB, rr = (tid >> 1) / IB, r = r0 + rr;
         if (r < nr && i < nbi) {
-          const double g = gam[r];
+          const double g = gm[r];
           if (A.mode == 0) {
-            const T sc = (T)(g * g) * A.hl[(size_t)(A.item0 + ib0 + i) * A.hl_stride + m + r];
-            T* dst = reinterpret_cast<T*>(&bsh[(size_t)i * L + r]);
+            const double sc = g * g * (double)A.hl[(size_t)(A.item0 + ib0 + i) * A.hl_stride + m + r];
+            double* dst = reinterpret_cast<double*>(&bs[(size_t)i * npad + r]);
             dst[comp] = tot * sc;
           } else {
             T* dst = reinterpret_cast<T*>(&A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r]);
-            dst[comp] = tot * (T)g;
+            dst[comp] = (T)(tot * g);
           }
         }
       }
-      __syncthreads();
     }
     if (A.mode == 1) return;
   } else {
     for (int i = 0; i < nbi; ++i)
-      for (int r = tid; r < nr; r += nt)
-        bsh[(size_t)i * L + r] = cscale(A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r], (T)gam[r]);
-    __syncthreads();
+      for (int r = tid; r < nr; r += nt) {
+        const cpx<T> c = A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r];
+        bs[(size_t)i * npad + r] = make_double2((double)c.x * gm[r], (double)c.y * gm[r]);
+      }
   }
+  __syncthreads();
 
-  // synthesis: G^{E|O}_m(j) = sum_l (b_l gamma_l) R_l(x_j)
-  cpx<T> gE[JPT][IB], gO[JPT][IB];
+  // synthesis: G^{E|O}_m(j) = sum_l (b_l gamma_l) R_l(x_j), rows in blocks of 16
+  double2 gE[JPT][IB], gO[JPT][IB];
 #pragma unroll
   for (int c = 0; c < JPT; ++c) {
-    const int j = tid + c * nt;
-    R1[c] = (j < h) ? A.rseed[(size_t)m * h + j] : 0.0;
+    R1[c] = seed[c];
     R2[c] = 0.0;
 #pragma unroll
-    for (int i = 0; i < IB; ++i) { gE[c][i] = {(T)0, (T)0}; gO[c][i] = {(T)0, (T)0}; }
+    for (int i = 0; i < IB; ++i) { gE[c][i] = make_double2(0.0, 0.0); gO[c][i] = make_double2(0.0, 0.0); }
   }
-  for (int r = 0; r < nr; ++r) {
-    if (r > 0) {
-      const double cf = coef[r];
+  const int nblk16 = (nr + 15) / 16;
+  for (int blk = 0; blk < nblk16; ++blk) {
+    const int r0 = blk * 16;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      const int r = r0 + rr;
+      const double c0 = (r < npad) ? cf[r] : 0.0;
+      double2 b[IB];
+#pragma unroll
+      for (int i = 0; i < IB; ++i) b[i] = (r < npad) ? bs[(size_t)i * npad + r] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int c = 0; c < JPT; ++c) {
-        const double rn = fma(cf * xj[c], R1[c], R2[c]);
-        R2[c] = R1[c];
-        R1[c] = rn;
-      }
-    }
-    cpx<T> b[IB];
+        if (r > 0) {
+          const double rn = fma(c0 * xj[c], R1[c], R2[c]);
+          R2[c] = R1[c];
+          R1[c] = rn;
+        }
 #pragma unroll
-    for (int i = 0; i < IB; ++i) b[i] = bsh[(size_t)i * L + r];
-    if (r & 1) {
-#pragma unroll
-      for (int c = 0; c < JPT; ++c) {
-        const T pv = (T)R1[c];
-#pragma unroll
-        for (int i = 0; i < IB; ++i) { gO[c][i].x += pv * b[i].x; gO[c][i].y += pv * b[i].y; }
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < JPT; ++c) {
-        const T pv = (T)R1[c];
-#pragma unroll
-        for (int i = 0; i < IB; ++i) { gE[c][i].x += pv * b[i].x; gE[c][i].y += pv * b[i].y; }
+        for (int i = 0; i < IB; ++i) {
+          if (rr & 1) {
+            gO[c][i].x = fma(R1[c], b[i].x, gO[c][i].x);
+            gO[c][i].y = fma(R1[c], b[i].y, gO[c][i].y);
+          } else {
+            gE[c][i].x = fma(R1[c], b[i].x, gE[c][i].x);
+            gE[c][i].y = fma(R1[c], b[i].y, gE[c][i].y);
+          }
+        }
       }
     }
   }
@@ -706,8 +791,188 @@ __global__ void __launch_bounds__(256) legendre_recur_kernel(LegArgs<T> A) {
     for (int i = 0; i < IB; ++i) {
       if (i >= nbi) continue;
       cpx<T>* dst = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
-      dst[j] = gE[c][i];
-      dst[h + j] = gO[c][i];
+      dst[j] = {(T)gE[c][i].x, (T)gE[c][i].y};
+      dst[h + j] = {(T)gO[c][i].x, (T)gO[c][i].y};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row-split recurrence Legendre kernel.
+//
+// One workgroup (4 waves) per order m and item chunk.  Every lane owns the C
+// latitude chains j = lane + 64 c, and the rows l = m..L-1 are split into
+// four contiguous ranges, one per wave.  A wave resumes the rescaled
+// recurrence at the start of its range from a plan-time checkpoint
+// (R_{r0}, R_{r0-1}) per (m, wave, j): 4 states per (m, j), i.e. O(n) memory.
+// Analysis sums over j are complete within a wave (C chains per lane, then a
+// wave transpose-reduction), so the analysis loop has no barrier; synthesis
+// partial sums of the four waves are combined once through LDS.
+// ---------------------------------------------------------------------------
+
+template <typename T, int IB, int C>
+__global__ void __launch_bounds__(256) legendre_split_kernel(LegArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using R = T;
+  constexpr int RB = 16 / IB;
+  constexpr int V = 2 * RB * IB;
+  const int L = A.L, h = A.h;
+  const int m = blockIdx.x;
+  const int nr = L - m;
+  const int npad = (nr + 15) / 16 * 16 + 16;  // one extra block: the look-ahead coefficient
+  const int ib0 = blockIdx.y * IB;
+  const int nbi = min(IB, A.nb - ib0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* cf = reinterpret_cast<double*>(smem_raw);
+  double* gm = cf + npad;
+  double2* bs = reinterpret_cast<double2*>(gm + npad);               // [IB][npad]
+  cpx<T>* gpart = reinterpret_cast<cpx<T>*>(bs + (size_t)IB * npad);  // [4][IB][2][h]
+  const long long toff = tri_off(m, L);
+  const int r_lo = split_row(nr, wave), r_hi = split_row(nr, wave + 1);
+
+  for (int r = tid; r < npad; r += 256) {
+    cf[r] = (r < nr && r > 0) ? A.rcoef[toff + r] : 0.0;
+    gm[r] = (r < nr) ? A.rgam[toff + r] : 0.0;
+  }
+  for (int i = 0; i < IB; ++i)
+    for (int r = tid; r < npad; r += 256) bs[(size_t)i * npad + r] = make_double2(0.0, 0.0);
+
+  double xj[C];
+  double2 ck[C];
+  const double2* ckp = reinterpret_cast<const double2*>(A.rck) + ((size_t)m * 4 + wave) * h;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int j = lane + 64 * c;
+    const bool act = j < h;
+    xj[c] = act ? A.xs[j] : 0.0;
+    ck[c] = act ? ckp[j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+
+  if (A.mode != 2) {
+    double2 yE[C][IB], yO[C][IB];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = lane + 64 * c;
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        yE[c][i] = make_double2(0.0, 0.0);
+        yO[c][i] = make_double2(0.0, 0.0);
+        if (j < h && i < nbi) {
+          const cpx<T>* s = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+          const cpx<T> e = s[j], o = s[h + j];
+          yE[c][i] = make_double2((double)e.x, (double)e.y);
+          yO[c][i] = make_double2((double)o.x, (double)o.y);
+        }
+      }
+    }
+    double R1[C], R2[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) { R1[c] = ck[c].x; R2[c] = ck[c].y; }
+    for (int r0 = r_lo; r0 < r_hi; r0 += RB) {
+      double acc[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = 0.0;
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const double cn = cf[r0 + rr + 1];  // coefficient of the next row
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+          for (int i = 0; i < IB; ++i) {
+            const double2 y = (rr & 1) ? yO[c][i] : yE[c][i];  // r0 - r_lo is even and r_lo is even
+            acc[(rr * IB + i) * 2 + 0] = fma(R1[c], y.x, acc[(rr * IB + i) * 2 + 0]);
+            acc[(rr * IB + i) * 2 + 1] = fma(R1[c], y.y, acc[(rr * IB + i) * 2 + 1]);
+          }
+          const double rn = fma(cn * xj[c], R1[c], R2[c]);
+          R2[c] = R1[c];
+          R1[c] = rn;
+        }
+      }
+      R red[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) red[v] = (R)acc[v];
+      const R s = transpose_reduce32<R>(red, lane);
+      if ((lane & 1) == 0) {
+        const int vv = lane >> 1, comp = vv & 1, i = (vv >> 1) % IB, rr = (vv >> 1) / IB, r = r0 + rr;
+        if (r < nr && i < nbi) {
+          const double g = gm[r];
+          if (A.mode == 0) {
+            const double sc = g * g * (double)A.hl[(size_t)(A.item0 + ib0 + i) * A.hl_stride + m + r];
+            reinterpret_cast<double*>(&bs[(size_t)i * npad + r])[comp] = (double)s * sc;
+          } else {
+            T* dst = reinterpret_cast<T*>(&A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r]);
+            dst[comp] = (T)((double)s * g);
+          }
+        }
+      }
+    }
+    if (A.mode == 1) return;
+  } else {
+    for (int i = 0; i < nbi; ++i)
+      for (int r = tid; r < nr; r += 256) {
+        const cpx<T> c = A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r];
+        bs[(size_t)i * npad + r] = make_double2((double)c.x * gm[r], (double)c.y * gm[r]);
+      }
+  }
+  __syncthreads();
+
+  // synthesis over this wave's rows: G^{E|O}_m(j) += (b_l gamma_l) R_l(x_j)
+  double2 gE[C][IB], gO[C][IB];
+  double R1[C], R2[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    R1[c] = ck[c].x;
+    R2[c] = ck[c].y;
+#pragma unroll
+    for (int i = 0; i < IB; ++i) { gE[c][i] = make_double2(0.0, 0.0); gO[c][i] = make_double2(0.0, 0.0); }
+  }
+  for (int r0 = r_lo; r0 < r_hi; r0 += 16) {
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      const int r = r0 + rr;
+      const double cn = cf[r + 1];
+      double2 b[IB];
+#pragma unroll
+      for (int i = 0; i < IB; ++i) b[i] = bs[(size_t)i * npad + r];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int i = 0; i < IB; ++i) {
+          if (rr & 1) {
+            gO[c][i].x = fma(R1[c], b[i].x, gO[c][i].x);
+            gO[c][i].y = fma(R1[c], b[i].y, gO[c][i].y);
+          } else {
+            gE[c][i].x = fma(R1[c], b[i].x, gE[c][i].x);
+            gE[c][i].y = fma(R1[c], b[i].y, gE[c][i].y);
+          }
+        }
+        const double rn = fma(cn * xj[c], R1[c], R2[c]);
+        R2[c] = R1[c];
+        R1[c] = rn;
+      }
+    }
+  }
+  // combine the four waves' partial sums (fixed order)
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int j = lane + 64 * c;
+    if (j >= h) continue;
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      cpx<T>* gp = gpart + (((size_t)wave * IB + i) * 2) * h;
+      gp[j] = {(T)gE[c][i].x, (T)gE[c][i].y};
+      gp[h + j] = {(T)gO[c][i].x, (T)gO[c][i].y};
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < nbi; ++i) {
+    cpx<T>* dst = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+    for (int q = tid; q < 2 * h; q += 256) {
+      cpx<T> s = {(T)0, (T)0};
+#pragma unroll
+      for (int w = 0; w < 4; ++w) s = cadd(s, gpart[(((size_t)w * IB + i) * 2) * h + q]);
+      dst[q] = s;
     }
   }
 }
@@ -753,8 +1018,11 @@ __global__ void __launch_bounds__(256) reduce_kernel(RowArgs<T> A, int nchk_done
 template <typename T>
 hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream) {
   dim3 grid(a.h, nb);
-  const size_t lds = (size_t)2 * a.nlon * sizeof(cpx<T>);
-  hipLaunchKernelGGL(row_kernel<T>, grid, dim3(256), lds, stream, a);
+  RowArgs<T> b = a;
+  // two FFT buffers, plus the twiddles when they fit in 64 KiB of LDS
+  b.tw_lds = (size_t)3 * a.nlon * sizeof(cpx<T>) <= 65536 - 512 ? 1 : 0;
+  const size_t lds = (size_t)(b.tw_lds ? 3 : 2) * a.nlon * sizeof(cpx<T>);
+  hipLaunchKernelGGL(row_kernel<T>, grid, dim3(256), lds, stream, b);
   return hipGetLastError();
 }
 
@@ -780,7 +1048,8 @@ template <typename T, int IB, int JPT>
 static hipError_t launch_recur(const LegArgs<T>& a, hipStream_t stream) {
   const int threads = ((a.h + JPT - 1) / JPT + 63) / 64 * 64;
   dim3 grid(a.L, (a.nb + IB - 1) / IB);
-  const size_t lds = (size_t)IB * a.L * sizeof(cpx<T>) + (size_t)(threads / 64) * 32 * sizeof(T);
+  const int npad = (a.L + 15) / 16 * 16;
+  const size_t lds = (size_t)npad * 16 + (size_t)IB * npad * 16 + (size_t)2 * (threads / 64) * 32 * sizeof(T);
   hipLaunchKernelGGL((legendre_recur_kernel<T, IB, JPT>), grid, dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
@@ -797,6 +1066,44 @@ static hipError_t launch_recur_ib(const LegArgs<T>& a, int jpt, hipStream_t stre
 // Chains per thread for the recurrence kernel: the fewest that keep the
 // block at <= 256 threads.
 int recur_jpt(int h) { return h <= 256 ? 1 : (h <= 512 ? 2 : 4); }
+int recur_jpt_valid(int h, int jpt) {
+  return (jpt == 1 || jpt == 2 || jpt == 4) && (h + jpt - 1) / jpt <= 256;
+}
+
+template <typename T, int IB, int C>
+static hipError_t launch_split(const LegArgs<T>& a, hipStream_t stream) {
+  dim3 grid(a.L, (a.nb + IB - 1) / IB);
+  const size_t npad = (a.L + 15) / 16 * 16 + 16;
+  const size_t lds = npad * 16 + (size_t)IB * npad * 16 + (size_t)4 * IB * 2 * a.h * sizeof(cpx<T>);
+  hipLaunchKernelGGL((legendre_split_kernel<T, IB, C>), grid, dim3(256), lds, stream, a);
+  return hipGetLastError();
+}
+
+template <typename T, int IB>
+static hipError_t launch_split_ib(const LegArgs<T>& a, hipStream_t stream) {
+  switch ((a.h + 63) / 64) {
+    case 1: return launch_split<T, IB, 1>(a, stream);
+    case 2: return launch_split<T, IB, 2>(a, stream);
+    case 3: return launch_split<T, IB, 3>(a, stream);
+    case 4: return launch_split<T, IB, 4>(a, stream);
+    case 5: return launch_split<T, IB, 5>(a, stream);
+    case 6: return launch_split<T, IB, 6>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t split_lds_bytes(int L, int h, int ib, int real_bytes) {
+  const size_t npad = (L + 15) / 16 * 16 + 16;
+  return npad * 16 + (size_t)ib * npad * 16 + (size_t)4 * ib * 2 * h * 2 * real_bytes;
+}
+
+template <typename T>
+hipError_t launch_legendre_split(const LegArgs<T>& a, int ib, hipStream_t stream) {
+  if (a.h > 384) return hipErrorInvalidValue;
+  return ib >= 2 ? launch_split_ib<T, 2>(a, stream) : launch_split_ib<T, 1>(a, stream);
+}
+template hipError_t launch_legendre_split<float>(const LegArgs<float>&, int, hipStream_t);
+template hipError_t launch_legendre_split<double>(const LegArgs<double>&, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_legendre(const LegArgs<T>& a, int table_kind, int ib, hipStream_t stream) {
@@ -806,7 +1113,7 @@ hipError_t launch_legendre(const LegArgs<T>& a, int table_kind, int ib, hipStrea
     case TAB_BF16: return launch_leg_tt<T, unsigned short>(a, ib, stream);
     case TAB_RECUR: {
       if (a.h > 1024) return hipErrorInvalidValue;
-      const int jpt = recur_jpt(a.h);
+      const int jpt = recur_jpt_valid(a.h, a.jpt) ? a.jpt : recur_jpt(a.h);
       switch (ib) {
         case 1: return launch_recur_ib<T, 1>(a, jpt, stream);
         case 2: return launch_recur_ib<T, 2>(a, jpt, stream);

@@ -49,6 +49,7 @@ struct RowArgs {
   int nfac;
   int fac[8];
   const cpx<T>* tw;   // nlon forward twiddles exp(-2 pi i k / nlon)
+  int tw_lds;         // set by the launcher: stage the twiddles in LDS
   const T* aw;        // h area weights (rows 0..h-1)
   int item0;          // absolute index of this launch's first item
   const ItemDev* items;
@@ -85,12 +86,14 @@ struct LegArgs {
   const double* rcoef;    // [L(L+1)/2]
   const double* rgam;     // [L(L+1)/2]
   const double* rseed;    // [L][h]
+  const double* rck;      // [L][4][h][2] recurrence checkpoints (row-split kernel)
   int item0, nb;
   const ItemDev* items;
   cpx<T>* spec;
   const T* hl;            // [nitems][hl_stride] heat multipliers (by absolute item index)
   int hl_stride;
   int mode;               // 0 fused (analysis, x h, synthesis), 1 analysis -> coeff, 2 coeff -> synthesis
+  int jpt;                // RECURRENCE mode: latitude chains per thread (0 = automatic)
   cpx<T>* coeff;          // packed (m, l) coefficients, item offsets ItemDev::coff (modes 1, 2)
 };
 
@@ -99,6 +102,12 @@ template <typename T>
 hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream);
 template <typename T>
 hipError_t launch_legendre(const LegArgs<T>& a, int table_kind, int ib, hipStream_t stream);
+int recur_jpt(int h);
+int recur_jpt_valid(int h, int jpt);
+size_t split_lds_bytes(int L, int h, int ib, int real_bytes);
+template <typename T>
+hipError_t launch_legendre_split(const LegArgs<T>& a, int ib, hipStream_t stream);
+
 template <typename T>
 hipError_t launch_reduce(const RowArgs<T>& a, int nb, int nchk_done, double* res, double* ehist,
                          hipStream_t stream);
