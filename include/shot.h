@@ -95,6 +95,9 @@ typedef struct {
   int32_t status;         /* shot_status of this item                                 */
   int32_t breakdown_iter; /* first iteration with K. <= 0 or non-finite, 0 if none     */
   int32_t reserved;
+  double kratio;          /* min over the iterations' heat applies of min(K.)/max(K.),
+                             -inf once an output was non-finite: how close the run came
+                             to the positivity breakdown of App. C.4                  */
 } shot_solve_info;
 
 /* Build a plan for `ngrids` grids (host array).  Computes the float64

@@ -57,7 +57,7 @@ class Params(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("cost", ctypes.c_double), ("err", ctypes.c_double), ("iters", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("breakdown_iter", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("kratio", ctypes.c_double)]
 
 
 class ShotError(RuntimeError):
@@ -280,7 +280,7 @@ class Plan:
     @staticmethod
     def _info_dicts(info, n):
         return [dict(cost=info[i].cost, err=info[i].err, iters=info[i].iters, status=info[i].status,
-                     breakdown_iter=info[i].breakdown_iter) for i in range(n)]
+                     breakdown_iter=info[i].breakdown_iter, kratio=info[i].kratio) for i in range(n)]
 
     def sinkhorn(self, p, q, eps, tau=math.inf, T=100, C=10, tol=0.0, grid_of_item=None,
                  potentials=True):

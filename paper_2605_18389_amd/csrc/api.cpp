@@ -62,6 +62,7 @@ struct shot_plan_s {
   int dev = 0;
   std::vector<GridRec> grids;
   DevBuf ws;  // call workspace arena (grown on demand)
+  DevBuf ws2; // gradient workspace arena (adjoint history, checkpoints, accumulators)
   bool prof = false;
   std::vector<Timed> timed;
   std::vector<hipEvent_t> evpool;
@@ -301,6 +302,7 @@ struct Work {
   double* res = nullptr;
   double* ehist = nullptr;
   int* brk = nullptr;
+  double* kr = nullptr;
   int nslot = 0;
 };
 
@@ -311,18 +313,20 @@ shot_status carve(shot_plan_s* P, const Layout& Lo, int nitems, bool sinkhorn, i
   const size_t o_items = take(sizeof(ItemDev) * nitems);
   const size_t o_spec = take(sizeof(cpx<T>) * Lo.spec_total);
   const size_t o_hl = take(sizeof(T) * (size_t)nitems * Lo.Lmax);
-  size_t o_u0 = 0, o_u1 = 0, o_v0 = 0, o_v1 = 0, o_red = 0, o_rh = 0, o_prep = 0, o_res = 0, o_eh = 0, o_brk = 0;
+  size_t o_u0 = 0, o_u1 = 0, o_v0 = 0, o_v1 = 0, o_red = 0, o_rh = 0, o_prep = 0, o_res = 0, o_eh = 0, o_brk = 0,
+         o_kr = 0;
   if (sinkhorn) {
     o_u0 = take(sizeof(T) * Lo.field_total);
     o_u1 = take(sizeof(T) * Lo.field_total);
     o_v0 = take(sizeof(T) * Lo.field_total);
     o_v1 = take(sizeof(T) * Lo.field_total);
-    o_red = take(sizeof(double) * 2 * (size_t)nitems * Lo.hs * 4);
+    o_red = take(sizeof(double) * 2 * (size_t)nitems * Lo.hs * RED_SLOTS);
     o_rh = take(sizeof(double) * (size_t)nitems * nslot * Lo.hs);
     o_prep = take(sizeof(double) * (size_t)nitems * Lo.hs * 4);
     o_res = take(sizeof(double) * (size_t)nitems * 8);
     o_eh = take(sizeof(double) * (size_t)nitems * nslot);
     o_brk = take(sizeof(int) * (size_t)nitems);
+    o_kr = take(sizeof(double) * (size_t)nitems);
   }
   shot_status st = grow(P->ws, off);
   if (st != SHOT_OK) return st;
@@ -341,8 +345,20 @@ shot_status carve(shot_plan_s* P, const Layout& Lo, int nitems, bool sinkhorn, i
     W.res = reinterpret_cast<double*>(b + o_res);
     W.ehist = reinterpret_cast<double*>(b + o_eh);
     W.brk = reinterpret_cast<int*>(b + o_brk);
+    W.kr = reinterpret_cast<double*>(b + o_kr);
     W.nslot = nslot;
   }
+  return SHOT_OK;
+}
+
+// Per-call status arrays: no breakdown yet, kernel ratio +inf.
+template <typename T>
+shot_status init_status(Work<T>& W, int nitems, hipStream_t s) {
+  std::vector<int> brk0(nitems, INT_MAX);
+  std::vector<double> kr0(nitems, INFINITY);
+  HIP_TRY(hipMemcpyAsync(W.brk, brk0.data(), sizeof(int) * nitems, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(W.kr, kr0.data(), sizeof(double) * nitems, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return SHOT_OK;
 }
 
@@ -410,6 +426,7 @@ RowArgs<T> row_args(const GridRec& g, const Layout& Lo, const Group& G, const Wo
   a.chk_slot = -1;
   a.prep = W.prep;
   a.brk = W.brk;
+  a.kr = W.kr;
   return a;
 }
 
@@ -596,11 +613,7 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
     tv[i] = S.prm[i].eps / 4.0;  // t = eps/4 (Alg. 1)
   }
   ST_TRY(upload_items<T>(P, Lo, S.grid.data(), eps, tau, tv, S.p, S.q, W, s));
-  {
-    std::vector<int> brk0(nitems, INT_MAX);
-    HIP_TRY(hipMemcpyAsync(W.brk, brk0.data(), sizeof(int) * nitems, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  }
+  ST_TRY(init_status(W, nitems, s));
 
   auto each_group = [&](auto&& fn) -> shot_status {
     for (const Group& G : Lo.groups) {
@@ -671,10 +684,11 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
     a.chk_slot = final_slot;
     HIP_TRY(launch_reduce<T>(a, G.count, nchk_done, W.res, W.ehist, s));
   }
-  std::vector<double> res((size_t)nitems * 8);
+  std::vector<double> res((size_t)nitems * 8), kr(nitems);
   std::vector<int> brk(nitems);
   HIP_TRY(hipMemcpyAsync(res.data(), W.res, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(brk.data(), W.brk, sizeof(int) * nitems, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(kr.data(), W.kr, sizeof(double) * nitems, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int si = 0; si < nitems; ++si) {
     const int ui = Lo.order[si];
@@ -683,6 +697,7 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
     I.err = res[(size_t)si * 8 + 1];
     I.iters = K;
     I.breakdown_iter = brk[si] == INT_MAX ? 0 : brk[si];
+    I.kratio = kr[si];
     if (mass_out) {
       mass_out[2 * ui] = res[(size_t)si * 8 + 2];
       mass_out[2 * ui + 1] = res[(size_t)si * 8 + 3];
@@ -779,6 +794,318 @@ void combine_divergence(const shot_params* prm, int npairs, const shot_solve_inf
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Reverse-mode gradient of balanced Alg. 1 (see the adjoint notes in
+// kernels.hip).  Items are advanced in lock step.  The forward sweep keeps
+// v-hat_k and s_k every CK iterations; the reverse sweep recomputes each
+// segment of CK iterations from its checkpoint (storing u-hat, v-hat and s
+// for that segment only) and then walks it backwards.  Outputs p-bar and
+// q-bar (gradients of each item's Alg. 1 cost with respect to its p and q).
+// ---------------------------------------------------------------------------
+template <typename T>
+shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_out, T** qbar_out,
+                         Layout& Lo, hipStream_t s) {
+  const int nitems = (int)S.grid.size();
+  ST_TRY(make_layout(P, S.grid.data(), nitems, Lo));
+  const int Tit = S.prm[0].max_iter;
+  for (int i = 0; i < nitems; ++i) {
+    ST_TRY(check_params(S.prm[i]));
+    if (!std::isinf(S.prm[i].tau) || S.prm[i].tol != 0 || S.prm[i].max_iter != Tit) return SHOT_E_UNSUPPORTED;
+  }
+  if (CK <= 0) CK = (int)std::ceil(std::sqrt((double)Tit));
+  CK = std::min(CK, Tit);
+  const int nck = (Tit - 1) / CK;  // checkpoints at k = CK, 2CK, ... < T
+  Work<T> W;
+  ST_TRY(carve<T>(P, Lo, nitems, true, 1, W));
+  std::vector<double> eps(nitems), tau(nitems), tv(nitems);
+  for (int i = 0; i < nitems; ++i) {
+    eps[i] = S.prm[i].eps;
+    tau[i] = S.prm[i].tau;
+    tv[i] = S.prm[i].eps / 4.0;
+  }
+  ST_TRY(upload_items<T>(P, Lo, S.grid.data(), eps, tau, tv, S.p, S.q, W, s));
+  ST_TRY(init_status(W, nitems, s));
+  // gradient arena
+  const size_t F = (size_t)Lo.field_total;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  const size_t o_specA = take(sizeof(cpx<T>) * Lo.spec_total);
+  const size_t o_gA = take(sizeof(T) * F), o_gB = take(sizeof(T) * F);
+  const size_t o_hu = take(sizeof(T) * F * CK), o_hv = take(sizeof(T) * F * CK);
+  const size_t o_ckv = take(sizeof(T) * F * std::max(nck, 1));
+  const size_t o_gh = take(sizeof(double) * nitems * (CK + 1));
+  const size_t o_ckg = take(sizeof(double) * nitems * std::max(nck, 1));
+  const size_t o_adjp = take(sizeof(double) * nitems * Lo.hs);
+  ST_TRY(grow(P->ws2, off));
+  char* b = static_cast<char*>(P->ws2.p);
+  cpx<T>* specA = reinterpret_cast<cpx<T>*>(b + o_specA);
+  T* gA = reinterpret_cast<T*>(b + o_gA);
+  T* gB = reinterpret_cast<T*>(b + o_gB);
+  T* hu = reinterpret_cast<T*>(b + o_hu);
+  T* hv = reinterpret_cast<T*>(b + o_hv);
+  T* ckv = reinterpret_cast<T*>(b + o_ckv);
+  double* gh = reinterpret_cast<double*>(b + o_gh);
+  double* ckg = reinterpret_cast<double*>(b + o_ckg);
+  double* adjp = reinterpret_cast<double*>(b + o_adjp);
+
+  auto base_args = [&](const Group& G, const GridRec& g) {
+    RowArgs<T> a = row_args<T>(g, Lo, G, W, nitems);
+    a.gA = gA;
+    a.gB = gB;
+    a.adjp = adjp;
+    a.kT = Tit;
+    return a;
+  };
+  auto each = [&](auto&& fn) -> shot_status {
+    for (const Group& G : Lo.groups) {
+      shot_status st = fn(G, P->grids[G.grid]);
+      if (st != SHOT_OK) return st;
+    }
+    return SHOT_OK;
+  };
+  auto leg = [&](const Group& G, const GridRec& g, cpx<T>* spec) {
+    LegArgs<T> la = leg_args<T>(g, G, W, Lo.Lmax);
+    la.spec = spec;
+    return run_leg<T>(P, g, la, s);
+  };
+  // ---- forward sweep with checkpoints of (v-hat_k, s_k) at k = CK, 2CK, ...
+  ST_TRY(each([&](const Group& G, const GridRec& g) {
+    RowArgs<T> a = base_args(G, g);
+    a.mode = ROW_INIT;
+    return run_rows<T>(P, a, G.count, s);
+  }));
+  for (int k = 1; k <= Tit; ++k) {
+    ST_TRY(each([&](const Group& G, const GridRec& g) {
+      shot_status st = leg(G, g, W.spec);
+      if (st != SHOT_OK) return st;
+      RowArgs<T> a = base_args(G, g);
+      a.mode = ROW_SINK_U;
+      a.k = k;
+      return run_rows<T>(P, a, G.count, s);
+    }));
+    ST_TRY(each([&](const Group& G, const GridRec& g) {
+      shot_status st = leg(G, g, W.spec);
+      if (st != SHOT_OK) return st;
+      RowArgs<T> a = base_args(G, g);
+      a.mode = ROW_SINK_V;
+      a.k = k;
+      return run_rows<T>(P, a, G.count, s);
+    }));
+    if (k % CK == 0 && k < Tit) {
+      const int c = k / CK - 1;
+      HIP_TRY(hipMemcpyAsync(ckv + F * c, W.vbuf[k & 1], sizeof(T) * F, hipMemcpyDeviceToDevice, s));
+      for (const Group& G : Lo.groups) {
+        RowArgs<T> a = base_args(G, P->grids[G.grid]);
+        HIP_TRY(launch_gauge<T>(a, G.count, k, ckg + (size_t)c * nitems, s));
+      }
+    }
+  }
+  // ---- reverse sweep, one segment at a time
+  bool started = false;
+  for (int seg = nck; seg >= 0; --seg) {
+    const int k0 = seg * CK;                 // state after iteration k0 is the checkpoint
+    const int k1 = std::min(k0 + CK, Tit);
+    // recompute iterations k0+1..k1, keeping u-hat, v-hat and s of each
+    ST_TRY(each([&](const Group& G, const GridRec& g) {
+      RowArgs<T> a = base_args(G, g);
+      if (k0 == 0) {
+        a.mode = ROW_INIT;
+      } else {
+        a.mode = ROW_FWD;
+        a.in = ckv + F * (size_t)(seg - 1);
+        a.wts_in = 1;
+      }
+      return run_rows<T>(P, a, G.count, s);
+    }));
+    for (int k = k0 + 1; k <= k1; ++k) {
+      const int slot = k - k0 - 1;
+      ST_TRY(each([&](const Group& G, const GridRec& g) {
+        shot_status st = leg(G, g, W.spec);
+        if (st != SHOT_OK) return st;
+        RowArgs<T> a = base_args(G, g);
+        a.mode = ROW_SINK_U;
+        a.k = k;
+        a.ubuf0 = a.ubuf1 = hu + F * slot;
+        if (k == k0 + 1 && k0 > 0) a.gk = ckg + (size_t)(seg - 1) * nitems;
+        return run_rows<T>(P, a, G.count, s);
+      }));
+      for (const Group& G : Lo.groups) {
+        RowArgs<T> a = base_args(G, P->grids[G.grid]);
+        HIP_TRY(launch_gauge<T>(a, G.count, k, gh + (size_t)slot * nitems, s));
+      }
+      ST_TRY(each([&](const Group& G, const GridRec& g) {
+        shot_status st = leg(G, g, W.spec);
+        if (st != SHOT_OK) return st;
+        RowArgs<T> a = base_args(G, g);
+        a.mode = ROW_SINK_V;
+        a.k = k;
+        a.vbuf0 = a.vbuf1 = hv + F * slot;
+        return run_rows<T>(P, a, G.count, s);
+      }));
+    }
+    // walk the segment backwards
+    for (int k = k1; k > k0; --k) {
+      const int slot = k - k0 - 1;
+      if (!started) {
+        ST_TRY(each([&](const Group& G, const GridRec& g) {
+          RowArgs<T> a = base_args(G, g);
+          a.mode = ROW_ADJ_START;
+          a.k = k;
+          a.spec = specA;
+          a.ubuf0 = a.ubuf1 = hu + F * slot;
+          a.vbuf0 = a.vbuf1 = hv + F * slot;
+          a.gk = gh + (size_t)slot * nitems;
+          return run_rows<T>(P, a, G.count, s);
+        }));
+        started = true;
+      }
+      ST_TRY(each([&](const Group& G, const GridRec& g) {
+        shot_status st = leg(G, g, specA);
+        if (st != SHOT_OK) return st;
+        RowArgs<T> a = base_args(G, g);
+        a.mode = ROW_ADJ_A;
+        a.k = k;
+        a.spec = specA;
+        a.ubuf0 = a.ubuf1 = hu + F * slot;
+        a.gk = gh + (size_t)slot * nitems;
+        return run_rows<T>(P, a, G.count, s);
+      }));
+      if (k == 1) break;
+      ST_TRY(each([&](const Group& G, const GridRec& g) {
+        shot_status st = leg(G, g, specA);
+        if (st != SHOT_OK) return st;
+        RowArgs<T> a = base_args(G, g);
+        a.mode = ROW_ADJ_VB;
+        a.k = k;
+        a.spec = specA;
+        if (k - 1 > k0) {
+          a.vbuf0 = a.vbuf1 = hv + F * (slot - 1);
+          a.gk = gh + (size_t)(slot - 1) * nitems;
+        } else {  // iteration k0: the checkpoint
+          a.vbuf0 = a.vbuf1 = ckv + F * (size_t)(seg - 1);
+          a.gk = ckg + (size_t)(seg - 1) * nitems;
+        }
+        return run_rows<T>(P, a, G.count, s);
+      }));
+    }
+  }
+  *pbar_out = gA;
+  *qbar_out = gB;
+  return SHOT_OK;
+}
+
+// Combine per-item fields into per-pair gradients on the device.
+template <typename T>
+shot_status combine_pairs(shot_plan_s* P, const std::vector<CombineDev>& dv, T* out, hipStream_t s) {
+  if (dv.empty()) return SHOT_OK;
+  long long maxn = 0;
+  for (const auto& d : dv) maxn = std::max(maxn, (long long)d.nlat * d.nlon);
+  void* dd = nullptr;
+  HIP_TRY(hipMalloc(&dd, sizeof(CombineDev) * dv.size()));
+  hipError_t e = hipMemcpyAsync(dd, dv.data(), sizeof(CombineDev) * dv.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_combine<T>(static_cast<CombineDev*>(dd), (int)dv.size(), maxn, out, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dd);
+  if (e != hipSuccess) return hip_fail(e, "gradient combine", __LINE__);
+  (void)P;
+  return SHOT_OK;
+}
+
+template <typename T>
+shot_status divergence_grad_impl(shot_plan_s* P, const int32_t* gop, int npairs, const shot_params* params,
+                                 const void* p, const void* q, double* S_out, T* dS, int mode, int CK,
+                                 shot_solve_info* info, hipStream_t s) {
+  Layout Lp;
+  ST_TRY(make_layout(P, gop, npairs, Lp));
+  for (int i = 0; i < npairs; ++i) {
+    ST_TRY(check_params(params[i]));
+    if (!std::isinf(params[i].tau) || params[i].tol != 0) return SHOT_E_UNSUPPORTED;
+  }
+  const T* pb = static_cast<const T*>(p);
+  const T* qb = static_cast<const T*>(q);
+  // forward divergence: three solves per pair (potentials kept for the envelope form)
+  SolveSpec S3;
+  for (int i = 0; i < npairs; ++i) {
+    const T* pi = pb + Lp.user_foff[i];
+    const T* qi = qb + Lp.user_foff[i];
+    const void* ps[3] = {pi, pi, qi};
+    const void* qs[3] = {qi, pi, qi};
+    for (int r = 0; r < 3; ++r) {
+      S3.grid.push_back(gop[i]);
+      S3.prm.push_back(params[i]);
+      S3.p.push_back(ps[r]);
+      S3.q.push_back(qs[r]);
+    }
+  }
+  std::vector<shot_solve_info> inf(3 * (size_t)npairs);
+  std::vector<double> mass(6 * (size_t)npairs);
+  Layout L3;
+  ST_TRY(make_layout(P, S3.grid.data(), 3 * npairs, L3));
+  T* phi3 = nullptr;
+  T* psi3 = nullptr;
+  if (mode == 1) {
+    const size_t F3 = (size_t)L3.field_total;
+    ST_TRY(grow(P->ws2, 2 * F3 * sizeof(T)));
+    phi3 = static_cast<T*>(P->ws2.p);
+    psi3 = phi3 + F3;
+  }
+  ST_TRY(solve_impl<T>(P, S3, phi3, psi3, inf.data(), mass.data(), s));
+  combine_divergence(params, npairs, inf.data(), mass.data(), S_out);
+  if (info) std::copy(inf.begin(), inf.end(), info);
+  std::vector<CombineDev> dv(npairs);
+  if (mode == 1) {
+    for (int i = 0; i < npairs; ++i) {
+      const GridRec& g = P->grids[gop[i]];
+      CombineDev& d = dv[i];
+      d.off_out = Lp.user_foff[i];
+      d.off1 = L3.user_foff[3 * i];      // phi_pq
+      d.off2 = L3.user_foff[3 * i + 1];  // phi_pp
+      d.off3 = L3.user_foff[3 * i + 1];  // psi_pp
+      d.x1 = phi3;
+      d.x2 = phi3;
+      d.x3 = psi3;
+      d.mul_area = 1;
+      d.coef = params[i].eps * (mass[6 * i] - mass[6 * i + 1]);
+      d.nlat = g.d.nlat;
+      d.nlon = g.d.nlon;
+      d.h = g.h;
+      d.aw = g.d_aw;
+    }
+    return combine_pairs<T>(P, dv, dS, s);
+  }
+  // unrolled: reverse sweeps of the (p,q) and (p,p) solves
+  SolveSpec S2;
+  for (int i = 0; i < npairs; ++i)
+    for (int r = 0; r < 2; ++r) {
+      S2.grid.push_back(gop[i]);
+      S2.prm.push_back(params[i]);
+      S2.p.push_back(S3.p[3 * i + r]);
+      S2.q.push_back(S3.q[3 * i + r]);
+    }
+  Layout L2;
+  T* gA = nullptr;
+  T* gB = nullptr;
+  ST_TRY(adjoint_impl<T>(P, S2, CK, &gA, &gB, L2, s));
+  for (int i = 0; i < npairs; ++i) {
+    const GridRec& g = P->grids[gop[i]];
+    CombineDev& d = dv[i];
+    d.off_out = Lp.user_foff[i];
+    d.off1 = L2.user_foff[2 * i];      // p-bar of (p,q)
+    d.off2 = L2.user_foff[2 * i + 1];  // p-bar of (p,p)
+    d.off3 = L2.user_foff[2 * i + 1];  // q-bar of (p,p)
+    d.x1 = gA;
+    d.x2 = gA;
+    d.x3 = gB;
+    d.mul_area = 0;
+    d.coef = params[i].eps * (mass[6 * i] - mass[6 * i + 1]);
+    d.nlat = g.d.nlat;
+    d.nlon = g.d.nlon;
+    d.h = g.h;
+    d.aw = g.d_aw;
+  }
+  return combine_pairs<T>(P, dv, dS, s);
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -845,6 +1172,7 @@ shot_status shot_plan_destroy(shot_plan_t P) {
   (void)hipDeviceSynchronize();
   for (auto& g : P->grids) free_grid(g);
   if (P->ws.p) (void)hipFree(P->ws.p);
+  if (P->ws2.p) (void)hipFree(P->ws2.p);
   for (auto e : P->evpool) (void)hipEventDestroy(e);
   delete P;
   return SHOT_OK;
@@ -949,9 +1277,22 @@ shot_status shot_sinkhorn_divergence_grad(shot_plan_t P, const int32_t* gop, int
                                           double* S_out, void* dS_dp, int32_t mode,
                                           int32_t checkpoint_every, shot_solve_info* info,
                                           void* stream) {
-  (void)P; (void)gop; (void)npairs; (void)params; (void)p; (void)q; (void)S_out; (void)dS_dp;
-  (void)mode; (void)checkpoint_every; (void)info; (void)stream;
-  return SHOT_E_UNSUPPORTED;
+  if (!P || !gop || npairs <= 0 || !params || !ptr_ok(p) || !ptr_ok(q) || !S_out || !ptr_ok(dS_dp))
+    return SHOT_E_INVALID;
+  if (mode != 0 && mode != 1) return SHOT_E_INVALID;
+  if (checkpoint_every < 0) return SHOT_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(P->dev));
+  std::vector<shot_solve_info> inf(3 * (size_t)npairs);
+  shot_status st =
+      P->prec == SHOT_FP64
+          ? divergence_grad_impl<double>(P, gop, npairs, params, p, q, S_out, static_cast<double*>(dS_dp),
+                                         mode, checkpoint_every, inf.data(), s)
+          : divergence_grad_impl<float>(P, gop, npairs, params, p, q, S_out, static_cast<float*>(dS_dp),
+                                        mode, checkpoint_every, inf.data(), s);
+  if (st != SHOT_OK) return st;
+  if (info) std::copy(inf.begin(), inf.end(), info);
+  return worst(inf.data(), 3 * npairs);
 }
 
 shot_status shot_plan_set_tuning(shot_plan_t P, int32_t grid, int32_t items_per_block,

@@ -155,6 +155,38 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
+__device__ double block_min(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int i = 1; i < nw; ++i) r = fmin(r, sh[i]);
+  return r;
+}
+
+__device__ double block_max(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int i = 1; i < nw; ++i) r = fmax(r, sh[i]);
+  return r;
+}
+
+// Non-finite outputs count as -inf so that the ratio of that half is -inf.
+template <typename T>
+__device__ __forceinline__ void track_minmax(double& mn, double& mx, T v) {
+  const double d = isfinite(v) ? (double)v : -INFINITY;
+  mn = fmin(mn, d);
+  mx = fmax(mx, d);
+}
+
 template <typename T>
 __device__ __forceinline__ bool bad_kernel_value(T x) {
   return !(x > (T)0) || !isfinite(x);
@@ -170,11 +202,11 @@ __device__ __forceinline__ T* vbuf_of(const RowArgs<T>& A, int k) { return (k & 
 // c = tau/2 (log sum a p u_hat^(-eps/tau) - log sum a q v_hat^(-eps/tau)).
 template <typename T>
 __device__ double gauge(const RowArgs<T>& A, const ItemDev& I, int it, int k, double* sh) {
-  const double* R = A.red + ((size_t)(k & 1) * A.nitems_all + it) * (size_t)A.hs * 4;
+  const double* R = A.red + ((size_t)(k & 1) * A.nitems_all + it) * (size_t)A.hs * RED_SLOTS;
   double s0 = 0.0, s1 = 0.0;
   for (int q = threadIdx.x; q < A.h; q += blockDim.x) {
-    s0 += R[(size_t)q * 4 + 0];
-    s1 += R[(size_t)q * 4 + 1];
+    s0 += R[(size_t)q * RED_SLOTS + 0];
+    s1 += R[(size_t)q * RED_SLOTS + 1];
   }
   s0 = block_sum(s0, sh);
   s1 = block_sum(s1, sh);
@@ -188,6 +220,36 @@ __device__ double gauge(const RowArgs<T>& A, const ItemDev& I, int it, int k, do
 __device__ __forceinline__ int xcd_row_pair(int b, int h) {
   const int q = h >> 3, r = h & 7, x = b & 7;
   return x * q + min(x, r) + (b >> 3);
+}
+
+// Adjoint notes (balanced Alg. 1, reverse mode).  Forward iteration k:
+//   A = K v_{k-1}, u-hat = p / A, B = K u-hat, v-hat = q / B, s = sum u-hat,
+//   u_k = u-hat / s, v_k = s v-hat;  cost R = sum a (eps log u_T p + eps log v_T q).
+// Only v_k feeds the next iteration, so the reverse sweep carries v-bar:
+//   s-bar = sum v-bar (.) v-hat  (- sum u-bar_T (.) u-hat / s^2 at k = T)
+//   q-bar += s v-bar v-hat / q,  B-bar = -s v-bar v-hat^2 / q
+//   u-hat-bar = s-bar + K^T B-bar (+ u-bar_T / s at k = T)
+//   p-bar += u-hat-bar u-hat / p,  A-bar = -u-hat-bar u-hat^2 / p,  v-bar_{k-1} = K^T A-bar
+// with K^T x = a (.) K(x / a): the forward FFT skips the area weights and the
+// inverse side multiplies by them.  u-bar_T = eps a p / u_T, v-bar_T = eps a q / v_T,
+// and the cost contributes eps a log u_T to p-bar and eps a log v_T to q-bar.
+
+// Kernel ratio of one half-iteration (min over all rows of K. / max), folded
+// into the item's running minimum.  Called by one block per item.
+template <typename T>
+__device__ void kratio_fold(const RowArgs<T>& A, int it, int k, int slot, double* sh) {
+  const double* R = A.red + ((size_t)(k & 1) * A.nitems_all + it) * (size_t)A.hs * RED_SLOTS;
+  double mn = INFINITY, mx = -INFINITY;
+  for (int q = threadIdx.x; q < A.h; q += blockDim.x) {
+    mn = fmin(mn, R[(size_t)q * RED_SLOTS + slot]);
+    mx = fmax(mx, R[(size_t)q * RED_SLOTS + slot + 1]);
+  }
+  mn = block_min(mn, sh);
+  mx = block_max(mx, sh);
+  if (threadIdx.x == 0) {
+    const double r = (mx > 0.0 && isfinite(mn)) ? mn / mx : -INFINITY;
+    A.kr[it] = fmin(A.kr[it], r);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -224,6 +286,7 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
 
   double g = 1.0;
   if (mode == ROW_FINAL) g = gauge(A, I, it, A.k, sh);
+  else if (mode == ROW_SINK_U && A.gk) g = A.gk[it];
   else if (mode == ROW_SINK_U && A.k > 1) g = gauge(A, I, it, A.k - 1, sh);
 
   if (mode == ROW_FINAL) {
@@ -247,6 +310,7 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
     }
     acc = block_sum(acc, sh);
     if (tid == 0) A.prep[((size_t)it * A.hs + jp) * 4 + 3] = acc;
+    if (A.kr && blockIdx.x == 0 && A.k >= 1) kratio_fold(A, it, A.k, 4, sh);
     return;
   }
 
@@ -256,7 +320,8 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
     tws = twl;
   }
   cpx<T>* X = buf0;
-  const bool has_inverse = (mode == ROW_INV || mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK);
+  const bool has_inverse = (mode == ROW_INV || mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK ||
+                            mode == ROW_ADJ_A || mode == ROW_ADJ_VB);
   if (has_inverse) {
     // G_j[m] = GE + GO, G_j'[m] = GE - GO; Z[m] = G_j[m] + i G_j'[m] and its
     // Hermitian mirror Z[N-m] = conj(G_j[m]) + i conj(G_j'[m]); zero elsewhere.
@@ -299,6 +364,7 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
   }
 
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  double kmin = INFINITY, kmax = -INFINITY;  // raw heat-kernel outputs of this row pair
   bool bad = false;
   if (mode == ROW_SINK_U || mode == ROW_CHECK) {
     // u_hat_k = f(p / (g_{k-1} K v_hat_{k-1})); residual of iteration k-1:
@@ -322,6 +388,7 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
         if (mode == ROW_CHECK) { nv[rr] = (T)0; continue; }
         const T kv = gs * kraw;
         bad |= bad_kernel_value(kv);
+        track_minmax(kmin, kmax, kraw);
         T u = pv / kv;
         if (!I.balanced) u = pow(u, (T)I.lam);
         un[fi] = u;
@@ -340,6 +407,7 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
         const long long idx = (rr ? r2 : r1) + c;
         const T kraw = rr ? z.y : z.x;
         bad |= bad_kernel_value(kraw);
+        track_minmax(kmin, kmax, kraw);
         const T qv = Q[idx];
         T v = qv / kraw;
         if (!I.balanced) {
@@ -348,6 +416,52 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
         }
         vn[idx - I.foff] = v;
         nv[rr] = v;
+      }
+      X[c] = {nv[0], eq ? (T)0 : nv[1]};
+    }
+  } else if (mode == ROW_ADJ_START || mode == ROW_ADJ_A || mode == ROW_ADJ_VB) {
+    // Reverse sweep of the balanced iteration (see adjoint notes above).
+    const double s = A.gk[it];
+    const T ss = (T)s;
+    const T* uh = ubuf_of(A, 0) + I.foff;  // u-hat of the iteration being reversed
+    const T* vh = vbuf_of(A, 0) + I.foff;  // v-hat (of k for START, of k-1 for VB)
+    const T ea = (T)I.eps * aj;
+    T sbar = (T)0;
+    if (mode == ROW_ADJ_A) {
+      double sb = 0.0;
+      for (int q = tid; q < h; q += bs) sb += A.adjp[(size_t)it * A.hs + q];
+      sbar = (T)block_sum(sb, sh);
+    }
+    for (int c = tid; c < N; c += bs) {
+      const cpx<T> z = (mode == ROW_ADJ_START) ? cpx<T>{(T)0, (T)0} : X[c];
+      T nv[2];
+      for (int rr = 0; rr < (eq ? 1 : 2); ++rr) {
+        const long long idx = (rr ? r2 : r1) + c;
+        const long long fi = idx - I.foff;
+        const T kt = aj * (rr ? z.y : z.x);  // K^T applied: a (.) (synthesised field)
+        if (mode == ROW_ADJ_A) {
+          const T u = uh[fi], pv = P[idx];
+          T ub = sbar + kt;
+          if (A.k == A.kT) ub += ea * pv / u;  // u-bar_T / s_T = eps a p / u-hat_T
+          A.gA[idx] += ub * u / pv;
+          nv[rr] = -ub * u * u / pv;
+        } else {
+          const T v = vh[fi], qv = Q[idx];
+          T vb;
+          if (mode == ROW_ADJ_START) {
+            const T u = uh[fi], pv = P[idx];
+            const T uT = u / ss, vT = ss * v;
+            A.gA[idx] = ea * log(uT);  // direct terms of the cost
+            A.gB[idx] = ea * log(vT);
+            vb = ea * qv / vT;
+            acc0 -= (double)(ea * pv / uT) * (double)u / (s * s);
+          } else {
+            vb = kt;
+          }
+          acc0 += (double)vb * (double)v;
+          A.gB[idx] += ss * vb * v / qv;
+          nv[rr] = -ss * vb * v * v / qv;
+        }
       }
       X[c] = {nv[0], eq ? (T)0 : nv[1]};
     }
@@ -380,15 +494,30 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
       pr[1] = acc1;
       pr[2] = acc2;
     }
+  } else if (mode == ROW_ADJ_START || mode == ROW_ADJ_VB) {
+    acc0 = block_sum(acc0, sh);
+    if (tid == 0) A.adjp[(size_t)it * A.hs + jp] = acc0;
   } else if (mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK) {
     if (A.chk_slot >= 0) {
       acc2 = block_sum(acc2, sh);
       if (tid == 0) A.rhist[((size_t)it * A.nslot + A.chk_slot) * A.hs + jp] = acc2;
     }
     if (mode != ROW_CHECK) {
+      const double kmn = block_min(kmin, sh), kmx = block_max(kmax, sh);
+      if (tid == 0) {
+        double* rp = A.red + (((size_t)(A.k & 1) * A.nitems_all + it) * A.hs + jp) * RED_SLOTS;
+        rp[mode == ROW_SINK_U ? 2 : 4] = kmn;
+        rp[mode == ROW_SINK_U ? 3 : 5] = kmx;
+      }
+      // fold the previous half-iteration's kernel ratio into the item's running minimum
+      if (A.kr && blockIdx.x == 0) {
+        if (mode == ROW_SINK_V) kratio_fold(A, it, A.k, 2, sh);
+        else if (A.k > 1) kratio_fold(A, it, A.k - 1, 4, sh);
+      }
       const double s = block_sum(mode == ROW_SINK_U ? acc0 : acc1, sh);
       if (tid == 0) {
-        A.red[(((size_t)(A.k & 1) * A.nitems_all + it) * A.hs + jp) * 4 + (mode == ROW_SINK_U ? 0 : 1)] = s;
+        double* rp = A.red + (((size_t)(A.k & 1) * A.nitems_all + it) * A.hs + jp) * RED_SLOTS;
+        rp[mode == ROW_SINK_U ? 0 : 1] = s;
         if (sh_bad) atomicMin(&A.brk[it], A.k);
       }
     }
@@ -399,7 +528,8 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
   // forward FFT of the rows now in X, fold, weight, store
   cpx<T>* other = (X == buf0) ? buf1 : buf0;
   cpx<T>* Z = fft_lds<T>(X, other, N, A.fac, A.nfac, tws, (T)-1);
-  const T cw = (mode == ROW_FWD && !A.wts_in) ? (T)1 : aj;
+  const bool adj = (mode == ROW_ADJ_START || mode == ROW_ADJ_A || mode == ROW_ADJ_VB);
+  const T cw = ((mode == ROW_FWD && !A.wts_in) || adj) ? (T)1 : aj;
   for (int m = tid; m < L; m += bs) {
     const cpx<T> a = Z[m];
     cpx<T> b = Z[(N - m) % N];
@@ -1013,6 +1143,38 @@ __global__ void __launch_bounds__(256) reduce_kernel(RowArgs<T> A, int nchk_done
 }
 
 // ---------------------------------------------------------------------------
+// Gauge of iteration k per item (g_k = s_k for balanced items), one block per item.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) gauge_kernel(RowArgs<T> A, int k, double* gout) {
+  __shared__ double sh[16];
+  const int it = A.item0 + blockIdx.x;
+  const ItemDev I = A.items[it];
+  const double g = gauge(A, I, it, k, sh);
+  if (threadIdx.x == 0) gout[it] = g;
+}
+
+// ---------------------------------------------------------------------------
+// Per-pair gradient combination: out = wa (x1 - (x2 + x3)/2) + coef a.
+// grid = (ceil(maxn / 256), npairs).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) combine_kernel(const CombineDev* __restrict__ D, T* out) {
+  const CombineDev d = D[blockIdx.y];
+  const long long n = (long long)d.nlat * d.nlon;
+  const long long x = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+  const int row = (int)(x / d.nlon);
+  const int jr = row < d.h ? row : d.nlat - 1 - row;
+  const double a = (double)static_cast<const T*>(d.aw)[jr];
+  const double v1 = (double)static_cast<const T*>(d.x1)[d.off1 + x];
+  const double v2 = (double)static_cast<const T*>(d.x2)[d.off2 + x];
+  const double v3 = (double)static_cast<const T*>(d.x3)[d.off3 + x];
+  const double w = d.mul_area ? a : 1.0;
+  out[d.off_out + x] = (T)(w * (v1 - 0.5 * (v2 + v3)) + d.coef * a);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1131,6 +1293,23 @@ hipError_t launch_reduce(const RowArgs<T>& a, int nb, int nchk_done, double* res
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_gauge(const RowArgs<T>& a, int nb, int k, double* gout, hipStream_t stream) {
+  hipLaunchKernelGGL(gauge_kernel<T>, dim3(nb), dim3(256), 0, stream, a, k, gout);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_combine(const CombineDev* d, int npairs, long long maxn, T* out, hipStream_t stream) {
+  dim3 grid((unsigned)((maxn + 255) / 256), npairs);
+  hipLaunchKernelGGL(combine_kernel<T>, grid, dim3(256), 0, stream, d, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gauge<float>(const RowArgs<float>&, int, int, double*, hipStream_t);
+template hipError_t launch_gauge<double>(const RowArgs<double>&, int, int, double*, hipStream_t);
+template hipError_t launch_combine<float>(const CombineDev*, int, long long, float*, hipStream_t);
+template hipError_t launch_combine<double>(const CombineDev*, int, long long, double*, hipStream_t);
 template hipError_t launch_rows<float>(const RowArgs<float>&, int, hipStream_t);
 template hipError_t launch_rows<double>(const RowArgs<double>&, int, hipStream_t);
 template hipError_t launch_legendre<float>(const LegArgs<float>&, int, int, hipStream_t);

@@ -27,6 +27,8 @@ struct ItemDev {
   int pad;
 };
 
+constexpr int RED_SLOTS = 8;
+
 // Row kernel modes.
 enum RowMode : int {
   ROW_FWD = 0,     // field -> folded spectrum
@@ -37,9 +39,9 @@ enum RowMode : int {
   ROW_FINAL = 5,   // potentials and cost partials (no FFT)
   ROW_INIT = 6,    // spectrum of the constant 1 field + norms/masses of p, q
   // adjoint sweep (balanced, see adjoint comments in kernels.hip)
-  ROW_ADJ_B = 7,   // v-bar -> B-bar, q-bar; spectrum of B-bar
-  ROW_ADJ_A = 8,   // K^T B-bar -> u-hat-bar -> A-bar, p-bar; spectrum of A-bar
-  ROW_ADJ_V = 9,   // K^T A-bar -> v-bar of the previous iteration (stored)
+  ROW_ADJ_START = 7,  // final-cost adjoints of u_T, v_T -> B-bar_T; spectrum of B-bar_T
+  ROW_ADJ_A = 8,      // K^T B-bar -> u-hat-bar -> A-bar, p-bar; spectrum of A-bar
+  ROW_ADJ_VB = 9,     // K^T A-bar = v-bar_{k-1} -> B-bar_{k-1}, q-bar; spectrum of B-bar_{k-1}
 };
 
 template <typename T>
@@ -63,19 +65,33 @@ struct RowArgs {
   T* out2;            // FINAL: psi
   T* ubuf0; T* ubuf1; // ping-pong u-hat by iteration parity
   T* vbuf0; T* vbuf1; // ping-pong v-hat by iteration parity
-  double* red;        // [2][nitems][h][4] per-row-pair partial sums (slot 0: u-half, 1: v-half)
+  double* red;        // [2][nitems][hs][RED_SLOTS] per-row-pair partials: 0 u-half sum, 1 v-half sum,
+                      // 2/3 u-half min/max of K v, 4/5 v-half min/max of K u
+  double* kr;         // [nitems] running min over half-iterations of min(K.)/max(K.)
   int nitems_all;
   double* rhist;      // [nitems][nslot][h] e_marg residual partials
   int nslot;
   int chk_slot;       // slot written by this launch, -1 for none
   double* prep;       // [nitems][h][4]: sum p^2, sum a p, sum a q, cost partial
   int* brk;           // [nitems] first breakdown iteration (INT_MAX = none)
-  // adjoint state
-  T* gA;              // adjoint sweep: p-bar accumulator (layout of fields)
+  // adjoint state (balanced reverse sweep) and gauge overrides
+  T* gA;              // p-bar accumulator (layout of fields)
   T* gB;              // q-bar accumulator
-  T* vbar;            // v-bar of the current reverse iteration
-  const double* sbar; // [nitems] per-item s-bar of the current reverse iteration
-  const double* gk;   // [nitems] gauge g_k of the current reverse iteration
+  double* adjp;       // [nitems][hs] partial sums of s-bar
+  const double* gk;   // [nitems] SINK_U: gauge of iteration k-1 to use instead of the partial sums;
+                      // adjoint modes: s of the iteration whose u-hat / v-hat are read
+  int kT;             // adjoint: last iteration T (its u-bar term enters ROW_ADJ_A)
+};
+
+// Pointwise combination of per-item fields into a per-pair gradient:
+// out = wa * (x1 - (x2 + x3)/2) + coef * a, wa = a (potentials) or 1.
+struct CombineDev {
+  long long off_out, off1, off2, off3;  // element offsets
+  double coef;
+  int nlat, nlon, h;
+  int mul_area;
+  const void* aw;   // h area weights (field precision)
+  const void* x1; const void* x2; const void* x3;
 };
 
 template <typename T>
@@ -112,8 +128,9 @@ template <typename T>
 hipError_t launch_reduce(const RowArgs<T>& a, int nb, int nchk_done, double* res, double* ehist,
                          hipStream_t stream);
 template <typename T>
-hipError_t launch_adjoint_scalar(const RowArgs<T>& a, int nb, double* sbar, const T* uold_bar,
-                                 hipStream_t stream);
+hipError_t launch_gauge(const RowArgs<T>& a, int nb, int k, double* gout, hipStream_t stream);
+template <typename T>
+hipError_t launch_combine(const CombineDev* d, int npairs, long long maxn, T* out, hipStream_t stream);
 
 // Table element kinds.
 enum { TAB_F64 = 0, TAB_F32 = 1, TAB_BF16 = 2, TAB_RECUR = 3 };

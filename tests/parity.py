@@ -37,6 +37,10 @@ def check_status(gpu, oref, prec):
     graded = kb == 0 and float(oref["kratio"]) > margin
     if graded:
         assert kg == 0, "item above the margin broke down on the GPU"
+        # the GPU's own running kernel ratio agrees with the oracle's to the
+        # accuracy of the smallest heat-kernel output
+        kr = float(oref["kratio"])
+        assert abs(gpu["kratio"] - kr) <= 10.0 * U[prec] / kr * kr + 1e-6 * kr, (gpu["kratio"], kr)
     return graded
 
 

@@ -1,0 +1,175 @@
+"""GPU gradient of the Sinkhorn divergence (Sec. 4.2.2) through the hand-written adjoint.
+
+Checks: directional derivatives of the unrolled adjoint against the FP64
+oracle's central finite differences of the same fixed-T computation, the
+envelope (potential-based) gradient against the oracle's, the autograd
+wrapper, and at the full 360x720 batch of 16 pairs against float64 GPU
+central differences (a property that holds at any size).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_18389_amd import synth
+
+from helpers import announce, ensure_built, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    ensure_built()
+
+
+def _plan(grids, precision, legendre="recurrence"):
+    from paper_2605_18389_amd import Plan
+    return Plan(grids, precision=precision, legendre=legendre)
+
+
+def _dirs(p, a, n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        d = p * rng.standard_normal(p.shape)
+        out.append(d - p * (a * d).sum() / (a * p).sum())   # mass preserving
+    return np.array(out)
+
+
+@pytest.mark.parametrize("prec,tol,ck", [("fp64", 1e-7, 0), ("fp64", 1e-7, 7), ("fp32", 2e-4, 0)])
+def test_unrolled_gradient_matches_oracle_fd(prec, tol, ck):
+    grid = ("gl", 16, 32, 16)
+    announce(f"grad FD {grid} {prec} ck={ck}")
+    g = O.make_grid(*grid)
+    p, q = synth.temperature_pair(21, g.x, g.w, g.nlon, K=4)
+    eps, T = 0.2, 30
+    P = _plan([grid], prec)
+    S, G, info = P.divergence_grad(to_dev(p, P.dtype), to_dev(q, P.dtype), eps, T=T, checkpoint_every=ck)
+    assert all(i["status"] == 0 for i in info)
+    Sref = O.divergence(p, q, g, eps, T=T)
+    assert abs(S[0] - Sref) <= (1e-10 if prec == "fp64" else 1e-4) * abs(Sref)
+    G = to_np(G).reshape(p.shape)
+    D = _dirs(p, g.area, 6, 5)
+    fd = O.fd_directional(p, q, D, g, eps, T, h=1e-4)
+    an = np.array([(G * d).sum() for d in D])
+    scale = np.abs(fd).max()
+    assert np.abs(an - fd).max() <= tol * scale, (an, fd)
+
+
+def test_unrolled_gradient_non_mass_preserving_direction():
+    grid = ("gl", 12, 24, 12)
+    announce("grad FD raw direction")
+    g = O.make_grid(*grid)
+    p, q = synth.temperature_pair(4, g.x, g.w, g.nlon, K=3)
+    eps, T = 0.3, 20
+    P = _plan([grid], "fp64")
+    _, G, _ = P.divergence_grad(to_dev(p, P.dtype), to_dev(q, P.dtype), eps, T=T)
+    d = np.random.default_rng(1).standard_normal(p.shape) * p
+    fd = O.fd_directional(p, q, d[None], g, eps, T, h=1e-5)[0]
+    an = (to_np(G).reshape(p.shape) * d).sum()
+    assert abs(an - fd) <= 1e-6 * abs(fd)
+
+
+def test_envelope_gradient_matches_oracle():
+    grid = ("gl", 16, 32, 16)
+    announce("grad envelope")
+    g = O.make_grid(*grid)
+    p, q = synth.temperature_pair(22, g.x, g.w, g.nlon, K=4)
+    eps, T = 0.2, 200
+    P = _plan([grid], "fp64")
+    S, G, _ = P.divergence_grad(to_dev(p, P.dtype), to_dev(q, P.dtype), eps, T=T, mode="envelope")
+    _, (rpq, rpp, rqq) = O.divergence(p, q, g, eps, T=T, return_solves=True)
+    ref = O.envelope_gradient(rpq, rpp, g, eps, O.sinkhorn.__globals__["mass"](p, g),
+                              O.sinkhorn.__globals__["mass"](q, g))
+    assert rel_l2(to_np(G).reshape(p.shape), ref) < 1e-10
+    # at convergence the unrolled gradient agrees with it up to a multiple of a
+    _, Gu, _ = P.divergence_grad(to_dev(p, P.dtype), to_dev(q, P.dtype), eps, T=T)
+    a = g.area
+    cu = to_np(Gu).reshape(p.shape) / a
+    ce = to_np(G).reshape(p.shape) / a
+    cu -= (a * cu).sum() / a.sum()
+    ce -= (a * ce).sum() / a.sum()
+    assert rel_l2(cu, ce) < 1e-6
+
+
+def test_autograd_function():
+    import torch
+    from paper_2605_18389_amd.autograd import sinkhorn_divergence
+    grid = ("gl", 16, 32, 16)
+    announce("autograd")
+    g = O.make_grid(*grid)
+    P = _plan([grid], "fp64")
+    ps, qs = [], []
+    for i in range(2):
+        p, q = synth.temperature_pair(30 + i, g.x, g.w, g.nlon, K=3)
+        ps.append(p)
+        qs.append(q)
+    pt = to_dev(np.stack(ps), P.dtype).requires_grad_(True)
+    qt = to_dev(np.stack(qs), P.dtype)
+    w = torch.tensor([0.7, -1.3], dtype=torch.float64, device="cuda")
+    for eager in (True, False):
+        pt.grad = None
+        S = sinkhorn_divergence(pt, qt, P, 0.2, T=25, eager=eager)
+        (S * w).sum().backward()
+        _, G, _ = P.divergence_grad(pt.detach(), qt, 0.2, T=25)
+        Gn = to_np(G).reshape(2, -1)
+        ref = np.concatenate([0.7 * Gn[0], -1.3 * Gn[1]])
+        np.testing.assert_allclose(to_np(pt.grad).reshape(-1), ref, rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("T", [30, 300])
+def test_full_batch_360x720(T):
+    """16 pairs on the 360x720 Gauss-Legendre grid, t = 1e-3: float64 adjoint against
+    float64 central differences of the same computation (exact at any size), and the
+    float32 adjoint against the float64 one, graded by the kernel-ratio margin."""
+    from parity import MARGIN, U
+    grid = ("gl", 360, 720, 360)
+    announce(f"grad full batch {grid} T={T}")
+    P32 = _plan([grid], "fp32")
+    P64 = _plan([grid], "fp64")
+    x, w = P32.grid_nodes(0)
+    a = np.repeat((w * 2 * np.pi / 720)[:, None], 720, axis=1)
+    ps, qs = [], []
+    for i in range(16):
+        p, q = synth.temperature_pair(synth.pair_seed(4, i), x, w, 720, K=8)
+        ps.append(p)
+        qs.append(q)
+    p = np.stack(ps)
+    q = np.stack(qs)
+    eps = 4e-3
+    S32, G32, info32 = P32.divergence_grad(to_dev(p, P32.dtype), to_dev(q, P32.dtype), eps, T=T)
+    S64, G64, info64 = P64.divergence_grad(to_dev(p, P64.dtype), to_dev(q, P64.dtype), eps, T=T)
+    G32 = to_np(G32).reshape(p.shape)
+    G64 = to_np(G64).reshape(p.shape)
+    # the float64 adjoint is the exact derivative of the float64 T-iteration computation
+    # (checked on the two best-conditioned pairs; the tolerance widens with the
+    # kernel ratio exactly as for value parity)
+    h = 1e-4
+    krs = [min(info64[3 * i]["kratio"], info64[3 * i + 1]["kratio"]) for i in range(16)]
+    for i in sorted(range(16), key=lambda j: -krs[j])[:2]:
+        assert all(inf["status"] == 0 for inf in info64[3 * i:3 * i + 3])
+        tol = max(1e-6, 10 * U["fp64"] / krs[i])
+        for d in _dirs(p[i], a, 2, 100 + i):
+            Sp, _ = P64.divergence(to_dev(p[i] + h * d, P64.dtype), to_dev(q[i], P64.dtype), eps, T=T)
+            Sm, _ = P64.divergence(to_dev(p[i] - h * d, P64.dtype), to_dev(q[i], P64.dtype), eps, T=T)
+            fd = (Sp[0] - Sm[0]) / (2 * h)
+            an = (G64[i] * d).sum()
+            assert abs(an - fd) <= tol * abs(fd), (i, krs[i], an, fd)
+    # float32 against float64, per pair: the (p,q) and (p,p) solves enter the gradient
+    graded = 0
+    for i in range(16):
+        kr = min(info64[3 * i]["kratio"], info64[3 * i + 1]["kratio"])
+        broke32 = any(inf["status"] == 17 for inf in info32[3 * i:3 * i + 2])
+        if broke32:
+            assert kr < MARGIN["fp32"], (i, kr)
+            continue
+        if kr > MARGIN["fp32"]:
+            graded += 1
+            tol = max(1e-4, 10 * U["fp32"] / kr)
+            assert rel_l2(G32[i], G64[i]) < tol, (i, kr, rel_l2(G32[i], G64[i]))
+            assert abs(S32[i] - S64[i]) <= tol * abs(S64[i])
+    if T == 30:
+        assert graded >= 8
