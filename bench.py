@@ -64,14 +64,20 @@ def make_inputs(plan, torch):
             torch.as_tensor(q, dtype=plan.dtype, device=dev).contiguous(), p, q)
 
 
-def time_solves(plan, p, q, steps, warmup, torch, profile=True):
+def time_solves(plan, p, q, steps, warmup, torch, profile=False):
+    """Wall time of `steps` full solves (HIP graph replay unless profiling).
+
+    With profile=True every Legendre and row-FFT launch is bracketed by HIP
+    events on its launch stream (eager launches) and their summed durations
+    are returned with the launch counts."""
     eps = 4 * T_HEAT
+    if profile:
+        plan.profile(True)
     for _ in range(warmup):
         plan.sinkhorn(p, q, eps, T=ITERS, potentials=True)
     torch.cuda.synchronize()
     if profile:
-        plan.profile(True)
-    torch.cuda.synchronize()
+        plan.profile(True)  # reset counts after the warm-up
     t0 = time.perf_counter()
     info = None
     for _ in range(steps):
@@ -135,9 +141,11 @@ def main():
     plan = Plan([GRID], precision=args.precision, legendre=args.legendre)
     p, q, _, _ = make_inputs(plan, torch)
     log("[bench] timing")
-    dt, info, leg, rows = time_solves(plan, p, q, args.steps, args.warmup, torch)
+    dt, info, _, _ = time_solves(plan, p, q, args.steps, args.warmup, torch)
     ms_step = dt / args.steps * 1e3
     value = args.steps * ITERS / dt
+    log("[bench] kernel timing (HIP events per launch)")
+    dtp, _, leg, rows = time_solves(plan, p, q, args.steps, 0, torch, profile=True)
     launches, leg_ms = leg
     avg_leg_ms = leg_ms / max(launches, 1)
     flops, bytes_ = legendre_work(GRID, 1, args.legendre, args.precision)
@@ -151,6 +159,9 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
     roof.update({"kernel": "legendre (per-order analysis + h_l + synthesis)",
                  "avg_launch_ms": avg_leg_ms, "launches": launches,
+                 "timing": f"HIP events around every launch on its stream during {args.steps} further "
+                           f"timed solves launched eagerly ({dtp / args.steps * 1e3:.1f} ms/step); "
+                           f"`value` is from HIP-graph replay",
                  "work_per_launch": {"flop": flops, "bytes": bytes_},
                  "row_fft_avg_launch_ms": rows[1] / max(rows[0], 1)})
     out = {
@@ -178,7 +189,8 @@ def main():
                 log(f"[bench] secondary {prec} {legm}")
                 pl = Plan([GRID], precision=prec, legendre=legm)
                 pp, qq, _, _ = make_inputs(pl, torch)
-                d2, _, lg, _ = time_solves(pl, pp, qq, 2, 1, torch)
+                d2, _, _, _ = time_solves(pl, pp, qq, 2, 1, torch)
+                _, _, lg, _ = time_solves(pl, pp, qq, 1, 0, torch, profile=True)
                 sec[f"{prec}_{legm}"] = {"iterations_per_s": 2 * ITERS / d2,
                                          "legendre_avg_launch_ms": lg[1] / max(lg[0], 1)}
                 del pl

@@ -185,11 +185,18 @@ shot_status shot_plan_get_tuning(shot_plan_t plan, int32_t grid, int32_t* items_
  * events on `stream`) and keeps the fastest on the plan.  Synchronises. */
 shot_status shot_autotune(shot_plan_t plan, int32_t grid, int32_t nitems, void* stream);
 
+/* Fixed-T solves (tol = 0) record their iteration loop once as a HIP graph
+ * per plan and call layout and replay it on later calls with the same layout
+ * (the per-call inputs live in device memory).  enable = 0 launches every
+ * kernel eagerly instead.  Default: enabled. */
+shot_status shot_plan_set_graphs(shot_plan_t plan, int32_t enable);
+
 /* Kernel timing.  When enabled, every launch of the Legendre kernels (class 0)
  * and of the row-FFT kernels (class 1) is bracketed by HIP events on the
  * launch stream; shot_profile_read synchronises and returns the number of
  * timed launches and their summed duration in milliseconds for one class.
- * shot_profile_enable(plan, 0) stops timing; enabling again resets the counts. */
+ * shot_profile_enable(plan, 0) stops timing; enabling again resets the counts.
+ * While timing is enabled, solves launch eagerly (no graph replay). */
 shot_status shot_profile_enable(shot_plan_t plan, int32_t enable);
 shot_status shot_profile_read(shot_plan_t plan, int32_t kernel_class, int64_t* launches,
                               double* total_ms);

@@ -40,7 +40,7 @@ EXPORTS = [
     "shot_sht_synthesis", "shot_heat_apply", "shot_sinkhorn_solve", "shot_sinkhorn_divergence",
     "shot_sinkhorn_divergence_grad", "shot_profile_enable", "shot_profile_read",
     "shot_status_string", "shot_last_error", "shot_plan_set_tuning", "shot_plan_get_tuning",
-    "shot_autotune",
+    "shot_autotune", "shot_plan_set_graphs",
 ]
 
 
@@ -107,6 +107,7 @@ def load_library(path=None):
         "shot_plan_set_tuning": [vp, i32, i32, i32],
         "shot_plan_get_tuning": [vp, i32, ip, ip],
         "shot_autotune": [vp, i32, i32, vp],
+        "shot_plan_set_graphs": [vp, i32],
         "shot_profile_read": [vp, i32, ctypes.POINTER(ctypes.c_int64), dp],
     }
     for name, args in sig.items():
@@ -342,6 +343,9 @@ class Plan:
         _check("shot_plan_get_tuning", self.lib.shot_plan_get_tuning(self.handle, grid, ctypes.byref(ib),
                                                                      ctypes.byref(jpt)))
         return ib.value, jpt.value
+
+    def set_graphs(self, enable=True):
+        _check("shot_plan_set_graphs", self.lib.shot_plan_set_graphs(self.handle, int(bool(enable))))
 
     def autotune(self, grid=0, nitems=1):
         _check("shot_autotune", self.lib.shot_autotune(self.handle, grid, nitems, _stream_ptr()))

@@ -68,7 +68,23 @@ struct shot_plan_s {
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
   int leg_ib = 0;  // 0 = choose automatically
+  // fixed-T solve loops are captured once into a HIP graph and replayed
+  bool graphs = true;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<long long> gkey;
 };
+
+namespace {
+void drop_graph(shot_plan_s* P) {
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->gexec = nullptr;
+  P->graph = nullptr;
+  P->gkey.clear();
+}
+}  // namespace
 
 namespace {
 
@@ -589,6 +605,11 @@ shot_status check_params(const shot_params& pr) {
 }
 
 template <typename T>
+shot_status finish_solve(shot_plan_s* P, const Layout& Lo, Work<T>& W, int nitems, int K, int C,
+                         int final_slot, double tol, T* phi, T* psi, shot_solve_info* info,
+                         double* mass_out, hipStream_t s);
+
+template <typename T>
 shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_solve_info* info,
                        double* mass_out, hipStream_t s) {
   const int nitems = (int)S.grid.size();
@@ -622,6 +643,7 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
     }
     return SHOT_OK;
   };
+  hipStream_t ls = s;  // launch stream (the capture stream while recording a graph)
   auto rows = [&](const Group& G, const GridRec& g, int mode, int k, int chk) {
     RowArgs<T> a = row_args<T>(g, Lo, G, W, nitems);
     a.mode = mode;
@@ -629,15 +651,75 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
     a.chk_slot = chk;
     a.out = phi;
     a.out2 = psi;
-    return run_rows<T>(P, a, G.count, s);
+    return run_rows<T>(P, a, G.count, ls);
   };
-  auto leg = [&](const Group& G, const GridRec& g) { return run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), s); };
+  auto leg = [&](const Group& G, const GridRec& g) { return run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), ls); };
 
-  // v_0 = 1: spectrum of the constant field, plus norms and masses
-  ST_TRY(each_group([&](const Group& G, const GridRec& g) { return rows(G, g, ROW_INIT, 0, -1); }));
   int K = T_iter;
   int final_slot = nslot - 1;
   bool early = false;
+  if (K % C == 0) final_slot = K / C - 1;
+  // Fixed T: the launch sequence depends only on the layout, so it is recorded
+  // once as a HIP graph (per-call data lives in device memory) and replayed.
+  auto fixed_loop = [&]() -> shot_status {
+    ST_TRY(each_group([&](const Group& G, const GridRec& g) { return rows(G, g, ROW_INIT, 0, -1); }));
+    for (int k = 1; k <= T_iter; ++k) {
+      const bool chk_prev = (k - 1 >= 1) && ((k - 1) % C == 0);
+      const int slot = chk_prev ? (k - 1) / C - 1 : -1;
+      ST_TRY(each_group([&](const Group& G, const GridRec& g) {
+        shot_status st = leg(G, g);
+        return st != SHOT_OK ? st : rows(G, g, ROW_SINK_U, k, slot);
+      }));
+      ST_TRY(each_group([&](const Group& G, const GridRec& g) {
+        shot_status st = leg(G, g);
+        return st != SHOT_OK ? st : rows(G, g, ROW_SINK_V, k, -1);
+      }));
+    }
+    return each_group([&](const Group& G, const GridRec& g) {
+      shot_status st = leg(G, g);
+      return st != SHOT_OK ? st : rows(G, g, ROW_CHECK, K + 1, final_slot);
+    });
+  };
+  // (event timing needs eager launches: events recorded inside a graph cannot be timed)
+  if (tol == 0 && P->graphs && !P->prof) {
+    std::vector<long long> key = {(long long)(uintptr_t)P->ws.p, (long long)P->ws.bytes, nitems, T_iter, C,
+                                  Lo.hs, Lo.Lmax, P->prof ? 1 : 0};
+    for (const Group& G : Lo.groups) {
+      key.push_back(G.grid);
+      key.push_back(G.first);
+      key.push_back(G.count);
+      key.push_back(P->grids[G.grid].tune_ib);
+      key.push_back(P->grids[G.grid].tune_jpt);
+    }
+    if (!P->gexec || key != P->gkey) {
+      drop_graph(P);
+      if (!P->cap) HIP_TRY(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+      HIP_TRY(hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed));
+      ls = P->cap;
+      shot_status st = fixed_loop();
+      ls = s;
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(P->cap, &graph);
+      if (st != SHOT_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st != SHOT_OK ? st : hip_fail(e, "hipStreamEndCapture", __LINE__);
+      }
+      e = hipGraphInstantiate(&P->gexec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        P->gexec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate", __LINE__);
+      }
+      P->graph = graph;
+      P->gkey = key;
+    }
+    HIP_TRY(hipGraphLaunch(P->gexec, s));
+    return finish_solve<T>(P, Lo, W, nitems, K, C, final_slot, tol, phi, psi, info, mass_out, s);
+  }
+
+  // v_0 = 1: spectrum of the constant field, plus norms and masses
+  ST_TRY(each_group([&](const Group& G, const GridRec& g) { return rows(G, g, ROW_INIT, 0, -1); }));
+  final_slot = nslot - 1;
   for (int k = 1; k <= T_iter; ++k) {
     const bool chk_prev = (k - 1 >= 1) && ((k - 1) % C == 0);
     const int slot = chk_prev ? (k - 1) / C - 1 : -1;
@@ -677,7 +759,22 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
       return st != SHOT_OK ? st : rows(G, g, ROW_CHECK, K + 1, final_slot);
     }));
   }
-  ST_TRY(each_group([&](const Group& G, const GridRec& g) { return rows(G, g, ROW_FINAL, K, -1); }));
+  return finish_solve<T>(P, Lo, W, nitems, K, C, final_slot, tol, phi, psi, info, mass_out, s);
+}
+
+// Potentials, cost and reports after the iteration loop (iteration K reached).
+template <typename T>
+shot_status finish_solve(shot_plan_s* P, const Layout& Lo, Work<T>& W, int nitems, int K, int C,
+                         int final_slot, double tol, T* phi, T* psi, shot_solve_info* info,
+                         double* mass_out, hipStream_t s) {
+  for (const Group& G : Lo.groups) {
+    RowArgs<T> a = row_args<T>(P->grids[G.grid], Lo, G, W, nitems);
+    a.mode = ROW_FINAL;
+    a.k = K;
+    a.out = phi;
+    a.out2 = psi;
+    ST_TRY(run_rows<T>(P, a, G.count, s));
+  }
   const int nchk_done = K / C;
   for (const Group& G : Lo.groups) {
     RowArgs<T> a = row_args<T>(P->grids[G.grid], Lo, G, W, nitems);
@@ -1171,6 +1268,8 @@ shot_status shot_plan_destroy(shot_plan_t P) {
   if (!P) return SHOT_OK;
   (void)hipDeviceSynchronize();
   for (auto& g : P->grids) free_grid(g);
+  drop_graph(P);
+  if (P->cap) (void)hipStreamDestroy(P->cap);
   if (P->ws.p) (void)hipFree(P->ws.p);
   if (P->ws2.p) (void)hipFree(P->ws2.p);
   for (auto e : P->evpool) (void)hipEventDestroy(e);
@@ -1331,8 +1430,16 @@ shot_status shot_autotune(shot_plan_t P, int32_t grid, int32_t nitems, void* str
   return st;
 }
 
+shot_status shot_plan_set_graphs(shot_plan_t P, int32_t enable) {
+  if (!P) return SHOT_E_INVALID;
+  P->graphs = enable != 0;
+  if (!P->graphs) drop_graph(P);
+  return SHOT_OK;
+}
+
 shot_status shot_profile_enable(shot_plan_t P, int32_t enable) {
   if (!P) return SHOT_E_INVALID;
+  drop_graph(P);  // captured graphs hold the previous event records
   if (enable) {
     P->timed.clear();
     P->evnext = 0;
