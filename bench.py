@@ -91,6 +91,69 @@ def time_solves(plan, p, q, steps, warmup, torch, profile=False):
     return dt, info[0], leg, rows
 
 
+C5_GRID = ("gl", 360, 720, 360)
+C4_GRIDS = [("gl", 90, 180, 90), ("gl", 180, 360, 180), ("gl", 360, 720, 360)]
+C4_COUNTS = [96, 96, 64]
+
+
+def bench_grad_batch(torch, precision, legendre, reps=1):
+    """16 pairs on 360x720 Gauss-Legendre, t = 1e-3, balanced, T = 300: S and dS/dp per pair
+    (forward, then the hand-written adjoint with checkpoint recompute)."""
+    from paper_2605_18389_amd import Plan, synth
+    plan = Plan([C5_GRID], precision=precision, legendre=legendre)
+    plan.autotune(0, 48)
+    x, w = plan.grid_nodes(0)
+    ps, qs = [], []
+    for i in range(16):
+        p, q = synth.temperature_pair(synth.pair_seed(4, i), x, w, C5_GRID[2], K=8)
+        ps.append(p)
+        qs.append(q)
+    p = torch.as_tensor(np.stack(ps), dtype=plan.dtype, device="cuda").contiguous()
+    q = torch.as_tensor(np.stack(qs), dtype=plan.dtype, device="cuda").contiguous()
+    plan.divergence_grad(p, q, 4e-3, T=300)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S, g, info = plan.divergence_grad(p, q, 4e-3, T=300)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    bad = sum(1 for i in range(16) if any(x["status"] == 17 for x in info[3 * i:3 * i + 3]))
+    return {"divergence_grad_per_s": 16 / dt, "ms_per_batch": dt * 1e3, "pairs": 16,
+            "pairs_with_breakdown": bad, "tuning": plan.get_tuning(0)}
+
+
+def bench_uneven_batch(torch, precision, legendre, reps=1):
+    """256 pairs on three grids (96 at 90x180, 96 at 180x360, 64 at 360x720), per-pair t
+    log-uniform in [1e-4, 1e-2], half balanced and half unbalanced (tau in {0.1, 1, 10},
+    masses 1 vs 1.05), T = 300, one divergence call (768 solves advanced together)."""
+    from paper_2605_18389_amd import Plan, synth
+    plan = Plan(C4_GRIDS, precision=precision, legendre=legendre)
+    goi = sum(([k] * c for k, c in enumerate(C4_COUNTS)), [])
+    for k, c in enumerate(C4_COUNTS):
+        plan.autotune(k, 3 * c)
+    prm = synth.batch_pair_params(synth.pair_seed(3, 0), len(goi))
+    ps, qs = [], []
+    for i, k in enumerate(goi):
+        x, w = plan.grid_nodes(k)
+        p, q = synth.temperature_pair(synth.pair_seed(3, i), x, w, C4_GRIDS[k][2], K=8, q_mass=prm[i][2])
+        ps.append(p.ravel())
+        qs.append(q.ravel())
+    p = torch.as_tensor(np.concatenate(ps), dtype=plan.dtype, device="cuda")
+    q = torch.as_tensor(np.concatenate(qs), dtype=plan.dtype, device="cuda")
+    eps = [4 * t for t, _, _ in prm]
+    tau = [tt for _, tt, _ in prm]
+    plan.divergence(p, q, eps, tau, T=300, grid_of_pair=goi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S, info = plan.divergence(p, q, eps, tau, T=300, grid_of_pair=goi)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    bad = sum(1 for i in range(len(goi)) if any(x["status"] == 17 for x in info[3 * i:3 * i + 3]))
+    return {"divergences_per_s": len(goi) / dt, "ms_per_batch": dt * 1e3, "pairs": len(goi),
+            "pairs_with_breakdown": bad}
+
+
 def cpu_baseline(budget_s):
     """FP64 oracle on host cores: iterations/s of Alg. 1 on the same workload."""
     import oracle as O
@@ -197,6 +260,18 @@ def main():
             except Exception as e:  # report, do not hide
                 sec[f"{prec}_{legm}"] = {"error": str(e)}
         out["secondary"] = sec
+        bat = {}
+        for prec, legm in (("fp32", "recurrence"), ("fp32", "table"), ("bf16", "table")):
+            key = f"{prec}_{'mfma' if legm == 'table' else 'recurrence'}"
+            try:
+                log(f"[bench] batched gradient {key}")
+                bat[f"grad_16x360x720_{key}"] = bench_grad_batch(torch, prec, legm)
+                log(f"[bench] uneven batch {key}")
+                bat[f"uneven_256_{key}"] = bench_uneven_batch(torch, prec, legm)
+            except Exception as e:
+                bat[key] = {"error": str(e)}
+            torch.cuda.empty_cache()
+        out["batched"] = bat
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)

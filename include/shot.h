@@ -172,9 +172,13 @@ shot_status shot_sinkhorn_divergence_grad(shot_plan_t plan, const int32_t* grid_
                                           shot_solve_info* info, void* stream);
 
 /* Launch configuration of grid `grid`'s Legendre kernel: items advanced per
- * workgroup (1, 2, 4 or 8; 0 = automatic, capped by LDS) and, for
- * SHOT_LEG_RECURRENCE grids, latitude chains per thread (1, 2 or 4 with at
- * most 256 threads per workgroup; 0 = automatic).  SHOT_E_INVALID otherwise. */
+ * workgroup of the VALU kernels (1, 2, 4 or 8; 0 = automatic, capped by LDS)
+ * and, as the second value, for SHOT_LEG_RECURRENCE grids the latitude chains
+ * per thread of the latitude-split kernel (1, 2 or 4, at most 256 threads per
+ * workgroup; 0 = the row-split kernel), for SHOT_LEG_TABLE grids of float32 and
+ * bfloat16 plans the matrix-core kernel's column tiles per workgroup (1, 2 or 4
+ * tiles of 16 columns = 8, 16 or 32 items; 0 = automatic, matrix cores for
+ * batches of 4 items and more; -1 = VALU kernel only).  SHOT_E_INVALID otherwise. */
 shot_status shot_plan_set_tuning(shot_plan_t plan, int32_t grid, int32_t items_per_block,
                                  int32_t chains_per_thread);
 shot_status shot_plan_get_tuning(shot_plan_t plan, int32_t grid, int32_t* items_per_block,

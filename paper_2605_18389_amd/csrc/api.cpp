@@ -33,6 +33,8 @@ struct GridRec {
   std::vector<int> fac;
   int tab_kind = TAB_F32;
   void* d_tab = nullptr;
+  void* d_tabT = nullptr;            // transposed per-(m, parity) blocks for the MFMA kernel
+  long long* d_toffT = nullptr;      // [2L] offsets of those blocks
   double* d_xs = nullptr;
   double* d_rcoef = nullptr;
   double* d_rgam = nullptr;
@@ -41,7 +43,8 @@ struct GridRec {
   void* d_aw = nullptr;
   void* d_tw = nullptr;
   int tune_ib = 0;   // Legendre items per workgroup (0 = automatic)
-  int tune_jpt = 0;  // recurrence chains per thread (0 = automatic)
+  int tune_jpt = 0;  // recurrence chains per thread (0 = automatic); table grids: MFMA column
+                     // tiles (1, 2, 4), 0 = automatic, -1 = VALU kernel only
   int64_t n() const { return (int64_t)d.nlat * d.nlon; }
 };
 
@@ -135,23 +138,17 @@ hipEvent_t take_event(shot_plan_s* P) {
   return P->evpool[P->evnext++];
 }
 
-// Bracket one launch with events when profiling is on.
+// Time one launch with dispatch-attached events when profiling is on.
 struct ProfScope {
   shot_plan_s* P;
-  hipStream_t s;
   int cls;
-  hipEvent_t a = nullptr;
-  ProfScope(shot_plan_s* P_, hipStream_t s_, int cls_) : P(P_), s(s_), cls(cls_) {
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(shot_plan_s* P_, hipStream_t, int cls_) : P(P_), cls(cls_) {
     if (P->prof) {
       a = take_event(P);
-      if (a) (void)hipEventRecord(a, s);
-    }
-  }
-  ~ProfScope() {
-    if (P->prof && a) {
-      hipEvent_t b = take_event(P);
-      if (b) {
-        (void)hipEventRecord(b, s);
+      b = take_event(P);
+      if (a && b) {
+        set_launch_events(a, b);
         P->timed.push_back({a, b, cls});
       }
     }
@@ -181,10 +178,11 @@ uint16_t to_bf16(double v) {
 }
 
 void free_grid(GridRec& g) {
-  for (void* p : {g.d_tab, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam, (void*)g.d_rseed,
-                  (void*)g.d_rck, g.d_aw, g.d_tw})
+  for (void* p : {g.d_tab, g.d_tabT, (void*)g.d_toffT, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam,
+                  (void*)g.d_rseed, (void*)g.d_rck, g.d_aw, g.d_tw})
     if (p) (void)hipFree(p);
-  g.d_tab = g.d_aw = g.d_tw = nullptr;
+  g.d_tab = g.d_tabT = g.d_aw = g.d_tw = nullptr;
+  g.d_toffT = nullptr;
   g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = g.d_rck = nullptr;
 }
 
@@ -193,7 +191,8 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
   if (d.kind == SHOT_GRID_GAUSS_LEGENDRE) gauss_legendre(d.nlat, g.x, g.w);
   else clenshaw_curtis(d.nlat, g.x, g.w);
   g.h = (d.nlat + 1) / 2;
-  g.hpad = (g.h + 3) / 4 * 4;
+  // table rows padded to the matrix-core K step (32) for fp32/bf16 tables
+  g.hpad = P->prec == SHOT_FP64 ? (g.h + 3) / 4 * 4 : (g.h + 31) / 32 * 32;
   g.fac = fft_radices(d.nlon);
   const bool f64 = P->prec == SHOT_FP64;
   // area weights of rows 0..h-1 and twiddles in field precision
@@ -223,6 +222,30 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
     std::vector<double> tab;
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     legendre_rows(d.L, xs, g.hpad, tab, (int)hw);
+    // transposed per-(m, parity) blocks [round_up(h,16)][mma_rpad(rows)] for the MFMA kernel
+    std::vector<long long> toffT;
+    std::vector<double> tabT;
+    if (P->prec != SHOT_FP64) {
+      const int hT = (g.h + 15) / 16 * 16;
+      toffT.resize(2 * (size_t)d.L);
+      long long off = 0;
+      for (int m = 0; m < d.L; ++m)
+        for (int par = 0; par < 2; ++par) {
+          toffT[2 * m + par] = off;
+          off += (long long)hT * mma_rpad((d.L - m + 1 - par) / 2);
+        }
+      tabT.assign((size_t)off, 0.0);
+      for (int m = 0; m < d.L; ++m)
+        for (int par = 0; par < 2; ++par) {
+          const int npar = (d.L - m + 1 - par) / 2, rpad = mma_rpad(npar);
+          double* blk = tabT.data() + toffT[2 * m + par];
+          for (int rp = 0; rp < npar; ++rp) {
+            const double* row = tab.data() + (tri_offset(m, d.L) + 2 * rp + par) * g.hpad;
+            for (int j = 0; j < g.h; ++j) blk[(size_t)j * rpad + rp] = row[j];
+          }
+        }
+      if ((st = upload((void**)&g.d_toffT, toffT, s)) != SHOT_OK) return st;
+    }
     if (P->prec == SHOT_FP64) {
       g.tab_kind = TAB_F64;
       st = upload(&g.d_tab, tab, s);
@@ -230,11 +253,20 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
       g.tab_kind = TAB_F32;
       std::vector<float> t32(tab.begin(), tab.end());
       st = upload(&g.d_tab, t32, s);
+      if (st == SHOT_OK) {
+        std::vector<float> tT(tabT.begin(), tabT.end());
+        st = upload(&g.d_tabT, tT, s);
+      }
     } else {
       g.tab_kind = TAB_BF16;
       std::vector<uint16_t> t16(tab.size());
       for (size_t i = 0; i < tab.size(); ++i) t16[i] = to_bf16(tab[i]);
       st = upload(&g.d_tab, t16, s);
+      if (st == SHOT_OK) {
+        std::vector<uint16_t> tT(tabT.size());
+        for (size_t i = 0; i < tabT.size(); ++i) tT[i] = to_bf16(tabT[i]);
+        st = upload(&g.d_tabT, tT, s);
+      }
     }
     if (st != SHOT_OK) return st;
   } else {
@@ -454,6 +486,8 @@ LegArgs<T> leg_args(const GridRec& g, const Group& G, const Work<T>& W, int hl_s
   a.h = g.h;
   a.hpad = g.hpad;
   a.tab = g.d_tab;
+  a.tabT = g.d_tabT;
+  a.toffT = g.d_toffT;
   a.xs = g.d_xs;
   a.rcoef = g.d_rcoef;
   a.rgam = g.d_rgam;
@@ -494,6 +528,22 @@ bool use_split(const shot_plan_s* P, const GridRec& g) {
   return split_lds_bytes(g.d.L, g.h, 1, P->prec == SHOT_FP64 ? 8 : 4) <= 60 * 1024;
 }
 
+// Matrix-core kernel for table grids: column tiles per workgroup, or 0 for
+// the VALU kernels.  Automatic: matrix cores from 4 items on, the widest tile
+// count (<= the batch) whose LDS staging fits.
+int mma_tiles(const shot_plan_s* P, const GridRec& g, int count) {
+  if (!g.d_tabT || (g.tab_kind != TAB_F32 && g.tab_kind != TAB_BF16) || g.tune_jpt < 0) return 0;
+  int nt = g.tune_jpt;
+  if (nt == 0) {
+    if (count < 4) return 0;
+    nt = count >= 32 ? 4 : (count >= 16 ? 2 : 1);
+  }
+  while (nt > 1 && mma_lds_bytes(g.d.L, g.hpad, nt, g.tab_kind) > 60 * 1024) nt >>= 1;
+  if (mma_lds_bytes(g.d.L, g.hpad, nt, g.tab_kind) > 60 * 1024) return 0;
+  (void)P;
+  return nt;
+}
+
 int split_ib(const shot_plan_s* P, const GridRec& g, int count) {
   int ib = (g.tune_ib == 2 || (g.tune_ib == 0 && count >= 2)) ? 2 : 1;
   if (ib == 2 && split_lds_bytes(g.d.L, g.h, 2, P->prec == SHOT_FP64 ? 8 : 4) > 60 * 1024) ib = 1;
@@ -511,7 +561,10 @@ template <typename T>
 shot_status run_leg(shot_plan_s* P, const GridRec& g, LegArgs<T> a, hipStream_t s) {
   ProfScope ps(P, s, 0);
   hipError_t e;
-  if (use_split(P, g)) {
+  const int nt = mma_tiles(P, g, a.nb);
+  if (nt > 0) {
+    e = launch_legendre_mma<T>(a, g.tab_kind, nt, s);
+  } else if (use_split(P, g)) {
     const int ib = split_ib(P, g, a.nb);
     e = launch_legendre_split<T>(a, ib, s);
   } else {
@@ -839,9 +892,12 @@ shot_status autotune_impl(shot_plan_s* P, GridRec& g, const Layout& Lo, int nite
       for (int jpt : {1, 2, 4})
         if (recur_jpt_valid(g.h, jpt)) cand.push_back({ib, jpt});
     } else {
-      cand.push_back({ib, 0});
+      cand.push_back({ib, -1});  // VALU table kernel
     }
   }
+  if (g.tab_kind != TAB_RECUR && g.d_tabT)
+    for (int nt : {1, 2, 4})
+      if (16 * nt <= 2 * std::max(nitems, 8)) cand.push_back({0, nt});
   const int save_ib = g.tune_ib, save_jpt = g.tune_jpt;
   const bool save_prof = P->prof;
   P->prof = false;
@@ -854,8 +910,11 @@ shot_status autotune_impl(shot_plan_s* P, GridRec& g, const Layout& Lo, int nite
   for (auto c : cand) {
     g.tune_ib = c.first;
     g.tune_jpt = c.second;
-    if (use_split(P, g) ? split_ib(P, g, nitems) != c.first : pick_ib(P, g, nitems) != c.first)
+    if (g.tab_kind != TAB_RECUR && c.second > 0) {
+      if (mma_tiles(P, g, nitems) != c.second) continue;  // does not fit LDS
+    } else if (use_split(P, g) ? split_ib(P, g, nitems) != c.first : pick_ib(P, g, nitems) != c.first) {
       continue;  // does not fit LDS
+    }
     if (g.tab_kind == TAB_RECUR && c.second == 0 && !use_split(P, g)) continue;
     shot_status st = SHOT_OK;
     for (int w = 0; w < 2 && st == SHOT_OK; ++w) st = run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), s);
@@ -1401,8 +1460,14 @@ shot_status shot_plan_set_tuning(shot_plan_t P, int32_t grid, int32_t items_per_
   if (items_per_block != 0 && items_per_block != 1 && items_per_block != 2 && items_per_block != 4 &&
       items_per_block != 8)
     return SHOT_E_INVALID;
-  if (chains_per_thread != 0 && (g.tab_kind != TAB_RECUR || !recur_jpt_valid(g.h, chains_per_thread)))
-    return SHOT_E_INVALID;
+  if (g.tab_kind == TAB_RECUR) {
+    if (chains_per_thread != 0 && !recur_jpt_valid(g.h, chains_per_thread)) return SHOT_E_INVALID;
+  } else if (chains_per_thread != 0) {
+    const bool mma = g.d_tabT != nullptr;
+    if (!(chains_per_thread == -1 || (mma && (chains_per_thread == 1 || chains_per_thread == 2 ||
+                                                chains_per_thread == 4))))
+      return SHOT_E_INVALID;
+  }
   g.tune_ib = items_per_block;
   g.tune_jpt = chains_per_thread;
   return SHOT_OK;

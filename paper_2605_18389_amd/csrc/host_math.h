@@ -24,6 +24,10 @@ inline SHOT_HD int split_row(int nr, int w) {
   return r < nr ? r : nr;
 }
 
+// Rows of one parity of an order, padded to the 32-row K step of the
+// matrix-core Legendre kernels.
+inline SHOT_HD int mma_rpad(int n) { return (n + 31) / 32 * 32; }
+
 // Gauss-Legendre nodes (descending, row 0 north) and weights (sum 2):
 // the rows of a Gauss-Legendre grid sit at the roots of P_nlat (App. C.1).
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);

@@ -25,6 +25,8 @@
 
 #include <climits>
 
+#include <hip/hip_ext.h>
+
 #include "host_math.h"
 #include "shot_internal.h"
 
@@ -1108,6 +1110,174 @@ __global__ void __launch_bounds__(256) legendre_split_kernel(LegArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// Batched Legendre stage as matrix-core GEMMs (table plans, many items).
+//
+// Per order m and parity, with columns n = (item, re/im) of the workgroup:
+//   analysis   D[r][n] = sum_j P̄[r][j] Y[j][n]       (A = table rows, K = j)
+//   scale      b[r][n] = D[r][n] h_l(item)
+//   synthesis  G[j][n] = sum_r P̄T[j][r] b[r][n]      (A = transposed table, K = r)
+// on v_mfma_f32_16x16x32_bf16 (bf16 operands) or v_mfma_f32_16x16x4_f32 (fp32
+// operands), fp32 accumulation.  Operand layout of the 16x16 MFMAs: A[i][k] in
+// lane i + 16*(k/kv), element k%kv; B[k][j] in lane j + 16*(k/kv); D[i][j] in
+// lane j + 16*(i/4), register i%4 (kv = 8 for bf16, 1 for fp32).  Y and b are
+// staged in LDS as [n][k] rows padded so the 16 lanes of a k-slice hit
+// distinct banks.
+// ---------------------------------------------------------------------------
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+
+template <typename TT>
+struct MmaTraits;
+template <>
+struct MmaTraits<unsigned short> {  // bf16
+  static constexpr int KS = 32, KV = 8, PAD = 8;
+  __device__ static unsigned short cvt(float v) { return f32_to_bf16_rne(v); }
+  __device__ static f32x4_t mma(const unsigned short* a, const unsigned short* b, f32x4_t c) {
+    const uint4 av = *reinterpret_cast<const uint4*>(a);
+    const uint4 bv = *reinterpret_cast<const uint4*>(b);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av),
+                                                   __builtin_bit_cast(bf16x8_t, bv), c, 0, 0, 0);
+  }
+  __device__ static void load_a(unsigned short* dst, const unsigned short* src, bool ok) {
+    *reinterpret_cast<uint4*>(dst) = ok ? *reinterpret_cast<const uint4*>(src) : make_uint4(0, 0, 0, 0);
+  }
+};
+template <>
+struct MmaTraits<float> {
+  static constexpr int KS = 4, KV = 1, PAD = 1;
+  __device__ static float cvt(float v) { return v; }
+  __device__ static f32x4_t mma(const float* a, const float* b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0);
+  }
+  __device__ static void load_a(float* dst, const float* src, bool ok) { *dst = ok ? *src : 0.0f; }
+};
+
+template <typename T, typename TT, int NT>
+__global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using MT = MmaTraits<TT>;
+  constexpr int NB = 16 * NT, KS = MT::KS, KV = MT::KV;
+  const int L = A.L, h = A.h, kpad = A.hpad;
+  const int m = blockIdx.x, nr = L - m;
+  const int c0 = blockIdx.y * NB;
+  const int ncol = 2 * A.nb;
+  const int RP = mma_rpad((L + 1) / 2);
+  const int ys_ld = kpad + MT::PAD, bs_ld = RP + MT::PAD;
+  TT* ys = reinterpret_cast<TT*>(smem_raw);                // [2][NB][ys_ld]
+  TT* bs = ys + (size_t)2 * NB * ys_ld;                    // [2][NB][bs_ld]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const long long toff = tri_off(m, L);
+  const TT* tab = static_cast<const TT*>(A.tab) + toff * kpad;
+
+  // stage Y (zero beyond h and beyond the last column) and clear b
+  for (int idx = tid; idx < 2 * NB * kpad; idx += 256) {
+    const int par = idx / (NB * kpad), rem = idx % (NB * kpad), n = rem / kpad, j = rem % kpad;
+    float v = 0.f;
+    const int col = c0 + n;
+    if (A.mode != 2 && j < h && col < ncol) {
+      const cpx<T> y = A.spec[A.items[A.item0 + (col >> 1)].soff + (size_t)(2 * m + par) * h + j];
+      v = (float)((col & 1) ? y.y : y.x);
+    }
+    ys[((size_t)par * NB + n) * ys_ld + j] = MT::cvt(v);
+  }
+  for (int idx = tid; idx < 2 * NB * bs_ld; idx += 256) bs[idx] = MT::cvt(0.f);
+  __syncthreads();
+
+  if (A.mode != 2) {
+    for (int par = 0; par < 2; ++par) {
+      const int npar = (nr + 1 - par) / 2;
+      const int Rt = (npar + 15) / 16;
+      for (int t = wave; t < Rt; t += 4) {
+        f32x4_t acc[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        const int rp = t * 16 + li;          // row (of this parity) fed by this lane
+        const int r = 2 * rp + par;
+        const bool rok = rp < npar;
+        const TT* arow = tab + (size_t)(rok ? r : 0) * kpad + lg * KV;
+        for (int k0 = 0; k0 < kpad; k0 += KS) {
+          TT a[KV];
+          MT::load_a(a, arow + k0, rok);
+#pragma unroll
+          for (int c = 0; c < NT; ++c) {
+            const TT* bp = ys + ((size_t)par * NB + c * 16 + li) * ys_ld + k0 + lg * KV;
+            acc[c] = MT::mma(a, bp, acc[c]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+          const int n = c * 16 + li, col = c0 + n;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int rpo = t * 16 + lg * 4 + i, ro = 2 * rpo + par;
+            if (rpo < npar && col < ncol) {
+              const int item = A.item0 + (col >> 1);
+              if (A.mode == 0) {
+                const float hv = (float)A.hl[(size_t)item * A.hl_stride + m + ro];
+                bs[((size_t)par * NB + n) * bs_ld + rpo] = MT::cvt(acc[c][i] * hv);
+              } else {
+                T* dst = reinterpret_cast<T*>(&A.coeff[A.items[item].coff + toff + ro]);
+                dst[col & 1] = (T)acc[c][i];
+              }
+            }
+          }
+        }
+      }
+    }
+    if (A.mode == 1) return;
+  } else {
+    for (int idx = tid; idx < NB * nr; idx += 256) {
+      const int n = idx / nr, r = idx % nr, col = c0 + n;
+      if (col >= ncol) continue;
+      const cpx<T> c = A.coeff[A.items[A.item0 + (col >> 1)].coff + toff + r];
+      bs[((size_t)(r & 1) * NB + n) * bs_ld + (r >> 1)] = MT::cvt((float)((col & 1) ? c.y : c.x));
+    }
+  }
+  __syncthreads();
+
+  const TT* tabT = static_cast<const TT*>(A.tabT);
+  const int Jt = (h + 15) / 16;
+  for (int task = wave; task < 2 * Jt; task += 4) {
+    const int par = task / Jt, jt = task % Jt;
+    const int npar = (nr + 1 - par) / 2;
+    const int rpad = mma_rpad(npar);
+    const TT* trow = tabT + A.toffT[2 * m + par] + (size_t)(jt * 16 + li) * rpad + lg * KV;
+    f32x4_t acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < rpad; k0 += KS) {
+      TT a[KV];
+      MT::load_a(a, trow + k0, true);
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        const TT* bp = bs + ((size_t)par * NB + c * 16 + li) * bs_ld + k0 + lg * KV;
+        acc[c] = MT::mma(a, bp, acc[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const int col = c0 + c * 16 + li;
+      if (col >= ncol) continue;
+      cpx<T>* dst = A.spec + A.items[A.item0 + (col >> 1)].soff + (size_t)(2 * m + par) * h;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = jt * 16 + lg * 4 + i;
+        if (j < h) reinterpret_cast<T*>(&dst[j])[col & 1] = (T)acc[c][i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Per-item final reductions: cost, e_marg history and final residual, masses.
 // res[item*8 + .] = {cost, err, m(p), m(q), ||p||, 0, 0, 0}.
 // ---------------------------------------------------------------------------
@@ -1126,11 +1296,13 @@ __global__ void __launch_bounds__(256) reduce_kernel(RowArgs<T> A, int nchk_done
     for (int q = threadIdx.x; q < h; q += blockDim.x) fin += A.rhist[((size_t)it * A.nslot + A.chk_slot) * A.hs + q];
     fin = block_sum(fin, sh);
   }
-  for (int c = 0; c < nchk_done; ++c) {
+  // one wave per history slot (fixed summation order, no barriers)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wave; c < nchk_done; c += nw) {
     double e = 0.0;
-    for (int q = threadIdx.x; q < h; q += blockDim.x) e += A.rhist[((size_t)it * A.nslot + c) * A.hs + q];
-    e = block_sum(e, sh);
-    if (threadIdx.x == 0) ehist[(size_t)it * A.nslot + c] = sqrt(e) / pn;
+    for (int q = lane; q < h; q += 64) e += A.rhist[((size_t)it * A.nslot + c) * A.hs + q];
+    e = wave_sum(e);
+    if (lane == 0) ehist[(size_t)it * A.nslot + c] = sqrt(e) / pn;
   }
   if (threadIdx.x == 0) {
     double* r = res + (size_t)it * 8;
@@ -1177,6 +1349,25 @@ __global__ void __launch_bounds__(256) combine_kernel(const CombineDev* __restri
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// Optional start/stop events of the next row or Legendre launch: the events
+// are attached to the dispatch itself (hipExtLaunchKernelGGL), so they time
+// the kernel's execution rather than the gap before it.
+static thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+}
+
+#define SHOT_LAUNCH(kernel, grid, block, lds, stream, ...)                                         \
+  do {                                                                                             \
+    if (g_ev_start && g_ev_stop) {                                                                 \
+      hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, g_ev_start, g_ev_stop, 0, __VA_ARGS__); \
+    } else {                                                                                       \
+      hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                           \
+    }                                                                                              \
+    g_ev_start = g_ev_stop = nullptr;                                                              \
+  } while (0)
 template <typename T>
 hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream) {
   dim3 grid(a.h, nb);
@@ -1184,7 +1375,7 @@ hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream) {
   // two FFT buffers, plus the twiddles when they fit in 64 KiB of LDS
   b.tw_lds = (size_t)3 * a.nlon * sizeof(cpx<T>) <= 65536 - 512 ? 1 : 0;
   const size_t lds = (size_t)(b.tw_lds ? 3 : 2) * a.nlon * sizeof(cpx<T>);
-  hipLaunchKernelGGL(row_kernel<T>, grid, dim3(256), lds, stream, b);
+  SHOT_LAUNCH(row_kernel<T>, grid, dim3(256), lds, stream, b);
   return hipGetLastError();
 }
 
@@ -1192,7 +1383,7 @@ template <typename T, typename TT, int IB>
 static hipError_t launch_leg_ib(const LegArgs<T>& a, hipStream_t stream) {
   dim3 grid(a.L, (a.nb + IB - 1) / IB);
   const size_t lds = ((size_t)IB * 2 * a.h + (size_t)IB * a.L) * sizeof(cpx<T>);
-  hipLaunchKernelGGL((legendre_table_kernel<T, TT, IB>), grid, dim3(256), lds, stream, a);
+  SHOT_LAUNCH((legendre_table_kernel<T, TT, IB>), grid, dim3(256), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -1212,7 +1403,7 @@ static hipError_t launch_recur(const LegArgs<T>& a, hipStream_t stream) {
   dim3 grid(a.L, (a.nb + IB - 1) / IB);
   const int npad = (a.L + 15) / 16 * 16;
   const size_t lds = (size_t)npad * 16 + (size_t)IB * npad * 16 + (size_t)2 * (threads / 64) * 32 * sizeof(T);
-  hipLaunchKernelGGL((legendre_recur_kernel<T, IB, JPT>), grid, dim3(threads), lds, stream, a);
+  SHOT_LAUNCH((legendre_recur_kernel<T, IB, JPT>), grid, dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -1237,7 +1428,7 @@ static hipError_t launch_split(const LegArgs<T>& a, hipStream_t stream) {
   dim3 grid(a.L, (a.nb + IB - 1) / IB);
   const size_t npad = (a.L + 15) / 16 * 16 + 16;
   const size_t lds = npad * 16 + (size_t)IB * npad * 16 + (size_t)4 * IB * 2 * a.h * sizeof(cpx<T>);
-  hipLaunchKernelGGL((legendre_split_kernel<T, IB, C>), grid, dim3(256), lds, stream, a);
+  SHOT_LAUNCH((legendre_split_kernel<T, IB, C>), grid, dim3(256), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -1266,6 +1457,40 @@ hipError_t launch_legendre_split(const LegArgs<T>& a, int ib, hipStream_t stream
 }
 template hipError_t launch_legendre_split<float>(const LegArgs<float>&, int, hipStream_t);
 template hipError_t launch_legendre_split<double>(const LegArgs<double>&, int, hipStream_t);
+
+size_t mma_lds_bytes(int L, int hpad, int nt, int table_kind) {
+  const size_t es = table_kind == TAB_BF16 ? 2 : 4;
+  const size_t pad = table_kind == TAB_BF16 ? 8 : 1;
+  const size_t NB = 16 * nt, RP = mma_rpad((L + 1) / 2);
+  return es * 2 * NB * ((size_t)hpad + pad) + es * 2 * NB * (RP + pad);
+}
+
+template <typename T, typename TT, int NT>
+static hipError_t launch_mma_nt(const LegArgs<T>& a, hipStream_t stream) {
+  dim3 grid(a.L, (2 * a.nb + 16 * NT - 1) / (16 * NT));
+  const size_t lds = mma_lds_bytes(a.L, a.hpad, NT, sizeof(TT) == 2 ? TAB_BF16 : TAB_F32);
+  SHOT_LAUNCH((legendre_mma_kernel<T, TT, NT>), grid, dim3(256), lds, stream, a);
+  return hipGetLastError();
+}
+
+template <typename T, typename TT>
+static hipError_t launch_mma_tt(const LegArgs<T>& a, int nt, hipStream_t stream) {
+  switch (nt) {
+    case 1: return launch_mma_nt<T, TT, 1>(a, stream);
+    case 2: return launch_mma_nt<T, TT, 2>(a, stream);
+    default: return launch_mma_nt<T, TT, 4>(a, stream);
+  }
+}
+
+template <typename T>
+hipError_t launch_legendre_mma(const LegArgs<T>& a, int table_kind, int nt, hipStream_t stream) {
+  if (!a.tabT || a.hpad % 32) return hipErrorInvalidValue;
+  if (table_kind == TAB_BF16) return launch_mma_tt<T, unsigned short>(a, nt, stream);
+  if (table_kind == TAB_F32) return launch_mma_tt<T, float>(a, nt, stream);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_legendre_mma<float>(const LegArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_legendre_mma<double>(const LegArgs<double>&, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_legendre(const LegArgs<T>& a, int table_kind, int ib, hipStream_t stream) {

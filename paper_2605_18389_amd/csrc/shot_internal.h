@@ -98,6 +98,8 @@ template <typename T>
 struct LegArgs {
   int L, h, hpad;
   const void* tab;        // TABLE mode: [L(L+1)/2][hpad] P̄ rows
+  const void* tabT;       // TABLE mode, MFMA kernel: per (m, parity) block [round_up(h,16)][rpad] of P̄ transposed
+  const long long* toffT; // [2L] element offsets of those blocks
   const double* xs;       // RECURRENCE mode: h nodes
   const double* rcoef;    // [L(L+1)/2]
   const double* rgam;     // [L(L+1)/2]
@@ -114,6 +116,8 @@ struct LegArgs {
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the launch status.
+// set_launch_events: time the next row/Legendre launch with these events.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
 template <typename T>
 hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream);
 template <typename T>
@@ -123,6 +127,11 @@ int recur_jpt_valid(int h, int jpt);
 size_t split_lds_bytes(int L, int h, int ib, int real_bytes);
 template <typename T>
 hipError_t launch_legendre_split(const LegArgs<T>& a, int ib, hipStream_t stream);
+
+// Batched MFMA Legendre GEMM (table plans): nt column tiles of 16 per workgroup.
+template <typename T>
+hipError_t launch_legendre_mma(const LegArgs<T>& a, int table_kind, int nt, hipStream_t stream);
+size_t mma_lds_bytes(int L, int hpad, int nt, int table_kind);
 
 template <typename T>
 hipError_t launch_reduce(const RowArgs<T>& a, int nb, int nchk_done, double* res, double* ehist,

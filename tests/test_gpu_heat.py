@@ -112,3 +112,34 @@ def test_heat_apply_climate_grid_fp32():
     out = to_np(P.heat_apply(to_dev(p, P.dtype), [1e-4]))
     ref = O.heat_apply(p, g, 1e-4)
     assert rel_l2(out.reshape(ref.shape), ref) < 1e-5
+
+
+@pytest.mark.parametrize("prec,tiles,tol", [("fp32", 0, 1e-5), ("fp32", 1, 1e-5), ("fp32", 2, 1e-5),
+                                            ("bf16", 0, 1e-2), ("bf16", 4, 1e-2), ("bf16", -1, 1e-2)])
+@pytest.mark.parametrize("grid", [("gl", 90, 180, 90), ("cc", 33, 64, 32), ("gl", 17, 36, 18)])
+def test_batched_matrix_core_heat_apply(grid, prec, tiles, tol):
+    """Batches on table plans run the MFMA Legendre GEMM (fp32 or bf16 operands)."""
+    announce(f"mma heat_apply {grid} {prec} tiles={tiles}")
+    P = _plan([grid], prec, "table")
+    P.set_tuning(0, 0, tiles)
+    g = O.make_grid(*grid)
+    rng = np.random.default_rng(8)
+    B = 21
+    v = np.stack([synth.temperature_like(rng, g.x, g.w, g.nlon, K=6) for _ in range(B)])
+    t = 10.0 ** rng.uniform(-4, -2, B)
+    out = to_np(P.heat_apply(to_dev(v, P.dtype), t)).reshape(v.shape)
+    errs = []
+    for i in range(B):
+        ref = O.heat_apply(v[i], g, t[i])
+        errs.append(rel_l2(out[i], ref))
+    print(f"[mma] {grid} {prec} tiles={tiles} max rel L2 {max(errs):.3e}", flush=True)
+    assert max(errs) < tol
+    # analysis / synthesis through the same kernel keep the packed (m, l) layout
+    c = P.analysis(to_dev(v, P.dtype)).cpu().numpy().astype(np.complex128)
+    ntri = g.L * (g.L + 1) // 2
+    for i in (0, B - 1):
+        ref = np.concatenate(O.analysis(v[i], g))
+        assert np.abs(c[i * ntri:(i + 1) * ntri] - ref).max() <= 10 * tol * np.abs(ref).max()
+    back = to_np(P.synthesis(P.analysis(to_dev(v, P.dtype)))).reshape(v.shape)
+    ref = O.synthesis(O.analysis(v[3], g), g)
+    assert rel_l2(back[3], ref) < 10 * tol
