@@ -26,6 +26,14 @@ using namespace shot;
 
 namespace {
 
+// Work list of the row-split Legendre kernel (parts, their checkpoints).
+struct SplitSched {
+  SplitPartH* d_parts = nullptr;
+  double* d_ck = nullptr;
+  int* d_order = nullptr;     // [n] part run by workgroup column b
+  int n = 0, maxlen = 0, npb = 0;
+};
+
 struct GridRec {
   shot_grid_desc d{};
   int h = 0, hpad = 0;
@@ -39,7 +47,10 @@ struct GridRec {
   double* d_rcoef = nullptr;
   double* d_rgam = nullptr;
   double* d_rseed = nullptr;
-  double* d_rck = nullptr;
+  SplitSched sw;                     // one part per order
+  SplitSched ss;                     // long orders cut into parts (small batches)
+  int2* d_cut = nullptr;             // [L] (parts, first partial slot) of the cut work list
+  void* d_pbuf = nullptr;            // partial sums of cut orders, 4 chunks of 2 items
   void* d_aw = nullptr;
   void* d_tw = nullptr;
   int tune_ib = 0;   // Legendre items per workgroup (0 = automatic)
@@ -179,11 +190,15 @@ uint16_t to_bf16(double v) {
 
 void free_grid(GridRec& g) {
   for (void* p : {g.d_tab, g.d_tabT, (void*)g.d_toffT, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam,
-                  (void*)g.d_rseed, (void*)g.d_rck, g.d_aw, g.d_tw})
+                  (void*)g.d_rseed, (void*)g.sw.d_parts, (void*)g.sw.d_ck, (void*)g.ss.d_parts,
+                  (void*)g.ss.d_ck, (void*)g.sw.d_order, (void*)g.ss.d_order, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
     if (p) (void)hipFree(p);
-  g.d_tab = g.d_tabT = g.d_aw = g.d_tw = nullptr;
+  g.d_tab = g.d_tabT = g.d_aw = g.d_tw = g.d_pbuf = nullptr;
   g.d_toffT = nullptr;
-  g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = g.d_rck = nullptr;
+  g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = nullptr;
+  g.sw = SplitSched{};
+  g.ss = SplitSched{};
+  g.d_cut = nullptr;
 }
 
 shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) {
@@ -271,11 +286,41 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
     if (st != SHOT_OK) return st;
   } else {
     g.tab_kind = TAB_RECUR;
-    std::vector<double> coef, gam, seed, ck;
+    std::vector<double> coef, gam, seed;
     legendre_recurrence_data(d.L, xs, coef, gam, seed);
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    legendre_checkpoints(d.L, xs, coef, seed, ck, (int)hw);
-    if ((st = upload((void**)&g.d_rck, ck, s)) != SHOT_OK) return st;
+    // Row-split work lists: whole orders, and, for grids whose longest order
+    // does not fit the kernel's LDS, orders cut into the longest parts that do.
+    int part_rows = (d.L + 63) / 64 * 64;
+    while (part_rows > 64 && split_lds_bytes(part_rows, g.h, 1, f64 ? 8 : 4) > 60 * 1024) part_rows -= 64;
+    for (int k = 0; k < 2; ++k) {
+      SplitSched& S = k ? g.ss : g.sw;
+      std::vector<SplitPartH> parts;
+      std::vector<double> ck;
+      S.npb = split_schedule(d.L, k ? part_rows : 0, parts);
+      if (k && S.npb == 0) break;  // no order is longer than a part
+      S.n = (int)parts.size();
+      S.maxlen = 0;
+      for (const auto& q : parts) S.maxlen = std::max(S.maxlen, q.r_hi - q.r_lo);
+      legendre_checkpoints(d.L, xs, coef, seed, parts, ck, (int)hw);
+      // dispatch order: rows balanced over the 256 compute units
+      std::vector<int> wts;
+      for (const auto& q : parts) wts.push_back(q.r_hi - q.r_lo);
+      const std::vector<int> order = balanced_dispatch(wts, 256);
+      if ((st = upload((void**)&S.d_parts, parts, s)) != SHOT_OK) return st;
+      if ((st = upload((void**)&S.d_ck, ck, s)) != SHOT_OK) return st;
+      if ((st = upload((void**)&S.d_order, order, s)) != SHOT_OK) return st;
+      if (k) {
+        std::vector<int2> cut(d.L, make_int2(1, -1));
+        for (const auto& q : parts)
+          if (q.s == 0) cut[q.m] = make_int2(q.ns, q.pslot);
+        if ((st = upload((void**)&g.d_cut, cut, s)) != SHOT_OK) return st;
+      }
+    }
+    if (g.ss.n > 0) {
+      const size_t pb = (size_t)4 * 2 * g.ss.npb * 2 * g.h * (f64 ? 16 : 8);
+      HIP_TRY(hipMalloc(&g.d_pbuf, pb));
+    }
     if ((st = upload((void**)&g.d_xs, xs, s)) != SHOT_OK) return st;
     if ((st = upload((void**)&g.d_rcoef, coef, s)) != SHOT_OK) return st;
     if ((st = upload((void**)&g.d_rgam, gam, s)) != SHOT_OK) return st;
@@ -447,10 +492,20 @@ shot_status upload_items(shot_plan_s* P, const Layout& Lo, const int32_t* grid_o
   return SHOT_OK;
 }
 
+const SplitSched* leg_split(const shot_plan_s* P, const GridRec& g, int nb, int* ib_out);
+
 template <typename T>
-RowArgs<T> row_args(const GridRec& g, const Layout& Lo, const Group& G, const Work<T>& W, int nitems) {
+RowArgs<T> row_args(const shot_plan_s* P, const GridRec& g, const Layout& Lo, const Group& G, const Work<T>& W,
+                    int nitems) {
   RowArgs<T> a;
   std::memset(&a, 0, sizeof(a));
+  int cib = 1;
+  if (leg_split(P, g, G.count, &cib) == &g.ss) {  // spectra arrive with long orders in parts
+    a.cut = g.d_cut;
+    a.pbuf = g.d_pbuf;
+    a.npb = g.ss.npb;
+    a.cut_ib = cib;
+  }
   a.nlat = g.d.nlat;
   a.nlon = g.d.nlon;
   a.L = g.d.L;
@@ -492,7 +547,6 @@ LegArgs<T> leg_args(const GridRec& g, const Group& G, const Work<T>& W, int hl_s
   a.rcoef = g.d_rcoef;
   a.rgam = g.d_rgam;
   a.rseed = g.d_rseed;
-  a.rck = g.d_rck;
   a.item0 = G.first;
   a.nb = G.count;
   a.items = W.items;
@@ -521,11 +575,23 @@ int pick_ib(const shot_plan_s* P, const GridRec& g, int count) {
   return ib;
 }
 
+// Row-split work list for a launch of nb items, ib per workgroup: whole
+// orders, or orders cut into parts when only the cut list fits in LDS (at most
+// 4 chunks: the partial buffer is sized for that); nullptr when neither fits.
+const SplitSched* pick_sched(const shot_plan_s* P, const GridRec& g, int nb, int ib) {
+  const int rb = P->prec == SHOT_FP64 ? 8 : 4;
+  const int chunks = (nb + ib - 1) / ib;
+  const bool cut_ok = g.ss.n > 0 && chunks <= 4 && split_lds_bytes(g.ss.maxlen, g.h, ib, rb) <= 60 * 1024;
+  const bool whole_ok = g.sw.n > 0 && split_lds_bytes(g.sw.maxlen, g.h, ib, rb) <= 60 * 1024;
+  if (cut_ok && !whole_ok) return &g.ss;
+  return whole_ok ? &g.sw : nullptr;
+}
+
 // Row-split recurrence kernel: used unless a chains-per-thread tuning selects
 // the latitude-split kernel, when ceil(nlat/2) <= 384 and its LDS fits.
 bool use_split(const shot_plan_s* P, const GridRec& g) {
   if (g.tab_kind != TAB_RECUR || g.tune_jpt != 0 || g.h > 384) return false;
-  return split_lds_bytes(g.d.L, g.h, 1, P->prec == SHOT_FP64 ? 8 : 4) <= 60 * 1024;
+  return pick_sched(P, g, 1, 1) != nullptr;
 }
 
 // Matrix-core kernel for table grids: column tiles per workgroup, or 0 for
@@ -546,7 +612,7 @@ int mma_tiles(const shot_plan_s* P, const GridRec& g, int count) {
 
 int split_ib(const shot_plan_s* P, const GridRec& g, int count) {
   int ib = (g.tune_ib == 2 || (g.tune_ib == 0 && count >= 2)) ? 2 : 1;
-  if (ib == 2 && split_lds_bytes(g.d.L, g.h, 2, P->prec == SHOT_FP64 ? 8 : 4) > 60 * 1024) ib = 1;
+  if (ib == 2 && !pick_sched(P, g, count, 2)) ib = 1;
   return ib;
 }
 
@@ -557,15 +623,31 @@ shot_status run_rows(shot_plan_s* P, const RowArgs<T>& a, int nb, hipStream_t s)
   return e == hipSuccess ? SHOT_OK : hip_fail(e, "row kernel launch", __LINE__);
 }
 
+// Row-split work list of a Legendre launch of nb items (nullptr when another
+// kernel runs it) and its items per workgroup.
+const SplitSched* leg_split(const shot_plan_s* P, const GridRec& g, int nb, int* ib_out) {
+  if (mma_tiles(P, g, nb) > 0 || !use_split(P, g)) return nullptr;
+  const int ib = split_ib(P, g, nb);
+  if (ib_out) *ib_out = ib;
+  return pick_sched(P, g, nb, ib);
+}
+
 template <typename T>
 shot_status run_leg(shot_plan_s* P, const GridRec& g, LegArgs<T> a, hipStream_t s) {
   ProfScope ps(P, s, 0);
   hipError_t e;
+  int ib = 1;
   const int nt = mma_tiles(P, g, a.nb);
   if (nt > 0) {
     e = launch_legendre_mma<T>(a, g.tab_kind, nt, s);
-  } else if (use_split(P, g)) {
-    const int ib = split_ib(P, g, a.nb);
+  } else if (const SplitSched* S = leg_split(P, g, a.nb, &ib)) {
+    a.parts = S->d_parts;
+    a.order = S->d_order;
+    a.nparts = S->n;
+    a.maxlen = S->maxlen;
+    a.rck = S->d_ck;
+    a.npb = S->npb;
+    a.pbuf = g.d_pbuf;
     e = launch_legendre_split<T>(a, ib, s);
   } else {
     const int ib = pick_ib(P, g, a.nb);
@@ -594,7 +676,7 @@ shot_status heat_apply_impl(shot_plan_s* P, const int32_t* goi, int nitems, cons
   ST_TRY(upload_items<T>(P, Lo, goi, {}, {}, tv, {}, {}, W, s));
   for (const Group& G : Lo.groups) {
     const GridRec& g = P->grids[G.grid];
-    RowArgs<T> a = row_args<T>(g, Lo, G, W, nitems);
+    RowArgs<T> a = row_args<T>(P, g, Lo, G, W, nitems);
     a.mode = ROW_FWD;
     a.in = static_cast<const T*>(v);
     a.wts_in = transpose ? 0 : 1;
@@ -619,7 +701,7 @@ shot_status sht_impl(shot_plan_s* P, const int32_t* goi, int nitems, const void*
   ST_TRY(upload_items<T>(P, Lo, goi, {}, {}, tv, {}, {}, W, s));
   for (const Group& G : Lo.groups) {
     const GridRec& g = P->grids[G.grid];
-    RowArgs<T> a = row_args<T>(g, Lo, G, W, nitems);
+    RowArgs<T> a = row_args<T>(P, g, Lo, G, W, nitems);
     LegArgs<T> la = leg_args<T>(g, G, W, Lo.Lmax);
     if (analysis) {
       a.mode = ROW_FWD;
@@ -698,7 +780,7 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
   };
   hipStream_t ls = s;  // launch stream (the capture stream while recording a graph)
   auto rows = [&](const Group& G, const GridRec& g, int mode, int k, int chk) {
-    RowArgs<T> a = row_args<T>(g, Lo, G, W, nitems);
+    RowArgs<T> a = row_args<T>(P, g, Lo, G, W, nitems);
     a.mode = mode;
     a.k = k;
     a.chk_slot = chk;
@@ -783,7 +865,7 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
     if (tol > 0 && chk_prev) {
       // e_marg of iteration k-1 is complete: decide before the v-half
       for (const Group& G : Lo.groups) {
-        RowArgs<T> a = row_args<T>(P->grids[G.grid], Lo, G, W, nitems);
+        RowArgs<T> a = row_args<T>(P, P->grids[G.grid], Lo, G, W, nitems);
         HIP_TRY(launch_reduce<T>(a, G.count, slot + 1, W.res, W.ehist, s));
       }
       std::vector<double> eh((size_t)nitems * nslot);
@@ -821,7 +903,7 @@ shot_status finish_solve(shot_plan_s* P, const Layout& Lo, Work<T>& W, int nitem
                          int final_slot, double tol, T* phi, T* psi, shot_solve_info* info,
                          double* mass_out, hipStream_t s) {
   for (const Group& G : Lo.groups) {
-    RowArgs<T> a = row_args<T>(P->grids[G.grid], Lo, G, W, nitems);
+    RowArgs<T> a = row_args<T>(P, P->grids[G.grid], Lo, G, W, nitems);
     a.mode = ROW_FINAL;
     a.k = K;
     a.out = phi;
@@ -830,7 +912,7 @@ shot_status finish_solve(shot_plan_s* P, const Layout& Lo, Work<T>& W, int nitem
   }
   const int nchk_done = K / C;
   for (const Group& G : Lo.groups) {
-    RowArgs<T> a = row_args<T>(P->grids[G.grid], Lo, G, W, nitems);
+    RowArgs<T> a = row_args<T>(P, P->grids[G.grid], Lo, G, W, nitems);
     a.chk_slot = final_slot;
     HIP_TRY(launch_reduce<T>(a, G.count, nchk_done, W.res, W.ehist, s));
   }
@@ -1005,7 +1087,7 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
   double* adjp = reinterpret_cast<double*>(b + o_adjp);
 
   auto base_args = [&](const Group& G, const GridRec& g) {
-    RowArgs<T> a = row_args<T>(g, Lo, G, W, nitems);
+    RowArgs<T> a = row_args<T>(P, g, Lo, G, W, nitems);
     a.gA = gA;
     a.gB = gB;
     a.adjp = adjp;

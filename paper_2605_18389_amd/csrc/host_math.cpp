@@ -2,6 +2,8 @@
 #include "host_math.h"
 
 #include <algorithm>
+#include <numeric>
+#include <queue>
 #include <cmath>
 #include <thread>
 
@@ -161,6 +163,136 @@ void legendre_recurrence_data(int L, const std::vector<double>& x, std::vector<d
       seed[(int64_t)m * nx + j] = pmm;
     }
   }
+}
+
+}  // namespace shot
+
+namespace shot {
+
+int split_schedule(int L, int part_rows, std::vector<SplitPartH>& parts) {
+  parts.clear();
+  int nslot = 0;
+  for (int m = 0; m < L; ++m) {
+    const int nr = L - m;
+    const int pr = part_rows > 0 ? part_rows : nr;
+    const int ns = (nr + pr - 1) / pr;
+    for (int s = 0; s < ns; ++s) {
+      const int lo = s * pr, hi = std::min(nr, lo + pr);
+      parts.push_back({m, lo, hi, s, ns, ns > 1 ? nslot + s : -1});
+    }
+    if (ns > 1) nslot += ns;
+  }
+  std::stable_sort(parts.begin(), parts.end(), [](const SplitPartH& a, const SplitPartH& b) {
+    return a.r_hi - a.r_lo > b.r_hi - b.r_lo;
+  });
+  return nslot;
+}
+
+std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu) {
+  const int n = (int)weight.size();
+  std::vector<int> order(n);
+  for (int b = 0; b < n; ++b) order[b] = b;
+  if (n <= ncu) return order;
+  // items by decreasing weight
+  std::vector<int> items(n);
+  std::iota(items.begin(), items.end(), 0);
+  std::stable_sort(items.begin(), items.end(), [&](int a, int b) { return weight[a] > weight[b]; });
+  const int rounds = (n + ncu - 1) / ncu;
+  std::vector<int> cap(ncu, 0);
+  for (int s = 0; s < ncu; ++s)
+    for (int r = 0; r < rounds; ++r)
+      if (r * ncu + s < n) ++cap[s];
+  double total = 0;
+  for (int w : weight) total += w;
+  const double target = total / ncu;
+  std::vector<std::vector<int>> slot(ncu);
+  std::vector<long long> load(ncu, 0);
+  std::vector<char> used(n, 0);
+  size_t next = 0;
+  const int cmin = *std::min_element(cap.begin(), cap.end());
+  const int cmax = *std::max_element(cap.begin(), cap.end());
+  if (cmin < cmax) {
+    for (int s = 0; s < ncu; ++s) {
+      if (cap[s] != cmin) continue;
+      while (used[items[next]]) ++next;
+      const int a = items[next];
+      used[a] = 1;
+      slot[s].push_back(a);
+      load[s] += weight[a];
+      for (int k = 1; k < cmin; ++k) {
+        const double need = target - (double)load[s];
+        int best = -1;
+        for (int i = 0; i < n; ++i)
+          if (!used[i] && (best < 0 || std::fabs(weight[i] - need) < std::fabs(weight[best] - need))) best = i;
+        used[best] = 1;
+        slot[s].push_back(best);
+        load[s] += weight[best];
+      }
+    }
+  }
+  using E = std::pair<long long, int>;
+  std::priority_queue<E, std::vector<E>, std::greater<E>> pq;
+  for (int s = 0; s < ncu; ++s)
+    if ((int)slot[s].size() < cap[s]) pq.push({load[s], s});
+  for (int i : items) {
+    if (used[i]) continue;
+    const E e = pq.top();
+    pq.pop();
+    const int s = e.second;
+    slot[s].push_back(i);
+    load[s] += weight[i];
+    used[i] = 1;
+    if ((int)slot[s].size() < cap[s]) pq.push({load[s], s});
+  }
+  for (int s = 0; s < ncu; ++s) {
+    std::stable_sort(slot[s].begin(), slot[s].end(), [&](int a, int b) { return weight[a] > weight[b]; });
+    for (int r = 0; r < (int)slot[s].size(); ++r) order[r * ncu + s] = slot[s][r];
+  }
+  return order;
+}
+
+void legendre_checkpoints(int L, const std::vector<double>& x, const std::vector<double>& coef,
+                          const std::vector<double>& seed, const std::vector<SplitPartH>& parts,
+                          std::vector<double>& ck, int nthreads) {
+  const int nx = (int)x.size();
+  const size_t np = parts.size();
+  ck.assign(np * 4 * nx * 2, 0.0);
+  // wave starts grouped by order, in increasing row
+  std::vector<std::vector<std::pair<int, size_t>>> by_m(L);
+  for (size_t k = 0; k < np; ++k) {
+    const SplitPartH& P = parts[k];
+    const int len = P.r_hi - P.r_lo;
+    for (int w = 0; w < 4; ++w) {
+      const int r0 = P.r_lo + split_row(len, w);
+      if (r0 < P.r_hi) by_m[P.m].push_back({r0, k * 4 + w});
+    }
+  }
+  for (auto& v : by_m) std::sort(v.begin(), v.end());
+  nthreads = std::max(1, nthreads);
+  std::vector<std::thread> pool;
+  for (int tid = 0; tid < nthreads; ++tid) {
+    pool.emplace_back([&, tid]() {
+      for (int m = tid; m < L; m += nthreads) {
+        const double* c = coef.data() + tri_offset(m, L);
+        for (int j = 0; j < nx; ++j) {
+          double r1 = seed[(size_t)m * nx + j], r2 = 0.0;
+          int r = 0;
+          for (const auto& st : by_m[m]) {
+            while (r < st.first) {
+              ++r;
+              const double rn = std::fma(c[r] * x[j], r1, r2);
+              r2 = r1;
+              r1 = rn;
+            }
+            double* dst = ck.data() + (st.second * nx + j) * 2;
+            dst[0] = r1;
+            dst[1] = r2;
+          }
+        }
+      }
+    });
+  }
+  for (auto& t : pool) t.join();
 }
 
 }  // namespace shot

@@ -60,12 +60,37 @@ void legendre_rows(int L, const std::vector<double>& x, int ld, std::vector<doub
 void legendre_recurrence_data(int L, const std::vector<double>& x, std::vector<double>& coef,
                               std::vector<double>& gam, std::vector<double>& seed);
 
-// Recurrence checkpoints for the row-split kernel: for every order m, wave
-// w = 0..3 and node j, the pair (R_{r0}, R_{r0-1}) of the rescaled recurrence
-// at r0 = split_row(L - m, w), stored at ck[((m*4 + w)*nx + j)*2 + {0,1}]
-// ((0, 0) when the wave has no rows).  Evaluated with the same fused
-// multiply-adds as the device recurrence.
+// One work item of the row-split Legendre kernel: rows [r_lo, r_hi) (row
+// r = l - m) of order m, part s of the order's ns parts.  Parts of an order
+// that has more than one sit at consecutive partial-buffer slots
+// pslot - s .. pslot - s + ns - 1 (pslot = -1 when ns == 1).
+struct SplitPartH {
+  int m, r_lo, r_hi, s, ns, pslot;
+};
+
+// Work list for the row-split kernel: every order cut into parts of at most
+// `part_rows` rows (a multiple of 64; <= 0: one part per order), sorted by
+// decreasing length so that the longest work is dispatched first.  Returns the
+// number of partial-buffer slots (parts of orders with ns > 1).
+int split_schedule(int L, int part_rows, std::vector<SplitPartH>& parts);
+
+// Dispatch order for the row-split kernel when every workgroup of a launch
+// is resident at once: workgroup b lands on compute-unit slot b % ncu in
+// round b / ncu, so the items dealt to one slot run side by side.  Returns
+// order (a permutation of the item indices) such that the weights summed per
+// slot are nearly equal: slots with fewer rounds take the heaviest items,
+// each topped up toward the mean with the best-fitting remaining item; the
+// others are filled heaviest first onto the least loaded slot; within a slot
+// the heaviest item runs in round 0.
+std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu);
+
+// Recurrence checkpoints for the row-split kernel: for every part k and wave
+// w = 0..3 of its workgroup, the pair (R_{r0}, R_{r0-1}) of the rescaled
+// recurrence at the wave's first row r0 = r_lo + split_row(r_hi - r_lo, w),
+// stored at ck[((k*4 + w)*nx + j)*2 + {0,1}] ((0, 0) when the wave has no
+// rows).  Evaluated with the same fused multiply-adds as the device recurrence.
 void legendre_checkpoints(int L, const std::vector<double>& x, const std::vector<double>& coef,
-                          const std::vector<double>& seed, std::vector<double>& ck, int nthreads);
+                          const std::vector<double>& seed, const std::vector<SplitPartH>& parts,
+                          std::vector<double>& ck, int nthreads);
 
 }  // namespace shot

@@ -299,6 +299,33 @@ __device__ double gauge(const RowArgs<T>& A, const ItemDev& I, int it, int k, do
   return exp(-c / I.eps);
 }
 
+// Folded spectrum entry (E, O) of order m and row pair jp of item `it`: read
+// from the spectrum, or, for an order that the preceding Legendre launch cut
+// into parts, the sum of the parts' partial sums taken in part order.
+template <typename T>
+__device__ __forceinline__ void load_spec_pair(const RowArgs<T>& A, const cpx<T>* spec, int it, int m, int jp,
+                                               cpx<T>& ge, cpx<T>& go) {
+  if (A.cut) {
+    const int2 c = A.cut[m];
+    if (c.x > 1) {
+      const int rel = it - A.item0, chunk = rel / A.cut_ib, i = rel - chunk * A.cut_ib;
+      const cpx<T>* pb = static_cast<const cpx<T>*>(A.pbuf) + (size_t)chunk * A.npb * A.cut_ib * 2 * A.h +
+                         (size_t)i * 2 * A.h + 2 * jp;
+      ge = {(T)0, (T)0};
+      go = {(T)0, (T)0};
+      for (int p = 0; p < c.x; ++p) {
+        const cpx<T>* q = pb + (size_t)(c.y + p) * A.cut_ib * 2 * A.h;
+        ge = cadd(ge, q[0]);
+        go = cadd(go, q[1]);
+      }
+      return;
+    }
+  }
+  const cpx<T>* sp = spec + ((size_t)m * A.h + jp) * 2;
+  ge = sp[0];
+  go = sp[1];
+}
+
 // Bijection of [0, h): workgroup b runs on XCD b % 8; XCD x gets the
 // contiguous row-pair range starting at x*(h/8) + min(x, h%8).
 __device__ __forceinline__ int xcd_row_pair(int b, int h) {
@@ -434,11 +461,7 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
       const int m = idx / RPW, pr = idx - m * RPW;
       const int jp = jp0 + pr;
       cpx<T> ge = {(T)0, (T)0}, go = {(T)0, (T)0};
-      if (pr < np) {
-        const cpx<T>* sp = spec + ((size_t)m * h + jp) * 2;
-        ge = sp[0];
-        go = sp[1];
-      }
+      if (pr < np) load_spec_pair(A, spec, it, m, jp, ge, go);
       const bool eq = (jp == nlat - 1 - jp);
       const cpx<T> a = cadd(ge, go);
       const cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : csub(ge, go);
@@ -759,11 +782,7 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
     const int m = idx / RPW, pr = idx - m * RPW;
     const int jp = jp0 + pr;
     cpx<T> ge = {(T)0, (T)0}, go = {(T)0, (T)0};
-    if (pr < np) {
-      const cpx<T>* sp = spec + ((size_t)m * h + jp) * 2;
-      ge = sp[0];
-      go = sp[1];
-    }
+    if (pr < np) load_spec_pair(A, spec, it, m, jp, ge, go);
     const bool eq = (jp == nlat - 1 - jp);
     const cpx<T> a = cadd(ge, go);
     const cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : csub(ge, go);
@@ -1076,6 +1095,46 @@ __device__ __forceinline__ R dpp_any(R v, int sel) {
   else return dpp_d(v, sel);
 }
 
+// NV (16 or 32) values per lane -> lane L holds the wave sum of value
+// L >> (6 - log2 NV): each stage halves the values a lane keeps while doubling
+// the lanes summed, so NV - 1 adds and exchanges in total.
+template <typename R, int NV>
+__device__ __forceinline__ R transpose_reduce(R* a, int lane) {
+  static_assert(NV == 16 || NV == 32, "NV");
+#pragma unroll
+  for (int i = 0; i < NV / 2; ++i) a[i] = swap_add32(a[i], a[NV / 2 + i]);   // lane bit 5
+#pragma unroll
+  for (int i = 0; i < NV / 4; ++i) a[i] = swap_add16(a[i], a[NV / 4 + i]);   // lane bit 4
+  {
+    const bool up = (lane & 8) != 0;                                          // lane bit 3
+#pragma unroll
+    for (int i = 0; i < NV / 8; ++i) {
+      const R send = up ? a[i] : a[NV / 8 + i];
+      const R keep = up ? a[NV / 8 + i] : a[i];
+      a[i] = keep + dpp_any(send, 0);
+    }
+  }
+  {
+    const bool up = (lane & 4) != 0;                                          // lane bit 2
+#pragma unroll
+    for (int i = 0; i < NV / 16; ++i) {
+      const R send = up ? a[i] : a[NV / 16 + i];
+      const R keep = up ? a[NV / 16 + i] : a[i];
+      a[i] = keep + dpp_any(send, 1);
+    }
+  }
+  if constexpr (NV == 32) {
+    const bool up = (lane & 2) != 0;                                          // lane bit 1
+    const R send = up ? a[0] : a[1];
+    const R keep = up ? a[1] : a[0];
+    a[0] = keep + dpp_any(send, 2);
+  } else {
+    a[0] += dpp_any(a[0], 2);
+  }
+  a[0] += dpp_any(a[0], 3);                                                   // lane bit 0
+  return a[0];
+}
+
 // 32 values per lane -> lane L holds the wave sum of value (L >> 1).
 template <typename R>
 __device__ __forceinline__ R transpose_reduce32(R* a, int lane) {
@@ -1277,52 +1336,66 @@ __global__ void __launch_bounds__(256) legendre_recur_kernel(LegArgs<T> A) {
 // ---------------------------------------------------------------------------
 // Row-split recurrence Legendre kernel.
 //
-// One workgroup (4 waves) per order m and item chunk.  Every lane owns the C
-// latitude chains j = lane + 64 c, and the rows l = m..L-1 are split into
-// four contiguous ranges, one per wave.  A wave resumes the rescaled
-// recurrence at the start of its range from a plan-time checkpoint
-// (R_{r0}, R_{r0-1}) per (m, wave, j): 4 states per (m, j), i.e. O(n) memory.
-// Analysis sums over j are complete within a wave (C chains per lane, then a
-// wave transpose-reduction), so the analysis loop has no barrier; synthesis
-// partial sums of the four waves are combined once through LDS.
+// One workgroup (4 waves) per part of an order m (rows [r_lo, r_hi) of the
+// order, taken from a host work list in a host-chosen dispatch order) and
+// item chunk.  Every
+// lane owns the C latitude chains j = lane + 64 c, and the part's rows are
+// split into four contiguous ranges, one per wave.  A wave resumes the
+// rescaled recurrence at the start of its range from a plan-time checkpoint
+// (R_{r0}, R_{r0-1}).  Analysis sums over j are complete within a wave (C
+// chains per lane, then a wave transpose-reduction), so the analysis loop has
+// no barrier and a part needs no other part's analysis.  Synthesis partial
+// sums of the four waves are combined once through LDS; an order cut into
+// several parts (so that long orders spread over several compute units) has
+// each part store its sum to a partial buffer; the consumer adds the parts in
+// part order, which keeps the result independent of timing.
 // ---------------------------------------------------------------------------
 
-template <typename T, int IB, int C>
-__global__ void __launch_bounds__(256) legendre_split_kernel(LegArgs<T> A) {
+// Three waves per SIMD where the registers allow it without spilling: then
+// a launch of up to 3 x 256 workgroups is resident at once, and the host's
+// dispatch order balances the rows that meet on one compute unit.
+template <typename T, int IB, int C, int NV>
+__global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel(LegArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using R = T;
-  constexpr int RB = 16 / IB;
-  constexpr int V = 2 * RB * IB;
+  constexpr int RB = NV / (2 * IB);
+  constexpr int V = NV;
   const int L = A.L, h = A.h;
-  const int m = blockIdx.x;
+  const int part = A.order[blockIdx.x];
+  const SplitPartH P = A.parts[part];
+  const int m = P.m;
   const int nr = L - m;
-  const int npad = (nr + 15) / 16 * 16 + 16;  // one extra block: the look-ahead coefficient
+  const int len = P.r_hi - P.r_lo;
+  const int npl = (len + 15) / 16 * 16 + 16;  // one extra block: the look-ahead coefficient
   const int ib0 = blockIdx.y * IB;
   const int nbi = min(IB, A.nb - ib0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* cf = reinterpret_cast<double*>(smem_raw);
-  double* gm = cf + npad;
-  double2* bs = reinterpret_cast<double2*>(gm + npad);               // [IB][npad]
-  cpx<T>* gpart = reinterpret_cast<cpx<T>*>(bs + (size_t)IB * npad);  // [4][IB][h][2]
+  const int maxpl = (A.maxlen + 15) / 16 * 16 + 16;
+  double* cf = reinterpret_cast<double*>(smem_raw);                   // [maxpl], local row index
+  double* gm = cf + maxpl;
+  double2* bs = reinterpret_cast<double2*>(gm + maxpl);               // [IB][maxpl]
+  cpx<T>* gpart = reinterpret_cast<cpx<T>*>(bs + (size_t)IB * maxpl);  // [4][IB][h][2]
   const long long toff = tri_off(m, L);
-  const int r_lo = split_row(nr, wave), r_hi = split_row(nr, wave + 1);
+  const int r_lo = P.r_lo + split_row(len, wave), r_hi = P.r_lo + split_row(len, wave + 1);
 
-  for (int r = tid; r < npad; r += 256) {
-    cf[r] = (r < nr && r > 0) ? A.rcoef[toff + r] : 0.0;
-    gm[r] = (r < nr) ? A.rgam[toff + r] : 0.0;
+  for (int q = tid; q < npl; q += 256) {
+    const int r = P.r_lo + q;
+    cf[q] = (r < nr && r > 0) ? A.rcoef[toff + r] : 0.0;
+    gm[q] = (r < nr) ? A.rgam[toff + r] : 0.0;
   }
   for (int i = 0; i < IB; ++i)
-    for (int r = tid; r < npad; r += 256) bs[(size_t)i * npad + r] = make_double2(0.0, 0.0);
+    for (int q = tid; q < npl; q += 256) bs[(size_t)i * maxpl + q] = make_double2(0.0, 0.0);
 
   double xj[C];
-  double2 ck[C];
-  const double2* ckp = reinterpret_cast<const double2*>(A.rck) + ((size_t)m * 4 + wave) * h;
+  const double2* ckp = reinterpret_cast<const double2*>(A.rck) + ((size_t)part * 4 + wave) * h;
+  auto checkpoint = [&](int c) {
+    const int j = lane + 64 * c;
+    return j < h ? ckp[j] : make_double2(0.0, 0.0);
+  };
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int j = lane + 64 * c;
-    const bool act = j < h;
-    xj[c] = act ? A.xs[j] : 0.0;
-    ck[c] = act ? ckp[j] : make_double2(0.0, 0.0);
+    xj[c] = j < h ? A.xs[j] : 0.0;
   }
   __syncthreads();
 
@@ -1345,19 +1418,24 @@ __global__ void __launch_bounds__(256) legendre_split_kernel(LegArgs<T> A) {
     }
     double R1[C], R2[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) { R1[c] = ck[c].x; R2[c] = ck[c].y; }
+    for (int c = 0; c < C; ++c) {
+      const double2 ck = checkpoint(c);
+      R1[c] = ck.x;
+      R2[c] = ck.y;
+    }
     for (int r0 = r_lo; r0 < r_hi; r0 += RB) {
       double acc[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] = 0.0;
+      const double* cfr = cf + (r0 - P.r_lo) + 1;  // coefficient of the next row
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) {
-        const double cn = cf[r0 + rr + 1];  // coefficient of the next row
+        const double cn = cfr[rr];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
 #pragma unroll
           for (int i = 0; i < IB; ++i) {
-            const double2 y = (rr & 1) ? yO[c][i] : yE[c][i];  // r0 - r_lo is even and r_lo is even
+            const double2 y = (rr & 1) ? yO[c][i] : yE[c][i];  // every range starts on an even row
             acc[(rr * IB + i) * 2 + 0] = fma(R1[c], y.x, acc[(rr * IB + i) * 2 + 0]);
             acc[(rr * IB + i) * 2 + 1] = fma(R1[c], y.y, acc[(rr * IB + i) * 2 + 1]);
           }
@@ -1369,14 +1447,16 @@ __global__ void __launch_bounds__(256) legendre_split_kernel(LegArgs<T> A) {
       R red[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) red[v] = (R)acc[v];
-      const R s = transpose_reduce32<R>(red, lane);
-      if ((lane & 1) == 0) {
-        const int vv = lane >> 1, comp = vv & 1, i = (vv >> 1) % IB, rr = (vv >> 1) / IB, r = r0 + rr;
-        if (r < nr && i < nbi) {
-          const double g = gm[r];
+      const R s = transpose_reduce<R, NV>(red, lane);
+      constexpr int SH = NV == 32 ? 1 : 2;
+      if ((lane & ((1 << SH) - 1)) == 0) {
+        const int vv = lane >> SH, comp = vv & 1, i = (vv >> 1) % IB, rr = (vv >> 1) / IB, r = r0 + rr;
+        if (r < r_hi && i < nbi) {
+          const int q = r - P.r_lo;
+          const double g = gm[q];
           if (A.mode == 0) {
             const double sc = g * g * (double)A.hl[(size_t)(A.item0 + ib0 + i) * A.hl_stride + m + r];
-            reinterpret_cast<double*>(&bs[(size_t)i * npad + r])[comp] = (double)s * sc;
+            reinterpret_cast<double*>(&bs[(size_t)i * maxpl + q])[comp] = (double)s * sc;
           } else {
             T* dst = reinterpret_cast<T*>(&A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r]);
             dst[comp] = (T)((double)s * g);
@@ -1387,9 +1467,9 @@ __global__ void __launch_bounds__(256) legendre_split_kernel(LegArgs<T> A) {
     if (A.mode == 1) return;
   } else {
     for (int i = 0; i < nbi; ++i)
-      for (int r = tid; r < nr; r += 256) {
-        const cpx<T> c = A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r];
-        bs[(size_t)i * npad + r] = make_double2((double)c.x * gm[r], (double)c.y * gm[r]);
+      for (int q = tid; q < len; q += 256) {
+        const cpx<T> c = A.coeff[A.items[A.item0 + ib0 + i].coff + toff + P.r_lo + q];
+        bs[(size_t)i * maxpl + q] = make_double2((double)c.x * gm[q], (double)c.y * gm[q]);
       }
   }
   __syncthreads();
@@ -1399,19 +1479,20 @@ __global__ void __launch_bounds__(256) legendre_split_kernel(LegArgs<T> A) {
   double R1[C], R2[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    R1[c] = ck[c].x;
-    R2[c] = ck[c].y;
+    const double2 ck = checkpoint(c);
+    R1[c] = ck.x;
+    R2[c] = ck.y;
 #pragma unroll
     for (int i = 0; i < IB; ++i) { gE[c][i] = make_double2(0.0, 0.0); gO[c][i] = make_double2(0.0, 0.0); }
   }
   for (int r0 = r_lo; r0 < r_hi; r0 += 16) {
+    const int q0 = r0 - P.r_lo;
 #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
-      const int r = r0 + rr;
-      const double cn = cf[r + 1];
+      const double cn = cf[q0 + rr + 1];
       double2 b[IB];
 #pragma unroll
-      for (int i = 0; i < IB; ++i) b[i] = bs[(size_t)i * npad + r];
+      for (int i = 0; i < IB; ++i) b[i] = bs[(size_t)i * maxpl + q0 + rr];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
 #pragma unroll
@@ -1443,8 +1524,23 @@ __global__ void __launch_bounds__(256) legendre_split_kernel(LegArgs<T> A) {
     }
   }
   __syncthreads();
+  if (P.ns == 1) {
+    for (int i = 0; i < nbi; ++i) {
+      cpx<T>* dst = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+      for (int q = tid; q < 2 * h; q += 256) {
+        cpx<T> s = {(T)0, (T)0};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) s = cadd(s, gpart[(((size_t)w * IB + i) * 2) * h + q]);
+        dst[q] = s;
+      }
+    }
+    return;
+  }
+  // order cut into parts: store this part's sum; the row kernel that reads
+  // the spectrum next adds the parts of the order in part order
+  cpx<T>* pb = static_cast<cpx<T>*>(A.pbuf) + (size_t)blockIdx.y * A.npb * IB * 2 * h;
   for (int i = 0; i < nbi; ++i) {
-    cpx<T>* dst = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+    cpx<T>* dst = pb + ((size_t)P.pslot * IB + i) * 2 * h;
     for (int q = tid; q < 2 * h; q += 256) {
       cpx<T> s = {(T)0, (T)0};
 #pragma unroll
@@ -1839,10 +1935,9 @@ int recur_jpt_valid(int h, int jpt) {
 
 template <typename T, int IB, int C>
 static hipError_t launch_split(const LegArgs<T>& a, hipStream_t stream) {
-  dim3 grid(a.L, (a.nb + IB - 1) / IB);
-  const size_t npad = (a.L + 15) / 16 * 16 + 16;
-  const size_t lds = npad * 16 + (size_t)IB * npad * 16 + (size_t)4 * IB * 2 * a.h * sizeof(cpx<T>);
-  SHOT_LAUNCH((legendre_split_kernel<T, IB, C>), grid, dim3(256), lds, stream, a);
+  dim3 grid(a.nparts, (a.nb + IB - 1) / IB);
+  const size_t lds = split_lds_bytes(a.maxlen, a.h, IB, (int)sizeof(T));
+  SHOT_LAUNCH((legendre_split_kernel<T, IB, C, 32>), grid, dim3(256), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -1859,8 +1954,8 @@ static hipError_t launch_split_ib(const LegArgs<T>& a, hipStream_t stream) {
   }
 }
 
-size_t split_lds_bytes(int L, int h, int ib, int real_bytes) {
-  const size_t npad = (L + 15) / 16 * 16 + 16;
+size_t split_lds_bytes(int maxlen, int h, int ib, int real_bytes) {
+  const size_t npad = (maxlen + 15) / 16 * 16 + 16;
   return npad * 16 + (size_t)ib * npad * 16 + (size_t)4 * ib * 2 * h * 2 * real_bytes;
 }
 

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "host_math.h"
+
 namespace shot {
 
 template <typename T>
@@ -81,6 +83,12 @@ struct RowArgs {
   const double* gk;   // [nitems] SINK_U: gauge of iteration k-1 to use instead of the partial sums;
                       // adjoint modes: s of the iteration whose u-hat / v-hat are read
   int kT;             // adjoint: last iteration T (its u-bar term enters ROW_ADJ_A)
+  // spectrum written by a row-split Legendre launch that cut long orders into
+  // parts: cut[m] = (parts, first partial slot); nullptr when nothing was cut
+  const int2* cut;
+  const void* pbuf;   // [chunks][npb][cut_ib][h][2] partial sums (cpx<T>)
+  int npb;
+  int cut_ib;         // items per Legendre workgroup of that launch
 };
 
 // Pointwise combination of per-item fields into a per-pair gradient:
@@ -104,7 +112,13 @@ struct LegArgs {
   const double* rcoef;    // [L(L+1)/2]
   const double* rgam;     // [L(L+1)/2]
   const double* rseed;    // [L][h]
-  const double* rck;      // [L][4][h][2] recurrence checkpoints (row-split kernel)
+  const double* rck;      // [nparts][4][h][2] recurrence checkpoints (row-split kernel)
+  const SplitPartH* parts;// row-split kernel: work list of parts
+  const int* order;       // [nparts] part run by workgroup column b
+  int nparts;
+  int maxlen;             // longest part (rows)
+  void* pbuf;             // [chunks][npb][IB][h][2] partial synthesis sums of cut orders (cpx<T>)
+  int npb;                // partial slots per item chunk
   int item0, nb;
   const ItemDev* items;
   cpx<T>* spec;
@@ -124,7 +138,7 @@ template <typename T>
 hipError_t launch_legendre(const LegArgs<T>& a, int table_kind, int ib, hipStream_t stream);
 int recur_jpt(int h);
 int recur_jpt_valid(int h, int jpt);
-size_t split_lds_bytes(int L, int h, int ib, int real_bytes);
+size_t split_lds_bytes(int maxlen, int h, int ib, int real_bytes);  // maxlen: longest part (rows)
 template <typename T>
 hipError_t launch_legendre_split(const LegArgs<T>& a, int ib, hipStream_t stream);
 
