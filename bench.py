@@ -179,6 +179,100 @@ def cpu_baseline(budget_s):
                       f"float64 NumPy, Legendre table built beforehand"}
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_2605_18389_amd", "csrc", "kernels.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+COPY_BYTES = 1 << 30          # calibration copy: 1 GiB read + 1 GiB written
+LEG_KERNEL = "legendre_split_kernel"
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_probe():
+    """Short program for the two `rocprofv3 --pmc` passes (FETCH_SIZE, then
+    WRITE_SIZE): one device-to-device copy of COPY_BYTES (the calibration
+    kernel of known traffic), then eager solves of the benchmark workload."""
+    import torch
+    from paper_2605_18389_amd import Plan, load_library
+    load_library()
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    plan = Plan([GRID], precision="fp32", legendre="recurrence")
+    plan.set_graphs(False)
+    p, q, _, _ = make_inputs(plan, torch)
+    for _ in range(2):
+        plan.sinkhorn(p, q, 4 * T_HEAT, T=10, potentials=True)
+    torch.cuda.synchronize()
+    print("traffic probe done", flush=True)
+
+
+def pmc_summary(fetch_dir, write_dir, command):
+    """Per-launch HBM bytes of every kernel from the two counter runs, scaled
+    by the ratio of the copy kernel's known traffic to its counter reading."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        per = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return per
+
+    fetch = load(fetch_dir, "FETCH_SIZE")
+    write = load(write_dir, "WRITE_SIZE")
+
+    def copy_reading(per):
+        vals = [max(v) for k, v in per.items() if "copyBuffer" in k]
+        if not vals:
+            raise SystemExit("no copy kernel in the counter output")
+        return max(vals) * 1024.0   # KiB -> bytes (largest copy = the calibration copy)
+
+    f_fac = COPY_BYTES / copy_reading(fetch)
+    w_fac = COPY_BYTES / copy_reading(write)
+    kernels = {}
+    for name in sorted(set(fetch) | set(write)):
+        if "copyBuffer" in name or "fillBuffer" in name:
+            continue
+        fv, wv = fetch.get(name, []), write.get(name, [])
+        kernels[name] = {"dispatches": max(len(fv), len(wv)),
+                         "fetch_bytes_per_launch": f_fac * 1024.0 * sum(fv) / max(len(fv), 1),
+                         "write_bytes_per_launch": w_fac * 1024.0 * sum(wv) / max(len(wv), 1)}
+    out = {"command": command, "kernels_hip_sha256_16": kernel_source_hash(),
+           "copy_calibration": {"bytes": COPY_BYTES, "fetch_factor": f_fac, "write_factor": w_fac},
+           "kernels": kernels}
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({"written": TRAFFIC_JSON, "fetch_factor": f_fac, "write_factor": w_fac}))
+
+
+def measured_traffic(kernel_substr):
+    """HBM bytes per launch of the named kernel from profiles/traffic.json, or
+    None when absent or taken from another revision of the kernels."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    hits = [v for k, v in t["kernels"].items() if kernel_substr in k and "float" in k]
+    if not hits:
+        return None
+    v = max(hits, key=lambda x: x["dispatches"])
+    return v["fetch_bytes_per_launch"] + v["write_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,13 +283,25 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run the short program profiled by the FETCH_SIZE / WRITE_SIZE passes")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="reduce the two counter runs to profiles/traffic.json")
+    ap.add_argument("--pmc-command", default="", help="command line recorded in profiles/traffic.json")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_command)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is "
                                    "described in DESIGN.md but not built", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.traffic_probe:
+        traffic_probe()
+        return
 
     import torch
     from paper_2605_18389_amd import Plan, load_library
@@ -214,8 +320,9 @@ def main():
     flops, bytes_ = legendre_work(GRID, 1, args.legendre, args.precision)
     if args.legendre == "recurrence":
         achieved = flops / (avg_leg_ms * 1e-3) / 1e12
+        traffic = measured_traffic(LEG_KERNEL) if args.precision == "fp32" else None
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / VALU_PEAK_TFLOPS, "traffic": None}
+                "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic}
     else:
         achieved = bytes_ / (avg_leg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -1,0 +1,135 @@
+// Host-logic checks for the row-split Legendre work lists (built with g++ by
+// test_host_math.py against the library's host_math.cpp).  Prints "OK" and
+// exits 0 when every check passes; prints the first failure otherwise.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "host_math.h"
+
+using namespace shot;
+
+static int fail(const char* what, long long a, long long b) {
+  std::printf("FAIL %s (%lld, %lld)\n", what, a, b);
+  return 1;
+}
+
+// Every row (m, r) of every order is covered by exactly one part; parts are
+// sorted longest first; cut orders own consecutive partial slots.
+static int check_schedule(int L, int part_rows) {
+  std::vector<SplitPartH> parts;
+  const int npb = split_schedule(L, part_rows, parts);
+  std::vector<int> cover((size_t)L * L, 0);
+  std::vector<int> slot_used(npb > 0 ? npb : 1, 0);
+  for (size_t k = 0; k < parts.size(); ++k) {
+    const SplitPartH& P = parts[k];
+    if (k && parts[k - 1].r_hi - parts[k - 1].r_lo < P.r_hi - P.r_lo) return fail("order", (long long)k, 0);
+    if (P.r_lo < 0 || P.r_hi > L - P.m || P.r_lo >= P.r_hi) return fail("range", P.m, P.r_lo);
+    if (part_rows > 0 && P.r_hi - P.r_lo > part_rows) return fail("part length", P.m, P.r_hi - P.r_lo);
+    if (P.r_lo % 16) return fail("part start alignment", P.m, P.r_lo);
+    if (P.s < 0 || P.s >= P.ns) return fail("part index", P.m, P.s);
+    if ((P.ns == 1) != (P.pslot < 0)) return fail("slot of whole order", P.m, P.pslot);
+    if (P.ns > 1) {
+      if (P.pslot >= npb) return fail("slot range", P.pslot, npb);
+      ++slot_used[P.pslot];
+    }
+    for (int r = P.r_lo; r < P.r_hi; ++r) ++cover[(size_t)P.m * L + r];
+  }
+  for (int m = 0; m < L; ++m)
+    for (int r = 0; r < L; ++r)
+      if (cover[(size_t)m * L + r] != (r < L - m ? 1 : 0)) return fail("coverage", m, r);
+  for (int q = 0; q < npb; ++q)
+    if (slot_used[q] != 1) return fail("slot used once", q, slot_used[q]);
+  // parts of one cut order: slots pslot - s consecutive
+  for (const auto& P : parts)
+    if (P.ns > 1)
+      for (const auto& Q : parts)
+        if (Q.m == P.m && Q.pslot - Q.s != P.pslot - P.s) return fail("slot base", P.m, Q.s);
+  return 0;
+}
+
+// The dispatch order is a permutation whose per-slot weight sums (slot b % ncu)
+// stay within `tol` of the mean, heaviest item first within a slot.
+static int check_dispatch(int L, int ncu, double tol) {
+  std::vector<int> w(L);
+  for (int m = 0; m < L; ++m) w[m] = L - m;
+  const std::vector<int> ord = balanced_dispatch(w, ncu);
+  std::vector<int> seen(L, 0);
+  for (int b = 0; b < L; ++b) {
+    if (ord[b] < 0 || ord[b] >= L) return fail("dispatch range", b, ord[b]);
+    ++seen[ord[b]];
+  }
+  for (int m = 0; m < L; ++m)
+    if (seen[m] != 1) return fail("dispatch permutation", m, seen[m]);
+  if (L <= ncu) return 0;
+  std::vector<long long> load(ncu, 0);
+  for (int b = 0; b < L; ++b) load[b % ncu] += w[ord[b]];
+  long long mx = 0, tot = 0;
+  for (long long v : load) { mx = std::max(mx, v); tot += v; }
+  if ((double)mx > tol * (double)tot / ncu) return fail("dispatch balance", mx, tot / ncu);
+  for (int b = ncu; b < L; ++b)
+    if (w[ord[b]] > w[ord[b - ncu]]) return fail("heaviest first within a slot", b, ord[b]);
+  return 0;
+}
+
+// Checkpoints: gamma_r * R_r reproduces the normalised table value P̄ (an
+// independent recurrence) at each wave's first row r0 and the row before it,
+// to 10 u L^1.5 of the row's largest value (the two recurrences round
+// differently; near a zero of P̄ only an absolute comparison is meaningful).
+static int check_checkpoints(int L, int nx, int part_rows) {
+  std::vector<double> x, wq;
+  gauss_legendre(nx, x, wq);
+  std::vector<double> coef, gam, seed, tab, ck;
+  legendre_recurrence_data(L, x, coef, gam, seed);
+  const int ld = nx;
+  legendre_rows(L, x, ld, tab, 2);
+  std::vector<SplitPartH> parts;
+  split_schedule(L, part_rows, parts);
+  legendre_checkpoints(L, x, coef, seed, parts, ck, 2);
+  const double tol = 10 * 1.1102230246251565e-16 * std::pow((double)L, 1.5);
+  auto rowmax = [&](int64_t t) {
+    double v = 0;
+    for (int j = 0; j < nx; ++j) v = std::fmax(v, std::fabs(tab[(size_t)t * ld + j]));
+    return v;
+  };
+  int checked = 0;
+  for (size_t k = 0; k < parts.size(); ++k) {
+    const SplitPartH& P = parts[k];
+    const int len = P.r_hi - P.r_lo;
+    for (int w = 0; w < 4; ++w) {
+      const int r0 = P.r_lo + split_row(len, w);
+      const int64_t t0 = tri_offset(P.m, L) + r0;
+      const double s0 = r0 < P.r_hi ? rowmax(t0) : 0.0, s1 = (r0 < P.r_hi && r0 > 0) ? rowmax(t0 - 1) : 0.0;
+      for (int j = 0; j < nx; ++j) {
+        const double* c = ck.data() + ((k * 4 + w) * (size_t)nx + j) * 2;
+        if (r0 >= P.r_hi) {
+          if (c[0] != 0.0 || c[1] != 0.0) return fail("empty wave checkpoint", P.m, r0);
+          continue;
+        }
+        if (std::fabs(gam[t0] * c[0] - tab[(size_t)t0 * ld + j]) > tol * s0)
+          return fail("checkpoint R_r0", P.m * 10000 + r0, j);
+        if (r0 > 0 && std::fabs(gam[t0 - 1] * c[1] - tab[(size_t)(t0 - 1) * ld + j]) > tol * s1)
+          return fail("checkpoint R_r0-1", P.m * 10000 + r0, j);
+        if (r0 == 0 && c[1] != 0.0) return fail("checkpoint below the seed", P.m, j);
+        ++checked;
+      }
+    }
+  }
+  if (checked == 0) return fail("nothing checked", 0, 0);
+  return 0;
+}
+
+int main() {
+  int rc = 0;
+  for (int L : {1, 15, 16, 17, 90, 181, 720})
+    for (int pr : {0, 64, 128, 384}) rc |= check_schedule(L, pr);
+  rc |= check_dispatch(720, 256, 1.08);
+  rc |= check_dispatch(360, 256, 1.45);  // one order of 360 rows exceeds the mean (254)
+  rc |= check_dispatch(100, 256, 1e9);
+  rc |= check_checkpoints(80, 40, 0);
+  rc |= check_checkpoints(80, 40, 64);
+  rc |= check_checkpoints(150, 75, 64);
+  if (!rc) std::printf("OK\n");
+  return rc;
+}
