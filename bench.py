@@ -154,8 +154,11 @@ def bench_uneven_batch(torch, precision, legendre, reps=1):
             "pairs_with_breakdown": bad}
 
 
-def cpu_baseline(budget_s):
-    """FP64 oracle on host cores: iterations/s of Alg. 1 on the same workload."""
+def cpu_baseline(budget_s, gpu_heat=None):
+    """FP64 oracle on host cores: iterations/s of Alg. 1 on the same workload.
+
+    With gpu_heat ({name: K p computed by a GPU plan}) also returns each
+    plan's relative L2 error against the oracle's heat apply of the same p."""
     import oracle as O
     from paper_2605_18389_amd import synth
     try:
@@ -165,7 +168,11 @@ def cpu_baseline(budget_s):
         threads = os.cpu_count() or 1
     g = O.make_grid(*GRID)
     p, q = synth.temperature_pair(synth.pair_seed(2, 0), g.x, g.w, GRID[2], K=32)
-    O.heat_apply(p, g, T_HEAT)  # builds the Legendre table (plan time, excluded)
+    Kp = O.heat_apply(p, g, T_HEAT)  # also builds the Legendre table (plan time, excluded)
+    errors = {}
+    for name, got in (gpu_heat or {}).items():
+        got = np.asarray(got, dtype=np.float64).reshape(Kp.shape)
+        errors[name] = float(np.linalg.norm(got - Kp) / np.linalg.norm(Kp))
     t0 = time.perf_counter()
     n = 1
     O.sinkhorn(p, q, g, 4 * T_HEAT, T=n)
@@ -174,9 +181,9 @@ def cpu_baseline(budget_s):
     t0 = time.perf_counter()
     O.sinkhorn(p, q, g, 4 * T_HEAT, T=n)
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} Alg. 1 iterations (2 heat applies each) of the 721x1440 pair, "
-                      f"float64 NumPy, Legendre table built beforehand"}
+    return ({"value": n / dt, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
+             "sample": f"{n} Alg. 1 iterations (2 heat applies each) of the 721x1440 pair, "
+                       f"float64 NumPy, Legendre table built beforehand"}, errors)
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_18389_amd", "csrc", "kernels.hip")
@@ -366,6 +373,20 @@ def main():
                 del pl
             except Exception as e:  # report, do not hide
                 sec[f"{prec}_{legm}"] = {"error": str(e)}
+        try:
+            log("[bench] divergence 721x1440 (3 solves advanced together)")
+            eps = 4 * T_HEAT
+            plan.divergence(p, q, eps, T=ITERS)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.divergence(p, q, eps, T=ITERS)
+            torch.cuda.synchronize()
+            d3 = time.perf_counter() - t0
+            sec["divergence_fp32_recurrence"] = {"divergences_per_s": 1 / d3,
+                                                 "solve_iterations_per_s": 3 * ITERS / d3,
+                                                 "ms_per_divergence": d3 * 1e3}
+        except Exception as e:
+            sec["divergence_fp32_recurrence"] = {"error": str(e)}
         out["secondary"] = sec
         bat = {}
         for prec, legm in (("fp32", "recurrence"), ("fp32", "table"), ("bf16", "table")):
@@ -380,8 +401,22 @@ def main():
             torch.cuda.empty_cache()
         out["batched"] = bat
     if not args.no_cpu_baseline:
+        log("[bench] heat applies for the error report")
+        gpu_heat = {}
+        _, _, p_np, _ = make_inputs(plan, torch)
+        for prec, legm in (("fp32", "recurrence"), ("bf16", "table"), ("fp64", "recurrence")):
+            try:
+                pl = plan if (prec, legm) == (args.precision, args.legendre) else \
+                    Plan([GRID], precision=prec, legendre=legm)
+                v = torch.as_tensor(p_np, dtype=pl.dtype, device="cuda").contiguous()
+                gpu_heat[f"{prec}_{legm}"] = pl.heat_apply(v, [T_HEAT]).double().cpu().numpy()
+                del pl
+            except Exception as e:
+                log(f"[bench] heat apply {prec} {legm} failed: {e}")
+            torch.cuda.empty_cache()
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+        out["cpu_baseline"], errs = cpu_baseline(args.cpu_budget, gpu_heat)
+        out["heat_apply_rel_l2_vs_oracle"] = errs
     print(json.dumps(out), flush=True)
 
 

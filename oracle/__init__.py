@@ -15,6 +15,8 @@ Everything is float64 NumPy, written step by step from the paper:
                     definition of Y_lm and N_lm).
 * ``sht``        -- semi-naive SHT (rFFT in longitude, per-order Legendre
                     projection) and HeatConv (Sec. 3.2, "Algorithm" paragraph).
+* ``healpix``    -- HEALPix rings (equal-area pixels, App. C.1) and the
+                    pseudo-spectral SHT written as direct sums over each ring.
 * ``dense``      -- the same operator written as a dense radial kernel via the
                     addition theorem (Prop. 3.4 / Thm. 3.3); a test pin only.
 * ``sinkhorn``   -- Algorithm 1 (balanced and unbalanced branches), potentials,
@@ -26,13 +28,14 @@ Readings where the paper is silent or inconsistent are listed in the design doc
 """
 
 from .grids import Grid, gauss_legendre, clenshaw_curtis, make_grid
+from .healpix import HealpixGrid, ring_geometry
 from .legendre import legendre_table, normalised_legendre_column
 from .sht import analysis, synthesis, heat_apply, heat_multipliers
 from .dense import dense_heat_matrix, dense_heat_apply
 from .sinkhorn import sinkhorn, divergence, envelope_gradient, fd_directional
 
 __all__ = [
-    "Grid", "gauss_legendre", "clenshaw_curtis", "make_grid",
+    "Grid", "gauss_legendre", "clenshaw_curtis", "make_grid", "HealpixGrid", "ring_geometry",
     "legendre_table", "normalised_legendre_column",
     "analysis", "synthesis", "heat_apply", "heat_multipliers",
     "dense_heat_matrix", "dense_heat_apply",

@@ -76,6 +76,10 @@ class Grid:
         return self.nlat * self.nlon
 
     @property
+    def field_shape(self):
+        return (self.nlat, self.nlon)
+
+    @property
     def theta(self):
         return np.arccos(np.clip(self.x, -1.0, 1.0))
 

@@ -13,10 +13,13 @@ For real fields only m >= 0 is stored (f_{l,-m} is fixed by conjugate symmetry):
     G_m(j)   = sum_l c_lm P̄_l^m(x_j)
     g_{jk}   = G_0(j) + 2 Re sum_{m>=1} G_m(j) e^{2 pi i m k / nlon}
 Arrays carry any leading batch dimensions: f has shape (..., nlat, nlon).
+HEALPix grids (pseudo-spectral, per-ring longitude sums) are handled in
+``healpix``; their fields have shape (..., 1, Npix).
 """
 
 import numpy as np
 
+from . import healpix
 from .legendre import legendre_table
 
 
@@ -36,6 +39,8 @@ def heat_multipliers(L, t):
 
 def analysis(f, grid):
     """Forward SHT.  Returns a list over m of complex arrays (..., L-m) holding f_lm, l = m..L-1."""
+    if grid.kind == "hp":
+        return healpix.analysis(f, grid)
     f = np.asarray(f, dtype=np.float64)
     F = np.fft.rfft(f, axis=-1)
     wq = grid.w * (2.0 * np.pi / grid.nlon)
@@ -49,6 +54,8 @@ def analysis(f, grid):
 
 def synthesis(coeffs, grid):
     """Inverse SHT of a list over m of (..., L-m) coefficient arrays; returns (..., nlat, nlon)."""
+    if grid.kind == "hp":
+        return healpix.synthesis(coeffs, grid)
     tab = _table(grid)
     lead = coeffs[0].shape[:-1]
     G = np.zeros(lead + (grid.nlat, grid.nlon // 2 + 1), dtype=np.complex128)

@@ -53,8 +53,8 @@ def sinkhorn(p, q, grid, eps, tau=math.inf, T=100, delta=0.0, C=10, K=None,
     a = grid.area
     balanced = math.isinf(tau)
     lead = np.broadcast_shapes(p.shape, q.shape)[:-2]
-    u = np.ones(lead + (grid.nlat, grid.nlon))
-    v = np.ones(lead + (grid.nlat, grid.nlon))
+    u = np.ones(lead + grid.field_shape)
+    v = np.ones(lead + grid.field_shape)
     breakdown = np.zeros(lead, dtype=np.int64)
     kratio = np.full(lead, np.inf)
     if delta > 0 and len(lead) > 0:
