@@ -63,13 +63,22 @@ typedef enum {
   SHOT_E_BREAKDOWN = 17      /* heat-kernel output <= 0 or non-finite (App. C.4)   */
 } shot_status;
 
-enum { SHOT_GRID_GAUSS_LEGENDRE = 0, SHOT_GRID_CLENSHAW_CURTIS = 1 };
+enum { SHOT_GRID_GAUSS_LEGENDRE = 0, SHOT_GRID_CLENSHAW_CURTIS = 1, SHOT_GRID_HEALPIX = 2 };
 enum { SHOT_FP64 = 0, SHOT_FP32 = 1, SHOT_BF16_MFMA = 2 };
 enum { SHOT_LEG_AUTO = 0, SHOT_LEG_TABLE = 1, SHOT_LEG_RECURRENCE = 2 };
 
 /* One grid.  kind: SHOT_GRID_GAUSS_LEGENDRE (rows at the roots of P_nlat) or
  * SHOT_GRID_CLENSHAW_CURTIS (equiangular rows theta_j = j*pi/(nlat-1), poles
- * included) -- App. C.1. */
+ * included) -- App. C.1: a field is [nlat][nlon] row-major, requires
+ * nlon >= 2L-1, nlon a product of 2, 3 and 5, nlon <= 2048.
+ *
+ * SHOT_GRID_HEALPIX (Sec. 3.3, App. C.1; Gorski et al. 2005): nlat = 4 Nside - 1
+ * iso-latitude rings, nlon = 4 Nside (the longest ring), Nside <= 512; a field
+ * holds the 12 Nside^2 equal-area pixels in RING order (rings from the north,
+ * pixels of a ring by increasing longitude from that ring's first pixel, see
+ * shot_plan_ring).  No sampling theorem holds, so the transform is
+ * pseudo-spectral: the analysis is the area-weighted pixel sum (every pixel
+ * has area 4 pi / Npix) and any band limit L >= 1 is accepted. */
 typedef struct {
   int32_t kind;
   int32_t nlat;
@@ -117,6 +126,12 @@ shot_status shot_plan_destroy(shot_plan_t plan);
 /* Copy grid `grid`'s float64 nodes x_j = cos(colatitude_j) and latitude
  * weights w_j (sum 2) into host arrays of nlat entries each (either may be NULL). */
 shot_status shot_plan_grid(shot_plan_t plan, int32_t grid, double* x_out, double* w_out);
+
+/* Ring layout of grid `grid`: for each of its nlat rows (HEALPix: rings), the
+ * number of points and the longitude of the first point (point k of the row
+ * sits at phi0 + 2 pi k / npix).  Host arrays of nlat entries (either may be
+ * NULL).  Latitude-longitude grids report nlon and 0 for every row. */
+shot_status shot_plan_ring(shot_plan_t plan, int32_t grid, int32_t* npix_out, double* phi0_out);
 
 /* Forward SHT (App. B: f_lm = <f, Y_lm>, evaluated by App. C.1's semi-naive
  * algorithm).  f: device, fields of the items.  coeffs: device, per item

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libshot.so")
 
 GRID_GAUSS_LEGENDRE = 0
 GRID_CLENSHAW_CURTIS = 1
+GRID_HEALPIX = 2
 FP64, FP32, BF16_MFMA = 0, 1, 2
 LEG_AUTO, LEG_TABLE, LEG_RECURRENCE = 0, 1, 2
 
@@ -32,7 +33,7 @@ _PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16_MFMA, "bf16_mfma": BF16_MFMA}
 _LEG = {"auto": LEG_AUTO, "table": LEG_TABLE, "recurrence": LEG_RECURRENCE}
 _KIND = {"gl": GRID_GAUSS_LEGENDRE, "gauss_legendre": GRID_GAUSS_LEGENDRE,
          "cc": GRID_CLENSHAW_CURTIS, "clenshaw_curtis": GRID_CLENSHAW_CURTIS,
-         "equiangular": GRID_CLENSHAW_CURTIS}
+         "equiangular": GRID_CLENSHAW_CURTIS, "hp": GRID_HEALPIX, "healpix": GRID_HEALPIX}
 
 # Every entry point declared in include/shot.h.
 EXPORTS = [
@@ -40,7 +41,7 @@ EXPORTS = [
     "shot_sht_synthesis", "shot_heat_apply", "shot_sinkhorn_solve", "shot_sinkhorn_divergence",
     "shot_sinkhorn_divergence_grad", "shot_profile_enable", "shot_profile_read",
     "shot_status_string", "shot_last_error", "shot_plan_set_tuning", "shot_plan_get_tuning",
-    "shot_autotune", "shot_plan_set_graphs",
+    "shot_autotune", "shot_plan_set_graphs", "shot_plan_ring",
 ]
 
 
@@ -94,6 +95,7 @@ def load_library(path=None):
         "shot_sht_plan": [ctypes.POINTER(vp), ctypes.POINTER(GridDesc), i32, i32, i32, vp],
         "shot_plan_destroy": [vp],
         "shot_plan_grid": [vp, i32, dp, dp],
+        "shot_plan_ring": [vp, i32, ip, dp],
         "shot_sht_analysis": [vp, ip, i32, vp, vp, vp],
         "shot_sht_synthesis": [vp, ip, i32, vp, vp, vp],
         "shot_heat_apply": [vp, ip, i32, dp, vp, vp, i32, vp],
@@ -151,10 +153,21 @@ def _i32_array(vals):
     return a
 
 
+def _grid_tuple(g):
+    """(kind, nlat, nlon, L); ("hp", nside, L) expands to ("hp", 4 nside - 1, 4 nside, L)."""
+    kind = g[0]
+    code = _KIND[kind] if isinstance(kind, str) else int(kind)
+    if code == GRID_HEALPIX and len(g) == 3:
+        nside = int(g[1])
+        return (kind, 4 * nside - 1, 4 * nside, int(g[2]))
+    return (kind, int(g[1]), int(g[2]), int(g[3]))
+
+
 class Plan:
     """A libshot plan for one or more grids.
 
-    grids: list of (kind, nlat, nlon, L) with kind "gl" or "cc".
+    grids: list of (kind, nlat, nlon, L) with kind "gl" or "cc", or ("hp", nside, L) for a
+    HEALPix grid (stored as ("hp", 4 nside - 1, 4 nside, L): rings, longest ring, L).
     precision: "fp64", "fp32" or "bf16" (bfloat16 Legendre operands, float32 accumulation).
     legendre: "auto", "table" (P̄ streamed from HBM) or "recurrence" (generated in float64).
     """
@@ -164,7 +177,7 @@ class Plan:
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libshot needs a ROCm GPU")
-        self.grids = [(g[0], int(g[1]), int(g[2]), int(g[3])) for g in grids]
+        self.grids = [_grid_tuple(g) for g in grids]
         self.precision = precision
         self.prec_code = _PREC[precision]
         self.dtype = torch.float64 if self.prec_code == FP64 else torch.float32
@@ -197,12 +210,40 @@ class Plan:
             w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return x, w
 
+    def is_healpix(self, grid=0):
+        k = self.grids[grid][0]
+        return (_KIND[k] if isinstance(k, str) else int(k)) == GRID_HEALPIX
+
+    def ring_layout(self, grid=0):
+        """Points per row (ring) and the longitude of each row's first point."""
+        nlat = self.grids[grid][1]
+        npix = np.zeros(nlat, dtype=np.int32)
+        phi0 = np.zeros(nlat)
+        _check("shot_plan_ring", self.lib.shot_plan_ring(
+            self.handle, grid, npix.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            phi0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return npix, phi0
+
+    def pixel_coords(self, grid=0):
+        """(z, phi) of every point in field order (rows, or rings in RING order)."""
+        x, _ = self.grid_nodes(grid)
+        npix, phi0 = self.ring_layout(grid)
+        z = np.repeat(x, npix)
+        phi = np.concatenate([phi0[r] + 2 * np.pi * np.arange(npix[r]) / npix[r] for r in range(len(npix))])
+        return z, phi
+
     def area(self, grid=0):
         _, nlat, nlon, _ = self.grids[grid]
+        if self.is_healpix(grid):
+            n = self.field_size(grid)
+            return np.full(n, 4 * np.pi / n)
         _, w = self.grid_nodes(grid)
         return np.repeat((w * 2 * np.pi / nlon)[:, None], nlon, axis=1)
 
     def field_size(self, grid):
+        if self.is_healpix(grid):
+            nside = self.grids[grid][2] // 4
+            return 12 * nside * nside
         return self.grids[grid][1] * self.grids[grid][2]
 
     def ncoeff(self, grid):

@@ -53,10 +53,18 @@ struct GridRec {
   void* d_pbuf = nullptr;            // partial sums of cut orders, 4 chunks of 2 items
   void* d_aw = nullptr;
   void* d_tw = nullptr;
+  // HEALPix: ring pairs, twiddles of every ring length, e^{i m phi0} per (pair, m)
+  bool hp = false;
+  int nside = 0;
+  std::vector<int> ring_npix;
+  std::vector<double> ring_phi0;
+  RingDev* d_ring = nullptr;
+  void* d_ring_tw = nullptr;
+  void* d_ring_ph = nullptr;
   int tune_ib = 0;   // Legendre items per workgroup (0 = automatic)
   int tune_jpt = 0;  // recurrence chains per thread (0 = automatic); table grids: MFMA column
                      // tiles (1, 2, 4), 0 = automatic, -1 = VALU kernel only
-  int64_t n() const { return (int64_t)d.nlat * d.nlon; }
+  int64_t n() const { return hp ? 12LL * nside * nside : (int64_t)d.nlat * d.nlon; }
 };
 
 struct DevBuf {
@@ -191,9 +199,10 @@ uint16_t to_bf16(double v) {
 void free_grid(GridRec& g) {
   for (void* p : {g.d_tab, g.d_tabT, (void*)g.d_toffT, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam,
                   (void*)g.d_rseed, (void*)g.sw.d_parts, (void*)g.sw.d_ck, (void*)g.ss.d_parts,
-                  (void*)g.ss.d_ck, (void*)g.sw.d_order, (void*)g.ss.d_order, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
+                  (void*)g.ss.d_ck, (void*)g.sw.d_order, (void*)g.ss.d_order, (void*)g.d_ring, g.d_ring_tw, g.d_ring_ph, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
     if (p) (void)hipFree(p);
-  g.d_tab = g.d_tabT = g.d_aw = g.d_tw = g.d_pbuf = nullptr;
+  g.d_tab = g.d_tabT = g.d_aw = g.d_tw = g.d_pbuf = g.d_ring_tw = g.d_ring_ph = nullptr;
+  g.d_ring = nullptr;
   g.d_toffT = nullptr;
   g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = nullptr;
   g.sw = SplitSched{};
@@ -203,16 +212,74 @@ void free_grid(GridRec& g) {
 
 shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) {
   const auto& d = g.d;
-  if (d.kind == SHOT_GRID_GAUSS_LEGENDRE) gauss_legendre(d.nlat, g.x, g.w);
-  else clenshaw_curtis(d.nlat, g.x, g.w);
+  g.hp = d.kind == SHOT_GRID_HEALPIX;
+  if (g.hp) {
+    // rings (z, pixel count, first longitude); w_j = the ring's area / (2 pi)
+    g.nside = d.nlon / 4;
+    healpix_rings(g.nside, g.x, g.ring_npix, g.ring_phi0);
+    g.w.resize(d.nlat);
+    const double npix = 12.0 * g.nside * g.nside;
+    for (int r = 0; r < d.nlat; ++r) g.w[r] = 2.0 * g.ring_npix[r] / npix;
+  } else if (d.kind == SHOT_GRID_GAUSS_LEGENDRE) {
+    gauss_legendre(d.nlat, g.x, g.w);
+  } else {
+    clenshaw_curtis(d.nlat, g.x, g.w);
+  }
   g.h = (d.nlat + 1) / 2;
   // table rows padded to the matrix-core K step (32) for fp32/bf16 tables
   g.hpad = P->prec == SHOT_FP64 ? (g.h + 3) / 4 * 4 : (g.h + 31) / 32 * 32;
-  g.fac = fft_radices(d.nlon);
+  g.fac = g.hp ? std::vector<int>() : fft_radices(d.nlon);
   const bool f64 = P->prec == SHOT_FP64;
   // area weights of rows 0..h-1 and twiddles in field precision
   std::vector<double> aw(g.h);
-  for (int j = 0; j < g.h; ++j) aw[j] = g.w[j] * 2.0 * M_PI / d.nlon;
+  for (int j = 0; j < g.h; ++j)
+    aw[j] = g.hp ? 4.0 * M_PI / (12.0 * g.nside * g.nside) : g.w[j] * 2.0 * M_PI / d.nlon;
+  if (g.hp) {
+    // ring pairs: geometry, twiddles per distinct length (4k pixels, k = 1..nside), phases
+    std::vector<RingDev> rings(g.h);
+    std::vector<long long> twoff(g.nside + 1, -1);
+    std::vector<double> rtw;
+    std::vector<long long> start(d.nlat + 1, 0);
+    for (int r = 0; r < d.nlat; ++r) start[r + 1] = start[r] + g.ring_npix[r];
+    for (int j = 0; j < g.h; ++j) {
+      RingDev& R = rings[j];
+      const int len = g.ring_npix[j];
+      R.len = len;
+      R.off1 = (int)start[j];
+      R.off2 = (int)start[d.nlat - 1 - j];
+      const int k = len / 4;
+      if (twoff[k] < 0) {
+        twoff[k] = (long long)rtw.size() / 2;
+        for (int q = 0; q < len; ++q) {
+          const long double ang = -2.0L * (long double)M_PI * (long double)q / (long double)len;
+          rtw.push_back((double)cosl(ang));
+          rtw.push_back((double)sinl(ang));
+        }
+      }
+      R.twoff = (int)twoff[k];
+      const std::vector<int> f = fft_factors(len);
+      if ((int)f.size() > RING_MAXFAC) return SHOT_E_UNSUPPORTED;
+      R.nfac = (int)f.size();
+      for (int q = 0; q < RING_MAXFAC; ++q) R.fac[q] = q < R.nfac ? f[q] : 0;
+    }
+    std::vector<double> ph((size_t)g.h * d.L * 2);
+    for (int j = 0; j < g.h; ++j)
+      for (int m = 0; m < d.L; ++m) {
+        const long double ang = (long double)m * (long double)g.ring_phi0[j];
+        ph[((size_t)j * d.L + m) * 2] = (double)cosl(ang);
+        ph[((size_t)j * d.L + m) * 2 + 1] = (double)sinl(ang);
+      }
+    shot_status st2;
+    if ((st2 = upload((void**)&g.d_ring, rings, s)) != SHOT_OK) return st2;
+    if (f64) {
+      if ((st2 = upload(&g.d_ring_tw, rtw, s)) != SHOT_OK) return st2;
+      if ((st2 = upload(&g.d_ring_ph, ph, s)) != SHOT_OK) return st2;
+    } else {
+      std::vector<float> a(rtw.begin(), rtw.end()), b(ph.begin(), ph.end());
+      if ((st2 = upload(&g.d_ring_tw, a, s)) != SHOT_OK) return st2;
+      if ((st2 = upload(&g.d_ring_ph, b, s)) != SHOT_OK) return st2;
+    }
+  }
   std::vector<double> tw(2 * (size_t)d.nlon);
   for (int k = 0; k < d.nlon; ++k) {
     // exp(-2 pi i k/N), argument reduced to [0, pi/2] style accuracy by long double
@@ -515,6 +582,11 @@ RowArgs<T> row_args(const shot_plan_s* P, const GridRec& g, const Layout& Lo, co
   for (int i = 0; i < a.nfac && i < 8; ++i) a.fac[i] = g.fac[i];
   a.tw = static_cast<const cpx<T>*>(g.d_tw);
   a.aw = static_cast<const T*>(g.d_aw);
+  if (g.hp) {
+    a.ring = g.d_ring;
+    a.ring_tw = static_cast<const cpx<T>*>(g.d_ring_tw);
+    a.ring_ph = static_cast<const cpx<T>*>(g.d_ring_ph);
+  }
   a.item0 = G.first;
   a.items = W.items;
   a.spec = W.spec;
@@ -1237,7 +1309,7 @@ template <typename T>
 shot_status combine_pairs(shot_plan_s* P, const std::vector<CombineDev>& dv, T* out, hipStream_t s) {
   if (dv.empty()) return SHOT_OK;
   long long maxn = 0;
-  for (const auto& d : dv) maxn = std::max(maxn, (long long)d.nlat * d.nlon);
+  for (const auto& d : dv) maxn = std::max(maxn, d.n);
   void* dd = nullptr;
   HIP_TRY(hipMalloc(&dd, sizeof(CombineDev) * dv.size()));
   hipError_t e = hipMemcpyAsync(dd, dv.data(), sizeof(CombineDev) * dv.size(), hipMemcpyHostToDevice, s);
@@ -1306,6 +1378,8 @@ shot_status divergence_grad_impl(shot_plan_s* P, const int32_t* gop, int npairs,
       d.coef = params[i].eps * (mass[6 * i] - mass[6 * i + 1]);
       d.nlat = g.d.nlat;
       d.nlon = g.d.nlon;
+      d.n = g.n();
+      d.equal_area = g.hp ? 1 : 0;
       d.h = g.h;
       d.aw = g.d_aw;
     }
@@ -1338,6 +1412,8 @@ shot_status divergence_grad_impl(shot_plan_s* P, const int32_t* gop, int npairs,
     d.coef = params[i].eps * (mass[6 * i] - mass[6 * i + 1]);
     d.nlat = g.d.nlat;
     d.nlon = g.d.nlon;
+    d.n = g.n();
+    d.equal_area = g.hp ? 1 : 0;
     d.h = g.h;
     d.aw = g.d_aw;
   }
@@ -1373,10 +1449,16 @@ shot_status shot_sht_plan(shot_plan_t* out, const shot_grid_desc* grids, int32_t
   if (legendre_mode < SHOT_LEG_AUTO || legendre_mode > SHOT_LEG_RECURRENCE) return SHOT_E_INVALID;
   for (int i = 0; i < ngrids; ++i) {
     const shot_grid_desc& d = grids[i];
-    if (d.kind != SHOT_GRID_GAUSS_LEGENDRE && d.kind != SHOT_GRID_CLENSHAW_CURTIS) return SHOT_E_INVALID;
-    if (d.nlat < 2 || d.L < 1 || d.nlon < 2 * d.L - 1) return SHOT_E_INVALID;
-    if (fft_radices(d.nlon).empty() || d.nlon > 2048) return SHOT_E_UNSUPPORTED;
-    if (fft_radices(d.nlon).size() > 8) return SHOT_E_UNSUPPORTED;
+    if (d.kind != SHOT_GRID_GAUSS_LEGENDRE && d.kind != SHOT_GRID_CLENSHAW_CURTIS && d.kind != SHOT_GRID_HEALPIX)
+      return SHOT_E_INVALID;
+    if (d.kind == SHOT_GRID_HEALPIX) {
+      if (d.L < 1 || d.nlon < 4 || d.nlon % 4 != 0 || d.nlat != d.nlon - 1) return SHOT_E_INVALID;
+      if (d.nlon > 2048) return SHOT_E_UNSUPPORTED;
+    } else {
+      if (d.nlat < 2 || d.L < 1 || d.nlon < 2 * d.L - 1) return SHOT_E_INVALID;
+      if (fft_radices(d.nlon).empty() || d.nlon > 2048) return SHOT_E_UNSUPPORTED;
+      if (fft_radices(d.nlon).size() > 8) return SHOT_E_UNSUPPORTED;
+    }
     // one order's inputs and coefficients must fit the Legendre kernel's LDS
     const size_t cs = precision == SHOT_FP64 ? 16 : 8;
     if ((size_t)(2 * ((d.nlat + 1) / 2) + d.L) * cs > 60 * 1024) return SHOT_E_UNSUPPORTED;
@@ -1423,6 +1505,16 @@ shot_status shot_plan_grid(shot_plan_t P, int32_t grid, double* x_out, double* w
   const GridRec& g = P->grids[grid];
   if (x_out) std::copy(g.x.begin(), g.x.end(), x_out);
   if (w_out) std::copy(g.w.begin(), g.w.end(), w_out);
+  return SHOT_OK;
+}
+
+shot_status shot_plan_ring(shot_plan_t P, int32_t grid, int32_t* npix_out, double* phi0_out) {
+  if (!P || grid < 0 || grid >= (int)P->grids.size()) return SHOT_E_INVALID;
+  const GridRec& g = P->grids[grid];
+  for (int r = 0; r < g.d.nlat; ++r) {
+    if (npix_out) npix_out[r] = g.hp ? g.ring_npix[r] : g.d.nlon;
+    if (phi0_out) phi0_out[r] = g.hp ? g.ring_phi0[r] : 0.0;
+  }
   return SHOT_OK;
 }
 

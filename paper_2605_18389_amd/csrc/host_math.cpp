@@ -77,6 +77,45 @@ void clenshaw_curtis(int n, std::vector<double>& x, std::vector<double>& w) {
   if (n % 2 == 1) x[n / 2] = 0.0;
 }
 
+std::vector<int> fft_factors(int n) {
+  std::vector<int> f;
+  if (n < 1) return f;
+  for (int r : {4, 2, 3, 5})
+    while (n % r == 0) {
+      f.push_back(r);
+      n /= r;
+    }
+  for (int p = 7; n > 1; p += 2)
+    while (n % p == 0) {
+      f.push_back(p);
+      n /= p;
+    }
+  return f;
+}
+
+void healpix_rings(int nside, std::vector<double>& z, std::vector<int>& npix, std::vector<double>& phi0) {
+  const int nr = 4 * nside - 1;
+  z.assign(nr, 0.0);
+  npix.assign(nr, 0);
+  phi0.assign(nr, 0.0);
+  const double ns = (double)nside;
+  for (int r = 0; r < nr; ++r) {
+    const int i = r + 1;
+    const int k = i <= 2 * nside ? i : 4 * nside - i;  // the northern ring of the mirror pair
+    double zk;
+    if (k < nside) {
+      zk = 1.0 - (double)k * k / (3.0 * ns * ns);
+      npix[r] = 4 * k;
+      phi0[r] = M_PI / (4.0 * k);
+    } else {
+      zk = 4.0 / 3.0 - 2.0 * k / (3.0 * ns);
+      npix[r] = 4 * nside;
+      phi0[r] = ((k - nside + 1) % 2) * M_PI / (4.0 * ns);
+    }
+    z[r] = i <= 2 * nside ? zk : -zk;
+  }
+}
+
 std::vector<int> fft_radices(int n) {
   std::vector<int> f;
   for (int r : {4, 2, 3, 5}) {

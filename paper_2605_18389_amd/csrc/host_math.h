@@ -39,6 +39,18 @@ void clenshaw_curtis(int n, std::vector<double>& x, std::vector<double>& w);
 // empty when n has another prime factor.
 std::vector<int> fft_radices(int n);
 
+// Factors of any n >= 1: 4, 2, 3, 5 extracted first, then the remaining
+// primes in increasing order (the device FFT runs those as generic stages).
+std::vector<int> fft_factors(int n);
+
+// HEALPix rings (Gorski et al. 2005), north to south, i = 1 .. 4 nside - 1:
+// z = cos(colatitude) of the ring, its pixel count and the longitude of its
+// first pixel in RING order.  North polar cap (i < nside): z = 1 - i^2/(3 nside^2),
+// 4 i pixels from pi/(4 i); equatorial belt (nside <= i <= 2 nside): z = 4/3 -
+// 2 i/(3 nside), 4 nside pixels from s pi/(4 nside), s = (i - nside + 1) mod 2;
+// the southern rings mirror the northern ones (z -> -z).
+void healpix_rings(int nside, std::vector<double>& z, std::vector<int>& npix, std::vector<double>& phi0);
+
 // Offset of order m in the packed triangular (m, l) layout, l = m..L-1.
 inline int64_t tri_offset(int64_t m, int64_t L) { return m * L - m * (m - 1) / 2; }
 

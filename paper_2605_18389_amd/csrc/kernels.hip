@@ -117,6 +117,34 @@ __device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ src, c
   }
 }
 
+// Stockham stage of any radix R (the primes above 5 of ring lengths that are
+// not 2,3,5-smooth): each thread forms whole outputs, output q of butterfly b
+// being sum_r src[b + r N/R] w^{r (k N/(Ns R) + q N/R)} with w the length-N
+// root, so every term costs one table lookup.
+template <typename T>
+__device__ void stockham_stage_generic(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst, int N, int Ns,
+                                       int R, int nb, const cpx<T>* __restrict__ tw, T sign) {
+  const int NR = N / R;
+  const int twstride = N / (Ns * R);
+  for (int o = threadIdx.x; o < nb * N; o += blockDim.x) {
+    const int t = o / N, rem = o - t * N;
+    const int q = rem / NR, b = rem - q * NR;
+    const int k = b % Ns;
+    const cpx<T>* s = src + t * N;
+    const int e = k * twstride + q * NR;
+    cpx<T> acc = {(T)0, (T)0};
+    int idx = 0;  // r * e mod N, advanced by e
+    for (int r = 0; r < R; ++r) {
+      cpx<T> w = tw[idx];
+      w.y *= -sign;  // table holds exp(-2 pi i k/N); inverse uses the conjugate
+      acc = cadd(acc, cmul(s[b + r * NR], w));
+      idx += e;
+      if (idx >= N) idx -= N * (idx / N);
+    }
+    dst[t * N + (b / Ns) * Ns * R + k + q * Ns] = acc;
+  }
+}
+
 template <typename T>
 __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int N, int nb, const int* fac, int nfac,
                            const cpx<T>* __restrict__ tw, T sign) {
@@ -129,7 +157,8 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int N, int nb, const int* fac, 
       case 2: stockham_stage<T, 2>(src, dst, N, Ns, nb, tw, sign); break;
       case 3: stockham_stage<T, 3>(src, dst, N, Ns, nb, tw, sign); break;
       case 4: stockham_stage<T, 4>(src, dst, N, Ns, nb, tw, sign); break;
-      default: stockham_stage<T, 5>(src, dst, N, Ns, nb, tw, sign); break;
+      case 5: stockham_stage<T, 5>(src, dst, N, Ns, nb, tw, sign); break;
+      default: stockham_stage_generic<T>(src, dst, N, Ns, R, nb, tw, sign); break;
     }
     __syncthreads();
     cpx<T>* t = src;
@@ -374,20 +403,23 @@ __device__ void kratio_fold(const RowArgs<T>& A, int it, int k, int slot, double
 template <typename T, int RPW, int NC>
 __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int N = NC > 0 ? NC : A.nlon;
   const int L = A.L, h = A.h;
-  cpx<T>* buf0 = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* buf1 = buf0 + RPW * N;
-  cpx<T>* twl = buf1 + RPW * N;
-  __shared__ double sh[16];
-  __shared__ int sh_bad;
-  __shared__ T awl[RPW];
-
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
   // contiguous range of groups so that neighbouring rows' spectral entries
   // (adjacent in memory) meet in the same L2.
   const int ngroups = (h + RPW - 1) / RPW;
   const int jp0 = xcd_row_pair(blockIdx.x, ngroups) * RPW;
+  // HEALPix: this pair's rings (one pair per group), else uniform rows
+  const RingDev* RG = A.ring ? A.ring + jp0 : nullptr;
+  const int N = RG ? RG->len : (NC > 0 ? NC : A.nlon);
+  const int NB = RG ? A.nlon : N;  // LDS stride: the longest row
+  cpx<T>* buf0 = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* buf1 = buf0 + RPW * NB;
+  cpx<T>* twl = buf1 + RPW * NB;
+  __shared__ double sh[16];
+  __shared__ int sh_bad;
+  __shared__ T awl[RPW];
+
   const int np = min(RPW, h - jp0);  // active pairs of this group
   const int it = A.item0 + blockIdx.y;
   const ItemDev I = A.items[it];
@@ -407,13 +439,13 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
   __syncthreads();
 
 // per-element pair geometry: pr = pair in group, c = column
-#define ROW_PAIR_SETUP(idx)                                       \
-  const int pr = (idx) / N, c = (idx) - pr * N;                   \
-  const int jp = jp0 + pr;                                        \
-  const int j2 = nlat - 1 - jp;                                   \
-  const bool eq = (jp == j2);                                     \
-  const long long r1 = I.foff + (long long)jp * N;                \
-  const long long r2 = I.foff + (long long)j2 * N;                \
+#define ROW_PAIR_SETUP(idx)                                                        \
+  const int pr = (idx) / N, c = (idx) - pr * N;                                    \
+  const int jp = jp0 + pr;                                                         \
+  const int j2 = nlat - 1 - jp;                                                    \
+  const bool eq = (jp == j2);                                                      \
+  const long long r1 = I.foff + (RG ? (long long)RG->off1 : (long long)jp * N);    \
+  const long long r2 = I.foff + (RG ? (long long)RG->off2 : (long long)j2 * N);    \
   const T aj = awl[pr];
 
   if (mode == ROW_FINAL) {
@@ -442,15 +474,45 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
     return;
   }
 
-  const cpx<T>* tws = A.tw;
+  const cpx<T>* twsrc = RG ? A.ring_tw + RG->twoff : A.tw;
+  const cpx<T>* tws = twsrc;
   if (A.tw_lds) {
-    for (int i = tid; i < N; i += bs) twl[i] = A.tw[i];
+    for (int i = tid; i < N; i += bs) twl[i] = twsrc[i];
     tws = twl;
   }
   cpx<T>* X = buf0;
   const bool has_inverse = (mode == ROW_INV || mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK ||
                             mode == ROW_ADJ_A || mode == ROW_ADJ_VB);
-  if (has_inverse) {
+  if (has_inverse && RG) {
+    // HEALPix ring pair: row r's field is sum_{|m| < L} G_m e^{i m (phi0 + 2 pi k/N)}
+    // with G_{-m} = conj(G_m); with P_m = G_m e^{i m phi0}, order m lands in bin
+    // m mod N and -m in bin -m mod N of the pair's packed spectrum
+    // Z = C_j + i C_j' (orders beyond the ring's length alias, as the samples do).
+    const cpx<T>* ph = A.ring_ph + (size_t)jp0 * L;
+    const bool eq = (jp0 == nlat - 1 - jp0);
+    for (int c = tid; c < N; c += bs) {
+      cpx<T> z = {(T)0, (T)0};
+      for (int m = c; m < L; m += N) {
+        cpx<T> ge, go;
+        load_spec_pair(A, spec, it, m, jp0, ge, go);
+        const cpx<T> a = cmul(cadd(ge, go), ph[m]);
+        const cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : cmul(csub(ge, go), ph[m]);
+        z.x += a.x - b.y;
+        z.y += a.y + b.x;
+      }
+      for (int m = (c == 0 ? N : N - c); m < L; m += N) {
+        cpx<T> ge, go;
+        load_spec_pair(A, spec, it, m, jp0, ge, go);
+        const cpx<T> a = cmul(cadd(ge, go), ph[m]);
+        const cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : cmul(csub(ge, go), ph[m]);
+        z.x += a.x + b.y;
+        z.y += -a.y + b.x;
+      }
+      buf0[c] = z;
+    }
+    __syncthreads();
+    X = fft_lds<T>(buf0, buf1, N, 1, RG->fac, RG->nfac, tws, (T)1);
+  } else if (has_inverse) {
     // G_j[m] = GE + GO, G_j'[m] = GE - GO; Z[m] = G_j[m] + i G_j'[m] and its
     // Hermitian mirror Z[N-m] = conj(G_j[m]) + i conj(G_j'[m]); zero elsewhere.
     for (int idx = tid; idx < RPW * (N - 2 * L + 1); idx += bs) {
@@ -651,7 +713,8 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
 
   // forward FFT of the rows now in X, fold, weight, store
   cpx<T>* other = (X == buf0) ? buf1 : buf0;
-  cpx<T>* Z = fft_any<T, NC, RPW>(X, other, N, A.fac, A.nfac, tws, (T)-1);
+  cpx<T>* Z = RG ? fft_lds<T>(X, other, N, 1, RG->fac, RG->nfac, tws, (T)-1)
+                 : fft_any<T, NC, RPW>(X, other, N, A.fac, A.nfac, tws, (T)-1);
   const bool adj = (mode == ROW_ADJ_START || mode == ROW_ADJ_A || mode == ROW_ADJ_VB);
   const bool unweighted = (mode == ROW_FWD && !A.wts_in) || adj;
   for (int idx = tid; idx < np * L; idx += bs) {
@@ -659,8 +722,9 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
     const int jp = jp0 + pr;
     const bool eq = (jp == nlat - 1 - jp);
     const cpx<T>* Zp = Z + pr * N;
-    const cpx<T> a = Zp[m];
-    cpx<T> b = Zp[(N - m) % N];
+    const int cm = RG ? m % N : m;  // HEALPix rings: order m sits in bin m mod N
+    const cpx<T> a = Zp[cm];
+    cpx<T> b = Zp[(N - cm) % N];
     b.y = -b.y;
     cpx<T> E, O;
     if (eq) {
@@ -671,6 +735,12 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
       const cpx<T> x2 = {(T)0.5 * (a.y - b.y), (T)-0.5 * (a.x - b.x)};
       E = cadd(x1, x2);
       O = csub(x1, x2);
+    }
+    if (RG) {  // e^{-i m phi0}: the rings' first pixels sit at phi0, not 0
+      cpx<T> e = A.ring_ph[(size_t)jp0 * L + m];
+      e.y = -e.y;
+      E = cmul(E, e);
+      O = cmul(O, e);
     }
     const T cw = unweighted ? (T)1 : awl[pr];
     cpx<T>* sp = spec + ((size_t)m * h + jp) * 2;
@@ -1774,11 +1844,14 @@ __global__ void __launch_bounds__(256) gauge_kernel(RowArgs<T> A, int k, double*
 template <typename T>
 __global__ void __launch_bounds__(256) combine_kernel(const CombineDev* __restrict__ D, T* out) {
   const CombineDev d = D[blockIdx.y];
-  const long long n = (long long)d.nlat * d.nlon;
+  const long long n = d.n;
   const long long x = (long long)blockIdx.x * 256 + threadIdx.x;
   if (x >= n) return;
-  const int row = (int)(x / d.nlon);
-  const int jr = row < d.h ? row : d.nlat - 1 - row;
+  int jr = 0;
+  if (!d.equal_area) {
+    const int row = (int)(x / d.nlon);
+    jr = row < d.h ? row : d.nlat - 1 - row;
+  }
   const double a = (double)static_cast<const T*>(d.aw)[jr];
   const double v1 = (double)static_cast<const T*>(d.x1)[d.off1 + x];
   const double v2 = (double)static_cast<const T*>(d.x2)[d.off2 + x];
@@ -1871,6 +1944,7 @@ static hipError_t launch_sink_nc(const RowArgs<T>& a, int nb, hipStream_t stream
 
 template <typename T>
 hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream) {
+  if (a.ring) return launch_rows_nc<T, 1, 0>(a, nb, stream);  // HEALPix: one ring pair per group
   if constexpr (sizeof(T) == 4) {
     if ((a.mode == ROW_SINK_U || a.mode == ROW_SINK_V) && a.tw) {
       switch (a.nlon) {

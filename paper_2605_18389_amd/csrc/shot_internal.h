@@ -31,6 +31,17 @@ struct ItemDev {
 
 constexpr int RED_SLOTS = 8;
 
+// One mirror pair of rings of a HEALPix grid (ring j and ring nlat-1-j have
+// the same length and first-pixel longitude).
+constexpr int RING_MAXFAC = 12;
+struct RingDev {
+  int len;                 // pixels per ring
+  int off1, off2;          // first pixel of the northern / southern ring in a field
+  int twoff;               // offset of this length's twiddles exp(-2 pi i k/len) in ring_tw
+  int nfac;                // factors of len (4, 2, 3, 5, then other primes)
+  int fac[RING_MAXFAC];
+};
+
 // Row kernel modes.
 enum RowMode : int {
   ROW_FWD = 0,     // field -> folded spectrum
@@ -89,15 +100,22 @@ struct RowArgs {
   const void* pbuf;   // [chunks][npb][cut_ib][h][2] partial sums (cpx<T>)
   int npb;
   int cut_ib;         // items per Legendre workgroup of that launch
+  // HEALPix grids: per row pair ring geometry, twiddles of every ring length,
+  // and e^{i m phi0} per (row pair, m < L); nullptr for latitude-longitude grids
+  const RingDev* ring;
+  const cpx<T>* ring_tw;
+  const cpx<T>* ring_ph;
 };
 
 // Pointwise combination of per-item fields into a per-pair gradient:
 // out = wa * (x1 - (x2 + x3)/2) + coef * a, wa = a (potentials) or 1.
 struct CombineDev {
   long long off_out, off1, off2, off3;  // element offsets
+  long long n;                          // points per field
   double coef;
   int nlat, nlon, h;
   int mul_area;
+  int equal_area;                       // every point has area aw[0] (HEALPix)
   const void* aw;   // h area weights (field precision)
   const void* x1; const void* x2; const void* x3;
 };

@@ -18,6 +18,10 @@ Generators (all draws from numpy's PCG64 ``default_rng(seed)`` in a fixed order)
                        a 1e-6 floor.  Per measure: K centres, K kappa ~ U[5, 50],
                        K amplitudes ~ U[-0.2, 0.2].
 * ``uniform_field`` -- i.i.d. U[0, 1] per point, normalised.
+
+The ``*_at`` variants take any point set instead of a latitude-longitude grid
+(e.g. HEALPix pixel centres): per point z = cos(colatitude), longitude phi
+and area weight, same draws in the same order.
 """
 
 import math
@@ -108,3 +112,45 @@ def batch_pair_params(seed, npairs):
             tau = (0.1, 1.0, 10.0)[int(rng.integers(0, 3))]
             out.append((t, tau, 1.05))
     return out
+
+
+def _points_at(z, phi):
+    z = np.asarray(z, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    st = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    return np.stack([np.cos(phi) * st, np.sin(phi) * st, z], -1)
+
+
+def _normalise_at(f, area, total):
+    return f * (total / float((np.asarray(area, dtype=np.float64) * f).sum()))
+
+
+def temperature_like_at(rng, z, phi, area, K=8, floor=1e-6, total=1.0):
+    X = _points_at(z, phi)
+    mu = _centres(rng, K)
+    kap = rng.uniform(5.0, 50.0, K)
+    amp = rng.uniform(-0.2, 0.2, K)
+    anom = np.ones(X.shape[0])
+    for k in range(K):
+        anom += amp[k] * np.exp(kap[k] * (X @ mu[k] - 1.0))
+    f = np.maximum((1.0 - np.asarray(z, dtype=np.float64) ** 2) * anom, 0.0) + floor
+    return _normalise_at(f, area, total)
+
+
+def uniform_at(rng, area, total=1.0):
+    f = rng.uniform(0.0, 1.0, np.asarray(area).shape)
+    return _normalise_at(f, area, total)
+
+
+def temperature_pair_at(seed, z, phi, area, K=8, q_mass=1.0):
+    """Two ``temperature_like_at`` measures on a point set; q has mass ``q_mass``."""
+    rng = np.random.default_rng(seed)
+    p = temperature_like_at(rng, z, phi, area, K)
+    q = temperature_like_at(rng, z, phi, area, K, total=q_mass)
+    return p, q
+
+
+def uniform_pair_at(seed, area):
+    """Two ``uniform_at`` probability measures (the paper's runtime workload)."""
+    rng = np.random.default_rng(seed)
+    return uniform_at(rng, area), uniform_at(rng, area)

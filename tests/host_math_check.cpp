@@ -120,6 +120,57 @@ static int check_checkpoints(int L, int nx, int part_rows) {
   return 0;
 }
 
+// HEALPix rings: 12 nside^2 pixels on 4 nside - 1 rings, mirror symmetric,
+// and equal-area: the cap above a ring's centres holds the rings above it and
+// half of the ring, 2 pi (1 - z) = (pixels above + N/2) 4 pi / Npix.
+static int check_healpix(int nside) {
+  std::vector<double> z, phi0;
+  std::vector<int> np;
+  healpix_rings(nside, z, np, phi0);
+  const int nr = 4 * nside - 1;
+  if ((int)z.size() != nr) return fail("ring count", nside, (long long)z.size());
+  long long tot = 0, above = 0;
+  const double npix = 12.0 * nside * nside;
+  for (int r = 0; r < nr; ++r) {
+    tot += np[r];
+    if (np[r] != np[nr - 1 - r] || std::fabs(z[r] + z[nr - 1 - r]) > 1e-15 ||
+        std::fabs(phi0[r] - phi0[nr - 1 - r]) > 1e-15)
+      return fail("mirror symmetry", nside, r);
+    if (phi0[r] < 0 || phi0[r] >= 2 * M_PI / np[r]) return fail("first longitude", nside, r);
+    const double cap = 2 * M_PI * (1 - z[r]), want = (above + np[r] / 2.0) * 4 * M_PI / npix;
+    if (std::fabs(cap - want) > 1e-13) return fail("equal area", nside, r);
+    above += np[r];
+  }
+  if (tot != 12LL * nside * nside) return fail("pixel count", nside, tot);
+  return 0;
+}
+
+// Factor lists multiply back to n, 4/2/3/5 first, then primes ascending.
+static int check_factors() {
+  for (int n = 1; n <= 4096; ++n) {
+    const std::vector<int> f = fft_factors(n);
+    long long prod = 1;
+    int stage = 0;  // 0: 4/2/3/5 section, 1: other primes
+    int last = 0;
+    for (int r : f) {
+      prod *= r;
+      const bool small = (r == 2 || r == 3 || r == 4 || r == 5);
+      if (!small) {
+        if (r < 7) return fail("factor", n, r);
+        for (int d = 2; d * d <= r; ++d)
+          if (r % d == 0) return fail("composite factor", n, r);
+        if (stage == 1 && r < last) return fail("factor order", n, r);
+        stage = 1;
+        last = r;
+      } else if (stage == 1) {
+        return fail("small factor after a prime", n, r);
+      }
+    }
+    if (prod != n) return fail("factor product", n, prod);
+  }
+  return 0;
+}
+
 int main() {
   int rc = 0;
   for (int L : {1, 15, 16, 17, 90, 181, 720})
@@ -130,6 +181,8 @@ int main() {
   rc |= check_checkpoints(80, 40, 0);
   rc |= check_checkpoints(80, 40, 64);
   rc |= check_checkpoints(150, 75, 64);
+  for (int nside : {1, 2, 3, 7, 8, 64, 256}) rc |= check_healpix(nside);
+  rc |= check_factors();
   if (!rc) std::printf("OK\n");
   return rc;
 }
