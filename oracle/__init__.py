@@ -8,7 +8,7 @@ from it; the two meet only through seeded input arrays.
 
 Everything is float64 NumPy, written step by step from the paper:
 
-* ``grids``      -- Gauss-Legendre and Clenshaw-Curtis (equiangular with poles)
+* ``grids``      -- Gauss-Legendre, Gauss-Lobatto and Clenshaw-Curtis (equiangular with poles)
                     latitude quadrature and area weights (App. C.1 "Discretizations
                     of S^2", App. C.2 "Discrete OT on the Sphere").
 * ``legendre``   -- orthonormal associated Legendre functions P̄_l^m (App. B,
@@ -22,22 +22,25 @@ Everything is float64 NumPy, written step by step from the paper:
 * ``sinkhorn``   -- Algorithm 1 (balanced and unbalanced branches), potentials,
                     cost (App. C.2 eq. for OT^tau_{C,eps}), convergence check
                     (App. C.3), divergence (Def. 2.3), envelope gradient (Sec. 4.2.2).
+* ``attribution`` -- centred gradient field and its area-weighted RMS per
+                    latitude band (Sec. 4.2.2, regional attribution).
 
 Readings where the paper is silent or inconsistent are listed in the design doc
 (heat time t = eps/4 everywhere, l < L, Alg. 1 taken literally, ...).
 """
 
-from .grids import Grid, gauss_legendre, clenshaw_curtis, make_grid
+from .grids import Grid, gauss_legendre, gauss_lobatto, clenshaw_curtis, make_grid
 from .healpix import HealpixGrid, ring_geometry
 from .legendre import legendre_table, normalised_legendre_column
 from .sht import analysis, synthesis, heat_apply, heat_multipliers
 from .dense import dense_heat_matrix, dense_heat_apply
 from .sinkhorn import sinkhorn, divergence, envelope_gradient, fd_directional
+from .attribution import regional_rms, latitudes
 
 __all__ = [
-    "Grid", "gauss_legendre", "clenshaw_curtis", "make_grid", "HealpixGrid", "ring_geometry",
+    "Grid", "gauss_legendre", "gauss_lobatto", "clenshaw_curtis", "make_grid", "HealpixGrid", "ring_geometry",
     "legendre_table", "normalised_legendre_column",
     "analysis", "synthesis", "heat_apply", "heat_multipliers",
     "dense_heat_matrix", "dense_heat_apply",
-    "sinkhorn", "divergence", "envelope_gradient", "fd_directional",
+    "sinkhorn", "divergence", "envelope_gradient", "fd_directional", "regional_rms", "latitudes",
 ]

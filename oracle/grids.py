@@ -62,9 +62,38 @@ def clenshaw_curtis(n):
     return np.cos(theta), w
 
 
+def gauss_lobatto(n):
+    """Gauss-Lobatto nodes (descending: x = 1 first) and weights (sum 2), n >= 2.
+
+    App. C.1's Lobatto grid: rows at the poles and at the zeros of P'_{n-1},
+    i.e. the zeros of (1 - x^2) P'_{n-1}(x); the weights of this rule are
+    w_j = 2 / (n (n-1) P_{n-1}(x_j)^2), and it integrates polynomials of degree
+    up to 2n - 3 exactly.  Interior nodes by Newton's method on P'_{n-1},
+    whose derivative follows from Legendre's equation:
+    (1 - x^2) P''_{n-1} = 2 x P'_{n-1} - n (n-1) P_{n-1}.
+    """
+    if n < 2:
+        raise ValueError("a Lobatto rule needs at least the two poles")
+    N = n - 1
+    x = np.cos(np.pi * np.arange(n, dtype=np.float64) / N)   # Chebyshev-Lobatto start
+    xi = x[1:-1].copy()
+    for _ in range(100):
+        p, dp = _legendre_p_and_dp(N, xi)
+        d2p = (2.0 * xi * dp - N * (N + 1) * p) / (1.0 - xi * xi)
+        dx = dp / d2p
+        xi = xi - dx
+        if xi.size == 0 or np.max(np.abs(dx)) < 1e-16:
+            break
+    x[1:-1] = xi
+    x[0], x[-1] = 1.0, -1.0
+    pN = np.array([_legendre_p_and_dp(N, np.array([v]))[0][0] if abs(v) < 1 else (v ** N) for v in x])
+    w = 2.0 / (n * N * pN * pN)
+    return x, w
+
+
 @dataclass
 class Grid:
-    kind: str          # "gl" (Gauss-Legendre) or "cc" (Clenshaw-Curtis, equiangular with poles)
+    kind: str          # "gl" (Gauss-Legendre), "cc" (Clenshaw-Curtis, equiangular with poles) or "lob" (Gauss-Lobatto)
     nlat: int
     nlon: int
     L: int             # band limit: degrees and orders l, m < L
@@ -107,6 +136,8 @@ def make_grid(kind, nlat, nlon, L):
         x, w = gauss_legendre(nlat)
     elif kind == "cc":
         x, w = clenshaw_curtis(nlat)
+    elif kind == "lob":
+        x, w = gauss_lobatto(nlat)
     else:
         raise ValueError(kind)
     return Grid(kind, nlat, nlon, L, x, w)
