@@ -154,6 +154,59 @@ def bench_uneven_batch(torch, precision, legendre, reps=1):
             "pairs_with_breakdown": bad}
 
 
+def bench_healpix(torch, nside, precision, T=200):
+    """The runtime workload on HEALPix: a pair of uniform random probability
+    measures (normalised by the pixel areas), eps = 0.1, balanced, band limit
+    L = 2 Nside; Sinkhorn iterations per second (graph replay)."""
+    from paper_2605_18389_amd import Plan, synth
+    L = 2 * nside
+    plan = Plan([("hp", nside, L)], precision=precision, legendre="recurrence")
+    p, q = synth.uniform_pair_at(synth.pair_seed(7, nside), plan.area(0))
+    p = torch.as_tensor(p, dtype=plan.dtype, device="cuda")
+    q = torch.as_tensor(q, dtype=plan.dtype, device="cuda")
+    plan.sinkhorn(p, q, 0.1, T=T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = plan.sinkhorn(p, q, 0.1, T=T)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"iterations_per_s": T / dt, "pixels": 12 * nside * nside, "L": L,
+            "status": info[0]["status"], "kratio": info[0]["kratio"]}
+
+
+def bench_climate_attribution(torch, precision, npairs=8, T=300):
+    """The climate study's computation on synthetic fields: npairs pairs on HEALPix
+    Nside 64 (L = 128), eps = 0.01, tau = 100 (unbalanced, masses 1 vs 1.05), T
+    iterations; per pair the divergence, its exact gradient and the five regional
+    RMS indices.  Pairs (with attribution) per second."""
+    from paper_2605_18389_amd import Plan, synth
+    nside, L = 64, 128
+    plan = Plan([("hp", nside, L)], precision=precision, legendre="recurrence")
+    z, phi = plan.pixel_coords(0)
+    area = plan.area(0)
+    ps, qs = [], []
+    for i in range(npairs):
+        p, q = synth.temperature_pair_at(synth.pair_seed(8, i), z, phi, area, K=8, q_mass=1.05)
+        ps.append(p)
+        qs.append(q)
+    p = torch.as_tensor(np.concatenate(ps), dtype=plan.dtype, device="cuda")
+    q = torch.as_tensor(np.concatenate(qs), dtype=plan.dtype, device="cuda")
+
+    def once():
+        S, g, info = plan.divergence_grad(p, q, 0.01, T=T, tau=100.0)
+        return S, plan.regional_rms(g), info
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S, rms, info = once()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"pairs_per_s": npairs / dt, "ms_per_batch": dt * 1e3, "pairs": npairs,
+            "pairs_with_breakdown": sum(1 for i in range(npairs)
+                                        if any(x["status"] == 17 for x in info[3 * i:3 * i + 3]))}
+
+
 def cpu_baseline(budget_s, gpu_heat=None):
     """FP64 oracle on host cores: iterations/s of Alg. 1 on the same workload.
 
@@ -387,6 +440,21 @@ def main():
                                                  "ms_per_divergence": d3 * 1e3}
         except Exception as e:
             sec["divergence_fp32_recurrence"] = {"error": str(e)}
+        for prec in ("fp32", "fp64"):
+            try:
+                log(f"[bench] climate attribution {prec}")
+                sec[f"climate_attribution_hp64_{prec}"] = bench_climate_attribution(torch, prec)
+            except Exception as e:
+                sec[f"climate_attribution_hp64_{prec}"] = {"error": str(e)}
+            torch.cuda.empty_cache()
+        for nside in (64, 256):
+            for prec in ("fp32", "fp64"):
+                try:
+                    log(f"[bench] healpix nside={nside} {prec}")
+                    sec[f"healpix_nside{nside}_{prec}"] = bench_healpix(torch, nside, prec)
+                except Exception as e:
+                    sec[f"healpix_nside{nside}_{prec}"] = {"error": str(e)}
+                torch.cuda.empty_cache()
         out["secondary"] = sec
         bat = {}
         for prec, legm in (("fp32", "recurrence"), ("fp32", "table"), ("bf16", "table")):

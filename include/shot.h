@@ -63,14 +63,16 @@ typedef enum {
   SHOT_E_BREAKDOWN = 17      /* heat-kernel output <= 0 or non-finite (App. C.4)   */
 } shot_status;
 
-enum { SHOT_GRID_GAUSS_LEGENDRE = 0, SHOT_GRID_CLENSHAW_CURTIS = 1, SHOT_GRID_HEALPIX = 2 };
+enum { SHOT_GRID_GAUSS_LEGENDRE = 0, SHOT_GRID_CLENSHAW_CURTIS = 1, SHOT_GRID_HEALPIX = 2, SHOT_GRID_LOBATTO = 3 };
 enum { SHOT_FP64 = 0, SHOT_FP32 = 1, SHOT_BF16_MFMA = 2 };
 enum { SHOT_LEG_AUTO = 0, SHOT_LEG_TABLE = 1, SHOT_LEG_RECURRENCE = 2 };
 
-/* One grid.  kind: SHOT_GRID_GAUSS_LEGENDRE (rows at the roots of P_nlat) or
+/* One grid.  kind: SHOT_GRID_GAUSS_LEGENDRE (rows at the roots of P_nlat),
  * SHOT_GRID_CLENSHAW_CURTIS (equiangular rows theta_j = j*pi/(nlat-1), poles
- * included) -- App. C.1: a field is [nlat][nlon] row-major, requires
- * nlon >= 2L-1, nlon a product of 2, 3 and 5, nlon <= 2048.
+ * included) or SHOT_GRID_LOBATTO (rows at the poles and at the zeros of
+ * P'_{nlat-1}, Gauss-Lobatto weights, exact to degree 2 nlat - 3) -- App. C.1:
+ * a field is [nlat][nlon] row-major, requires nlon >= 2L-1, nlon a product of
+ * 2, 3 and 5, nlon <= 2048.
  *
  * SHOT_GRID_HEALPIX (Sec. 3.3, App. C.1; Gorski et al. 2005): nlat = 4 Nside - 1
  * iso-latitude rings, nlon = 4 Nside (the longest ring), Nside <= 512; a field
@@ -172,12 +174,13 @@ shot_status shot_sinkhorn_divergence(shot_plan_t plan, const int32_t* grid_of_pa
                                      double* S_out, shot_solve_info* info, void* stream);
 
 /* Divergence and its gradient with respect to the density array p (Sec. 4.2.2),
- * balanced pairs only (tau = +INFINITY), with tol = 0.
+ * with tol = 0; the pairs of one call are all balanced (tau = +INFINITY) or all
+ * unbalanced (SHOT_E_UNSUPPORTED otherwise).
  * mode 0: exact reverse-mode derivative of the T-iteration computation
- *         (hand-written adjoint of Alg. 1 and of HeatConv); the forward iterates
- *         are recomputed from checkpoints of v taken every `checkpoint_every`
- *         iterations (0 = ceil(sqrt(T))) instead of being stored.
- * mode 1: envelope gradient from the potentials,
+ *         (hand-written adjoint of Alg. 1, both branches, and of HeatConv); the
+ *         forward iterates are recomputed from checkpoints of v taken every
+ *         `checkpoint_every` iterations (0 = ceil(sqrt(T))) instead of being stored.
+ * mode 1: envelope gradient from the potentials (balanced pairs only),
  *         a (.) (phi_pq - (phi_pp + psi_pp)/2) + eps (m(p)-m(q)) a.
  * dS_dp: device, layout of p.  Other arguments as shot_sinkhorn_divergence. */
 shot_status shot_sinkhorn_divergence_grad(shot_plan_t plan, const int32_t* grid_of_pair,
@@ -185,6 +188,20 @@ shot_status shot_sinkhorn_divergence_grad(shot_plan_t plan, const int32_t* grid_
                                           const void* p, const void* q, double* S_out,
                                           void* dS_dp, int32_t mode, int32_t checkpoint_every,
                                           shot_solve_info* info, void* stream);
+
+/* Regional attribution of a gradient (Sec. 4.2.2, "Gradient-based regional
+ * attribution"): for each pair, g = dS_dp / a (a: point areas) is centred by
+ * its area-weighted mean over the sphere, and its area-weighted RMS over each
+ * latitude band is returned.  dS_dp: device, the layout of
+ * shot_sinkhorn_divergence_grad's output for these pairs.  bands: host,
+ * nbands (lat_lo, lat_hi) pairs in degrees; a row (ring) belongs to a band
+ * when lat_lo < its latitude < lat_hi (rows on an edge are excluded).
+ * rms_out: host, npairs * nbands (NaN for a band holding no row).  The
+ * per-row sums run on the device in float64, the band combination on the
+ * host.  Synchronises `stream`. */
+shot_status shot_gradient_regional_rms(shot_plan_t plan, const int32_t* grid_of_pair, int32_t npairs,
+                                       const void* dS_dp, const double* bands, int32_t nbands,
+                                       double* rms_out, void* stream);
 
 /* Launch configuration of grid `grid`'s Legendre kernel: items advanced per
  * workgroup of the VALU kernels (1, 2, 4 or 8; 0 = automatic, capped by LDS)

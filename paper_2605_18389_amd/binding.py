@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libshot.so")
 GRID_GAUSS_LEGENDRE = 0
 GRID_CLENSHAW_CURTIS = 1
 GRID_HEALPIX = 2
+GRID_LOBATTO = 3
 FP64, FP32, BF16_MFMA = 0, 1, 2
 LEG_AUTO, LEG_TABLE, LEG_RECURRENCE = 0, 1, 2
 
@@ -33,7 +34,8 @@ _PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16_MFMA, "bf16_mfma": BF16_MFMA}
 _LEG = {"auto": LEG_AUTO, "table": LEG_TABLE, "recurrence": LEG_RECURRENCE}
 _KIND = {"gl": GRID_GAUSS_LEGENDRE, "gauss_legendre": GRID_GAUSS_LEGENDRE,
          "cc": GRID_CLENSHAW_CURTIS, "clenshaw_curtis": GRID_CLENSHAW_CURTIS,
-         "equiangular": GRID_CLENSHAW_CURTIS, "hp": GRID_HEALPIX, "healpix": GRID_HEALPIX}
+         "equiangular": GRID_CLENSHAW_CURTIS, "hp": GRID_HEALPIX, "healpix": GRID_HEALPIX,
+         "lob": GRID_LOBATTO, "lobatto": GRID_LOBATTO}
 
 # Every entry point declared in include/shot.h.
 EXPORTS = [
@@ -41,8 +43,14 @@ EXPORTS = [
     "shot_sht_synthesis", "shot_heat_apply", "shot_sinkhorn_solve", "shot_sinkhorn_divergence",
     "shot_sinkhorn_divergence_grad", "shot_profile_enable", "shot_profile_read",
     "shot_status_string", "shot_last_error", "shot_plan_set_tuning", "shot_plan_get_tuning",
-    "shot_autotune", "shot_plan_set_graphs", "shot_plan_ring",
+    "shot_autotune", "shot_plan_set_graphs", "shot_plan_ring", "shot_gradient_regional_rms",
 ]
+
+# The five latitude bands of the regional attribution (Sec. 4.2.2), degrees,
+# bounds exclusive: Tropics |lat| < 23.5, ITCZ |lat| < 10, NH and SH
+# midlatitudes 30-60, Arctic > 66.5 N (the upper bound admits a pole row).
+PAPER_REGIONS = {"tropics": (-23.5, 23.5), "itcz": (-10.0, 10.0), "nh_midlatitudes": (30.0, 60.0),
+                 "sh_midlatitudes": (-60.0, -30.0), "arctic": (66.5, 90.5)}
 
 
 class GridDesc(ctypes.Structure):
@@ -96,6 +104,7 @@ def load_library(path=None):
         "shot_plan_destroy": [vp],
         "shot_plan_grid": [vp, i32, dp, dp],
         "shot_plan_ring": [vp, i32, ip, dp],
+        "shot_gradient_regional_rms": [vp, ip, i32, vp, dp, i32, dp, vp],
         "shot_sht_analysis": [vp, ip, i32, vp, vp, vp],
         "shot_sht_synthesis": [vp, ip, i32, vp, vp, vp],
         "shot_heat_apply": [vp, ip, i32, dp, vp, vp, i32, vp],
@@ -166,7 +175,7 @@ def _grid_tuple(g):
 class Plan:
     """A libshot plan for one or more grids.
 
-    grids: list of (kind, nlat, nlon, L) with kind "gl" or "cc", or ("hp", nside, L) for a
+    grids: list of (kind, nlat, nlon, L) with kind "gl", "cc" or "lob", or ("hp", nside, L) for a
     HEALPix grid (stored as ("hp", 4 nside - 1, 4 nside, L): rings, longest ring, L).
     precision: "fp64", "fp32" or "bf16" (bfloat16 Legendre operands, float32 accumulation).
     legendre: "auto", "table" (P̄ streamed from HBM) or "recurrence" (generated in float64).
@@ -356,13 +365,31 @@ class Plan:
         _check("shot_sinkhorn_divergence", code, allow=(OK, W_NOT_CONVERGED, E_BREAKDOWN))
         return S, self._info_dicts(info, 3 * n)
 
+    def regional_rms(self, dS_dp, bands=None, grid_of_pair=None):
+        """Area-weighted RMS of the centred gradient field dS_dp / a per latitude band.
+        bands: dict name -> (lat_lo, lat_hi) in degrees (default: the paper's five regions).
+        Returns a dict name -> numpy array over pairs."""
+        bands = PAPER_REGIONS if bands is None else bands
+        names = list(bands)
+        goi = self._items(dS_dp, grid_of_pair, "field")
+        n = len(goi)
+        b = np.array([bands[k] for k in names], dtype=np.float64).reshape(-1)
+        out = np.zeros(n * len(names))
+        _check("shot_gradient_regional_rms", self.lib.shot_gradient_regional_rms(
+            self.handle, _i32_array(goi), n, ctypes.c_void_p(dS_dp.data_ptr()),
+            b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(names),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr()))
+        out = out.reshape(n, len(names))
+        return {k: out[:, i] for i, k in enumerate(names)}
+
     def divergence_grad(self, p, q, eps, T=100, C=10, mode="unrolled", checkpoint_every=0,
-                        grid_of_pair=None):
-        """S and dS/dp (balanced).  mode: "unrolled" (exact adjoint with recompute) or "envelope"."""
+                        grid_of_pair=None, tau=math.inf):
+        """S and dS/dp.  mode: "unrolled" (exact adjoint with recompute; balanced or, with a
+        finite tau, unbalanced pairs) or "envelope" (balanced)."""
         torch = _torch()
         goi = self._items(p, grid_of_pair, "field")
         n = len(goi)
-        prm = self._params(n, eps, math.inf, T, C, 0.0)
+        prm = self._params(n, eps, tau, T, C, 0.0)
         S = np.zeros(n)
         g = torch.empty_like(p)
         info = (SolveInfo * (3 * n))()

@@ -38,6 +38,7 @@ struct GridRec {
   shot_grid_desc d{};
   int h = 0, hpad = 0;
   std::vector<double> x, w;
+  std::vector<double> aw_host;  // area weight of each row pair, double precision
   std::vector<int> fac;
   int tab_kind = TAB_F32;
   void* d_tab = nullptr;
@@ -222,6 +223,8 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
     for (int r = 0; r < d.nlat; ++r) g.w[r] = 2.0 * g.ring_npix[r] / npix;
   } else if (d.kind == SHOT_GRID_GAUSS_LEGENDRE) {
     gauss_legendre(d.nlat, g.x, g.w);
+  } else if (d.kind == SHOT_GRID_LOBATTO) {
+    gauss_lobatto(d.nlat, g.x, g.w);
   } else {
     clenshaw_curtis(d.nlat, g.x, g.w);
   }
@@ -234,6 +237,7 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
   std::vector<double> aw(g.h);
   for (int j = 0; j < g.h; ++j)
     aw[j] = g.hp ? 4.0 * M_PI / (12.0 * g.nside * g.nside) : g.w[j] * 2.0 * M_PI / d.nlon;
+  g.aw_host = aw;
   if (g.hp) {
     // ring pairs: geometry, twiddles per distinct length (4k pixels, k = 1..nside), phases
     std::vector<RingDev> rings(g.h);
@@ -660,9 +664,9 @@ const SplitSched* pick_sched(const shot_plan_s* P, const GridRec& g, int nb, int
 }
 
 // Row-split recurrence kernel: used unless a chains-per-thread tuning selects
-// the latitude-split kernel, when ceil(nlat/2) <= 384 and its LDS fits.
+// the latitude-split kernel, when ceil(nlat/2) <= 512 and its LDS fits.
 bool use_split(const shot_plan_s* P, const GridRec& g) {
-  if (g.tab_kind != TAB_RECUR || g.tune_jpt != 0 || g.h > 384) return false;
+  if (g.tab_kind != TAB_RECUR || g.tune_jpt != 0 || g.h > 512) return false;
   return pick_sched(P, g, 1, 1) != nullptr;
 }
 
@@ -684,7 +688,7 @@ int mma_tiles(const shot_plan_s* P, const GridRec& g, int count) {
 
 int split_ib(const shot_plan_s* P, const GridRec& g, int count) {
   int ib = (g.tune_ib == 2 || (g.tune_ib == 0 && count >= 2)) ? 2 : 1;
-  if (ib == 2 && !pick_sched(P, g, count, 2)) ib = 1;
+  if (ib == 2 && (g.h > 384 || !pick_sched(P, g, count, 2))) ib = 1;  // 2 items: at most 6 chains per lane
   return ib;
 }
 
@@ -1118,9 +1122,11 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
   const int nitems = (int)S.grid.size();
   ST_TRY(make_layout(P, S.grid.data(), nitems, Lo));
   const int Tit = S.prm[0].max_iter;
+  const bool unbal = !std::isinf(S.prm[0].tau);  // every item of a call takes the same branch
   for (int i = 0; i < nitems; ++i) {
     ST_TRY(check_params(S.prm[i]));
-    if (!std::isinf(S.prm[i].tau) || S.prm[i].tol != 0 || S.prm[i].max_iter != Tit) return SHOT_E_UNSUPPORTED;
+    if (std::isinf(S.prm[i].tau) == unbal || S.prm[i].tol != 0 || S.prm[i].max_iter != Tit)
+      return SHOT_E_UNSUPPORTED;
   }
   if (CK <= 0) CK = (int)std::ceil(std::sqrt((double)Tit));
   CK = std::min(CK, Tit);
@@ -1143,7 +1149,8 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
   const size_t o_gA = take(sizeof(T) * F), o_gB = take(sizeof(T) * F);
   const size_t o_hu = take(sizeof(T) * F * CK), o_hv = take(sizeof(T) * F * CK);
   const size_t o_ckv = take(sizeof(T) * F * std::max(nck, 1));
-  const size_t o_gh = take(sizeof(double) * nitems * (CK + 1));
+  const size_t o_gh = take(sizeof(double) * nitems * (CK + 1) * 3);
+  const size_t o_vbar = take(unbal ? sizeof(T) * F : 0);
   const size_t o_ckg = take(sizeof(double) * nitems * std::max(nck, 1));
   const size_t o_adjp = take(sizeof(double) * nitems * Lo.hs);
   ST_TRY(grow(P->ws2, off));
@@ -1157,6 +1164,7 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
   double* gh = reinterpret_cast<double*>(b + o_gh);
   double* ckg = reinterpret_cast<double*>(b + o_ckg);
   double* adjp = reinterpret_cast<double*>(b + o_adjp);
+  T* vbar = reinterpret_cast<T*>(b + o_vbar);
 
   auto base_args = [&](const Group& G, const GridRec& g) {
     RowArgs<T> a = row_args<T>(P, g, Lo, G, W, nitems);
@@ -1164,6 +1172,7 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
     a.gB = gB;
     a.adjp = adjp;
     a.kT = Tit;
+    a.vbar = vbar;
     return a;
   };
   auto each = [&](auto&& fn) -> shot_status {
@@ -1239,10 +1248,11 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
         if (k == k0 + 1 && k0 > 0) a.gk = ckg + (size_t)(seg - 1) * nitems;
         return run_rows<T>(P, a, G.count, s);
       }));
-      for (const Group& G : Lo.groups) {
-        RowArgs<T> a = base_args(G, P->grids[G.grid]);
-        HIP_TRY(launch_gauge<T>(a, G.count, k, gh + (size_t)slot * nitems, s));
-      }
+      if (!unbal)  // s_k = sum u-hat_k
+        for (const Group& G : Lo.groups) {
+          RowArgs<T> a = base_args(G, P->grids[G.grid]);
+          HIP_TRY(launch_gauge<T>(a, G.count, k, gh + (size_t)slot * nitems, s));
+        }
       ST_TRY(each([&](const Group& G, const GridRec& g) {
         shot_status st = leg(G, g, W.spec);
         if (st != SHOT_OK) return st;
@@ -1252,8 +1262,49 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
         a.vbuf0 = a.vbuf1 = hv + F * slot;
         return run_rows<T>(P, a, G.count, s);
       }));
+      if (unbal)  // (g_k, S_A, S_B): needs both halves' partial sums
+        for (const Group& G : Lo.groups) {
+          RowArgs<T> a = base_args(G, P->grids[G.grid]);
+          HIP_TRY(launch_gauge3<T>(a, G.count, k, gh + (size_t)slot * nitems * 3, s));
+        }
     }
     // walk the segment backwards
+    if (unbal) {
+      for (int k = k1; k > k0; --k) {
+        const int slot = k - k0 - 1;
+        auto hist = [&](RowArgs<T>& a) {
+          a.k = k;
+          a.spec = specA;
+          a.ubuf0 = a.ubuf1 = hu + F * slot;
+          a.vbuf0 = a.vbuf1 = hv + F * slot;
+          a.gk = gh + (size_t)slot * nitems * 3;
+        };
+        // v-bar_k: from the cost at k = T, else K^T of the A-bar_{k+1} spectrum heat-applied below
+        ST_TRY(each([&](const Group& G, const GridRec& g) {
+          RowArgs<T> a = base_args(G, g);
+          a.mode = ROW_ADJU_V1;
+          hist(a);
+          return run_rows<T>(P, a, G.count, s);
+        }));
+        ST_TRY(each([&](const Group& G, const GridRec& g) {
+          RowArgs<T> a = base_args(G, g);
+          a.mode = ROW_ADJU_B;
+          hist(a);
+          return run_rows<T>(P, a, G.count, s);
+        }));
+        ST_TRY(each([&](const Group& G, const GridRec& g) {
+          shot_status st = leg(G, g, specA);
+          if (st != SHOT_OK) return st;
+          RowArgs<T> a = base_args(G, g);
+          a.mode = ROW_ADJU_A;
+          hist(a);
+          return run_rows<T>(P, a, G.count, s);
+        }));
+        if (k == 1) break;
+        ST_TRY(each([&](const Group& G, const GridRec& g) { return leg(G, g, specA); }));
+      }
+      continue;
+    }
     for (int k = k1; k > k0; --k) {
       const int slot = k - k0 - 1;
       if (!started) {
@@ -1327,9 +1378,12 @@ shot_status divergence_grad_impl(shot_plan_s* P, const int32_t* gop, int npairs,
                                  shot_solve_info* info, hipStream_t s) {
   Layout Lp;
   ST_TRY(make_layout(P, gop, npairs, Lp));
+  // unrolled: balanced or unbalanced, every pair of a call the same; the
+  // envelope form (the potentials' formula of Sec. 4.2.2) is balanced only
+  const bool unbal = !std::isinf(params[0].tau);
   for (int i = 0; i < npairs; ++i) {
     ST_TRY(check_params(params[i]));
-    if (!std::isinf(params[i].tau) || params[i].tol != 0) return SHOT_E_UNSUPPORTED;
+    if (params[i].tol != 0 || std::isinf(params[i].tau) == unbal || (mode == 1 && unbal)) return SHOT_E_UNSUPPORTED;
   }
   const T* pb = static_cast<const T*>(p);
   const T* qb = static_cast<const T*>(q);
@@ -1420,6 +1474,63 @@ shot_status divergence_grad_impl(shot_plan_s* P, const int32_t* gop, int npairs,
   return combine_pairs<T>(P, dv, dS, s);
 }
 
+template <typename T>
+shot_status regional_rms_impl(shot_plan_s* P, const int32_t* gop, int npairs, const void* d, const double* bands,
+                              int nbands, double* out, hipStream_t s) {
+  Layout Lo;
+  ST_TRY(make_layout(P, gop, npairs, Lo));
+  Work<T> W;
+  ST_TRY(carve<T>(P, Lo, npairs, false, 0, W));
+  std::fill(out, out + (size_t)npairs * nbands, std::nan(""));
+  for (const Group& G : Lo.groups) {
+    const GridRec& g = P->grids[G.grid];
+    const int nlat = g.d.nlat;
+    std::vector<long long> foff(G.count);
+    for (int i = 0; i < G.count; ++i) foff[i] = Lo.user_foff[Lo.order[G.first + i]];
+    long long* d_foff = nullptr;
+    double* d_aw = nullptr;
+    double* d_out = nullptr;
+    ST_TRY(upload((void**)&d_foff, foff, s));
+    shot_status sa = upload((void**)&d_aw, g.aw_host, s);
+    if (sa != SHOT_OK) { (void)hipFree(d_foff); return sa; }
+    hipError_t e = hipMalloc((void**)&d_out, sizeof(double) * 3 * nlat * G.count);
+    if (e != hipSuccess) {
+      (void)hipFree(d_foff);
+      (void)hipFree(d_aw);
+      return hip_fail(e, "hipMalloc", __LINE__);
+    }
+    RowArgs<T> a = row_args<T>(P, g, Lo, G, W, npairs);
+    e = launch_row_stats<T>(a, G.count, static_cast<const T*>(d), d_foff, d_aw, d_out, s);
+    std::vector<double> st((size_t)3 * nlat * G.count);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.data(), d_out, sizeof(double) * st.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_foff);
+    (void)hipFree(d_aw);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_fail(e, "regional statistics", __LINE__);
+    for (int i = 0; i < G.count; ++i) {
+      const int ui = Lo.order[G.first + i];
+      const double* r = st.data() + (size_t)i * nlat * 3;
+      double A0 = 0, A1 = 0;
+      for (int j = 0; j < nlat; ++j) { A0 += r[3 * j]; A1 += r[3 * j + 1]; }
+      const double mean = A1 / A0;
+      for (int b = 0; b < nbands; ++b) {
+        double B0 = 0, B1 = 0, B2 = 0;
+        for (int j = 0; j < nlat; ++j) {
+          const double lat = std::asin(std::max(-1.0, std::min(1.0, g.x[j]))) * 180.0 / M_PI;
+          if (lat > bands[2 * b] && lat < bands[2 * b + 1]) {
+            B0 += r[3 * j];
+            B1 += r[3 * j + 1];
+            B2 += r[3 * j + 2];
+          }
+        }
+        if (B0 > 0) out[(size_t)ui * nbands + b] = std::sqrt(std::max(0.0, (B2 - 2 * mean * B1 + mean * mean * B0) / B0));
+      }
+    }
+  }
+  return SHOT_OK;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1449,7 +1560,8 @@ shot_status shot_sht_plan(shot_plan_t* out, const shot_grid_desc* grids, int32_t
   if (legendre_mode < SHOT_LEG_AUTO || legendre_mode > SHOT_LEG_RECURRENCE) return SHOT_E_INVALID;
   for (int i = 0; i < ngrids; ++i) {
     const shot_grid_desc& d = grids[i];
-    if (d.kind != SHOT_GRID_GAUSS_LEGENDRE && d.kind != SHOT_GRID_CLENSHAW_CURTIS && d.kind != SHOT_GRID_HEALPIX)
+    if (d.kind != SHOT_GRID_GAUSS_LEGENDRE && d.kind != SHOT_GRID_CLENSHAW_CURTIS && d.kind != SHOT_GRID_HEALPIX &&
+        d.kind != SHOT_GRID_LOBATTO)
       return SHOT_E_INVALID;
     if (d.kind == SHOT_GRID_HEALPIX) {
       if (d.L < 1 || d.nlon < 4 || d.nlon % 4 != 0 || d.nlat != d.nlon - 1) return SHOT_E_INVALID;
@@ -1506,6 +1618,15 @@ shot_status shot_plan_grid(shot_plan_t P, int32_t grid, double* x_out, double* w
   if (x_out) std::copy(g.x.begin(), g.x.end(), x_out);
   if (w_out) std::copy(g.w.begin(), g.w.end(), w_out);
   return SHOT_OK;
+}
+
+shot_status shot_gradient_regional_rms(shot_plan_t P, const int32_t* goi, int32_t npairs, const void* d,
+                                       const double* bands, int32_t nbands, double* out, void* stream) {
+  if (!P || !goi || npairs <= 0 || !ptr_ok(d) || !bands || nbands <= 0 || !out) return SHOT_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(P->dev));
+  return P->prec == SHOT_FP64 ? regional_rms_impl<double>(P, goi, npairs, d, bands, nbands, out, s)
+                              : regional_rms_impl<float>(P, goi, npairs, d, bands, nbands, out, s);
 }
 
 shot_status shot_plan_ring(shot_plan_t P, int32_t grid, int32_t* npix_out, double* phi0_out) {

@@ -77,6 +77,50 @@ void clenshaw_curtis(int n, std::vector<double>& x, std::vector<double>& w) {
   if (n % 2 == 1) x[n / 2] = 0.0;
 }
 
+void gauss_lobatto(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const int N = n - 1;
+  // P_N and P_N' by the three-term recurrence (plain Legendre polynomials)
+  auto pn = [N](double t, double& p, double& dp) {
+    double p0 = 1.0, p1 = t;
+    if (N == 0) { p = 1.0; dp = 0.0; return; }
+    for (int k = 1; k < N; ++k) {
+      const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+      p0 = p1;
+      p1 = p2;
+    }
+    p = p1;
+    dp = N * (t * p1 - p0) / (t * t - 1.0);
+  };
+  x[0] = 1.0;
+  x[N] = -1.0;
+  for (int j = 1; j < N; ++j) {
+    // Newton on P_N' from the Chebyshev-Lobatto point; Legendre's equation gives
+    // (1 - t^2) P_N'' = 2 t P_N' - N (N + 1) P_N
+    double t = std::cos(M_PI * j / N);
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      pn(t, p, dp);
+      const double d2p = (2.0 * t * dp - N * (N + 1.0) * p) / (1.0 - t * t);
+      const double dt = dp / d2p;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    x[j] = t;
+  }
+  for (int j = 0; j < n; ++j) {
+    double p;
+    if (j == 0) p = 1.0;
+    else if (j == N) p = (N % 2) ? -1.0 : 1.0;
+    else {
+      double dp;
+      pn(x[j], p, dp);
+    }
+    w[j] = 2.0 / (n * (double)N * p * p);
+  }
+}
+
 std::vector<int> fft_factors(int n) {
   std::vector<int> f;
   if (n < 1) return f;

@@ -32,6 +32,11 @@ inline SHOT_HD int mma_rpad(int n) { return (n + 31) / 32 * 32; }
 // the rows of a Gauss-Legendre grid sit at the roots of P_nlat (App. C.1).
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 
+// Gauss-Lobatto rule (App. C.1, Lobatto): nodes at the poles and at the zeros
+// of P'_{n-1} (descending, x = 1 first), weights 2 / (n (n-1) P_{n-1}(x_j)^2);
+// exact to polynomial degree 2n - 3.  n >= 2.
+void gauss_lobatto(int n, std::vector<double>& x, std::vector<double>& w);
+
 // Clenshaw-Curtis rule on theta_j = j pi/(n-1), poles included (App. C.1).
 void clenshaw_curtis(int n, std::vector<double>& x, std::vector<double>& w);
 

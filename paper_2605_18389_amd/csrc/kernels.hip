@@ -122,7 +122,7 @@ __device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ src, c
 // being sum_r src[b + r N/R] w^{r (k N/(Ns R) + q N/R)} with w the length-N
 // root, so every term costs one table lookup.
 template <typename T>
-__device__ void stockham_stage_generic(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst, int N, int Ns,
+__device__ __forceinline__ void stockham_stage_generic(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst, int N, int Ns,
                                        int R, int nb, const cpx<T>* __restrict__ tw, T sign) {
   const int NR = N / R;
   const int twstride = N / (Ns * R);
@@ -133,20 +133,42 @@ __device__ void stockham_stage_generic(const cpx<T>* __restrict__ src, cpx<T>* _
     const cpx<T>* s = src + t * N;
     const int e = k * twstride + q * NR;
     cpx<T> acc = {(T)0, (T)0};
-    int idx = 0;  // r * e mod N, advanced by e
-    for (int r = 0; r < R; ++r) {
+    int idx = 0;  // r * e mod N, advanced by e (< N, so one subtraction wraps it)
+    int r = 0;
+    // eight terms per step: their LDS reads are all in flight before the first use
+    for (; r + 8 <= R; r += 8) {
+      int ix[8];
+      cpx<T> v[8], w[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        ix[j] = idx;
+        idx += e;
+        idx = idx >= N ? idx - N : idx;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        v[j] = s[b + (r + j) * NR];
+        w[j] = tw[ix[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        w[j].y *= -sign;  // table holds exp(-2 pi i k/N); inverse uses the conjugate
+        acc = cadd(acc, cmul(v[j], w[j]));
+      }
+    }
+    for (; r < R; ++r) {
       cpx<T> w = tw[idx];
-      w.y *= -sign;  // table holds exp(-2 pi i k/N); inverse uses the conjugate
+      w.y *= -sign;
       acc = cadd(acc, cmul(s[b + r * NR], w));
       idx += e;
-      if (idx >= N) idx -= N * (idx / N);
+      idx = idx >= N ? idx - N : idx;
     }
     dst[t * N + (b / Ns) * Ns * R + k + q * Ns] = acc;
   }
 }
 
 template <typename T>
-__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int N, int nb, const int* fac, int nfac,
+__device__ __forceinline__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int N, int nb, const int* fac, int nfac,
                            const cpx<T>* __restrict__ tw, T sign) {
   int Ns = 1;
   cpx<T>* src = a;
@@ -373,6 +395,21 @@ __device__ __forceinline__ int xcd_row_pair(int b, int h) {
 // with K^T x = a (.) K(x / a): the forward FFT skips the area weights and the
 // inverse side multiplies by them.  u-bar_T = eps a p / u_T, v-bar_T = eps a q / v_T,
 // and the cost contributes eps a log u_T to p-bar and eps a log v_T to q-bar.
+//
+// Unbalanced iteration k (lambda = tau/(tau+eps), eta = eps/tau):
+//   u-hat = (p / K v_{k-1})^lambda, v-hat = (q / K u-hat)^lambda,
+//   S_A = sum a p u-hat^-eta, S_B = sum a q v-hat^-eta, g = (S_A / S_B)^(-1/(2 eta)),
+//   u_k = u-hat / g, v_k = g v-hat;  cost R = tau sum a (p (1 - u_T^-eta) + q (1 - v_T^-eta)).
+// K v_{k-1} = p u-hat^(-1/lambda) and K u-hat = q v-hat^(-1/lambda) are recovered
+// pointwise.  Reverse step k, given v-bar_k (at k = T: eps a q v_T^(-eta-1), and
+// u-bar_T = eps a p u_T^(-eta-1)):
+//   g-bar = sum v-bar v-hat (- sum u-bar_T u-hat / g^2 at k = T)
+//   S_A-bar = -g-bar g / (2 eta S_A),  S_B-bar = g-bar g / (2 eta S_B)
+//   v-hat-bar = g v-bar - eta S_B-bar a q v-hat^(-eta-1)
+//   q-bar += S_B-bar a v-hat^-eta + lambda v-hat-bar v-hat / q,  B-bar = -lambda v-hat-bar v-hat^(1+1/lambda) / q
+//   u-hat-bar = K^T B-bar - eta S_A-bar a p u-hat^(-eta-1) (+ u-bar_T / g at k = T)
+//   p-bar += S_A-bar a u-hat^-eta + lambda u-hat-bar u-hat / p,  A-bar = -lambda u-hat-bar u-hat^(1+1/lambda) / p
+//   v-bar_{k-1} = K^T A-bar;  the cost adds tau a (1 - u_T^-eta) to p-bar and tau a (1 - v_T^-eta) to q-bar.
 
 // Kernel ratio of one half-iteration (min over all rows of K. / max), folded
 // into the item's running minimum.  Called by one block per item.
@@ -400,8 +437,8 @@ __device__ void kratio_fold(const RowArgs<T>& A, int it, int k, int slot, double
 // partial sums are written at the group's first pair (the other slots of the
 // group get the neutral element) so all consumers still reduce over j < h.
 // ---------------------------------------------------------------------------
-template <typename T, int RPW, int NC>
-__global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
+template <typename T, int RPW, int NC, int BS = 256>
+__global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int L = A.L, h = A.h;
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
@@ -482,17 +519,23 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
   }
   cpx<T>* X = buf0;
   const bool has_inverse = (mode == ROW_INV || mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK ||
-                            mode == ROW_ADJ_A || mode == ROW_ADJ_VB);
+                            mode == ROW_ADJ_A || mode == ROW_ADJ_VB || mode == ROW_ADJU_A ||
+                            (mode == ROW_ADJU_V1 && A.k < A.kT));
   if (has_inverse && RG) {
     // HEALPix ring pair: row r's field is sum_{|m| < L} G_m e^{i m (phi0 + 2 pi k/N)}
     // with G_{-m} = conj(G_m); with P_m = G_m e^{i m phi0}, order m lands in bin
     // m mod N and -m in bin -m mod N of the pair's packed spectrum
     // Z = C_j + i C_j' (orders beyond the ring's length alias, as the samples do).
+    // Short rings collect many orders per bin: G threads share a bin (orders
+    // split by stride G N) and their partials are added in a fixed order.
+    __shared__ cpx<T> ringpart[BS];
     const cpx<T>* ph = A.ring_ph + (size_t)jp0 * L;
     const bool eq = (jp0 == nlat - 1 - jp0);
-    for (int c = tid; c < N; c += bs) {
+    const int G = N >= bs ? 1 : bs / N;  // N * G <= bs = BS
+    for (int t = tid; t < N * G; t += bs) {
+      const int c = t % N, g = t / N;
       cpx<T> z = {(T)0, (T)0};
-      for (int m = c; m < L; m += N) {
+      for (int m = c + g * N; m < L; m += G * N) {
         cpx<T> ge, go;
         load_spec_pair(A, spec, it, m, jp0, ge, go);
         const cpx<T> a = cmul(cadd(ge, go), ph[m]);
@@ -500,7 +543,7 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
         z.x += a.x - b.y;
         z.y += a.y + b.x;
       }
-      for (int m = (c == 0 ? N : N - c); m < L; m += N) {
+      for (int m = (c == 0 ? N : N - c) + g * N; m < L; m += G * N) {
         cpx<T> ge, go;
         load_spec_pair(A, spec, it, m, jp0, ge, go);
         const cpx<T> a = cmul(cadd(ge, go), ph[m]);
@@ -508,7 +551,16 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
         z.x += a.x + b.y;
         z.y += -a.y + b.x;
       }
-      buf0[c] = z;
+      if (G == 1) buf0[c] = z;
+      else ringpart[t] = z;
+    }
+    if (G > 1) {
+      __syncthreads();
+      for (int c = tid; c < N; c += bs) {
+        cpx<T> z = ringpart[c];
+        for (int g = 1; g < G; ++g) z = cadd(z, ringpart[g * N + c]);
+        buf0[c] = z;
+      }
     }
     __syncthreads();
     X = fft_lds<T>(buf0, buf1, N, 1, RG->fac, RG->nfac, tws, (T)1);
@@ -652,6 +704,62 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
       }
       X[pr * N + c] = {nv[0], eq ? (T)0 : nv[1]};
     }
+  } else if (mode == ROW_ADJU_V1 || mode == ROW_ADJU_B || mode == ROW_ADJU_A) {
+    // Reverse sweep of the unbalanced iteration (see adjoint notes above).
+    // gk[3 it + {0,1,2}] = (g_k, S_A, S_B) of the iteration being reversed.
+    const double G = A.gk[3 * it], SA = A.gk[3 * it + 1], SB = A.gk[3 * it + 2];
+    const T Gt = (T)G;
+    const T* uh = ubuf_of(A, 0) + I.foff;  // u-hat_k
+    const T* vh = vbuf_of(A, 0) + I.foff;  // v-hat_k
+    const T ea = (T)I.eps, lam = (T)I.lam, eta = (T)I.eot, tau = (T)I.tau;
+    const bool last = (A.k == A.kT);
+    T sAb = (T)0, sBb = (T)0;
+    if (mode != ROW_ADJU_V1) {
+      double gb = 0.0;
+      for (int q = tid; q < h; q += bs) gb += A.adjp[(size_t)it * A.hs + q];
+      gb = block_sum(gb, sh);
+      sAb = (T)(-gb * G / (2.0 * I.eot * SA));
+      sBb = (T)(gb * G / (2.0 * I.eot * SB));
+    }
+    for (int idx = tid; idx < np * N; idx += bs) {
+      ROW_PAIR_SETUP(idx)
+      const cpx<T> z = has_inverse ? X[pr * N + c] : cpx<T>{(T)0, (T)0};
+      T nv[2] = {(T)0, (T)0};
+      for (int rr = 0; rr < (eq ? 1 : 2); ++rr) {
+        const long long fidx = (rr ? r2 : r1) + c;
+        const long long fi = fidx - I.foff;
+        const T kt = aj * (rr ? z.y : z.x);  // K^T applied: a (.) (synthesised field)
+        if (mode == ROW_ADJU_V1) {
+          const T v = vh[fi];
+          T vb;
+          if (last) {
+            const T u = uh[fi], pv = P[fidx], qv = Q[fidx];
+            const T uT = u / Gt, vT = Gt * v;
+            const T ubT = ea * aj * pv * pow(uT, -eta - (T)1);
+            vb = ea * aj * qv * pow(vT, -eta - (T)1);
+            acc0 -= (double)ubT * (double)u / (G * G);
+            A.gA[fidx] = tau * aj * ((T)1 - pow(uT, -eta));  // direct terms of the cost
+            A.gB[fidx] = tau * aj * ((T)1 - pow(vT, -eta));
+          } else {
+            vb = kt;
+          }
+          acc0 += (double)vb * (double)v;
+          A.vbar[fidx] = vb;
+        } else if (mode == ROW_ADJU_B) {
+          const T v = vh[fi], qv = Q[fidx];
+          const T vhb = Gt * A.vbar[fidx] - eta * sBb * aj * qv * pow(v, -eta - (T)1);
+          A.gB[fidx] += sBb * aj * pow(v, -eta) + lam * vhb * v / qv;
+          nv[rr] = -lam * vhb * v * pow(v, (T)1 / lam) / qv;
+        } else {
+          const T u = uh[fi], pv = P[fidx];
+          T uhb = kt - eta * sAb * aj * pv * pow(u, -eta - (T)1);
+          if (last) uhb += ea * aj * pv * pow(u / Gt, -eta - (T)1) / Gt;
+          A.gA[fidx] += sAb * aj * pow(u, -eta) + lam * uhb * u / pv;
+          nv[rr] = -lam * uhb * u * pow(u, (T)1 / lam) / pv;
+        }
+      }
+      X[pr * N + c] = {nv[0], eq ? (T)0 : nv[1]};
+    }
   } else {  // ROW_FWD, ROW_INIT: load the input rows
     const T* in = A.in;
     for (int idx = tid; idx < np * N; idx += bs) {
@@ -683,9 +791,10 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
       pr[1] = tid == 0 ? acc1 : 0.0;
       pr[2] = tid == 0 ? acc2 : 0.0;
     }
-  } else if (mode == ROW_ADJ_START || mode == ROW_ADJ_VB) {
+  } else if (mode == ROW_ADJ_START || mode == ROW_ADJ_VB || mode == ROW_ADJU_V1) {
     acc0 = block_sum(acc0, sh);
     if (tid < np) A.adjp[(size_t)it * A.hs + jp0 + tid] = tid == 0 ? acc0 : 0.0;
+    if (mode == ROW_ADJU_V1) return;  // v-bar is consumed pointwise by the next launch
   } else if (mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK) {
     if (A.chk_slot >= 0) {
       acc2 = block_sum(acc2, sh);
@@ -715,7 +824,8 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs<T> A) {
   cpx<T>* other = (X == buf0) ? buf1 : buf0;
   cpx<T>* Z = RG ? fft_lds<T>(X, other, N, 1, RG->fac, RG->nfac, tws, (T)-1)
                  : fft_any<T, NC, RPW>(X, other, N, A.fac, A.nfac, tws, (T)-1);
-  const bool adj = (mode == ROW_ADJ_START || mode == ROW_ADJ_A || mode == ROW_ADJ_VB);
+  const bool adj = (mode == ROW_ADJ_START || mode == ROW_ADJ_A || mode == ROW_ADJ_VB || mode == ROW_ADJU_B ||
+                   mode == ROW_ADJU_A);
   const bool unweighted = (mode == ROW_FWD && !A.wts_in) || adj;
   for (int idx = tid; idx < np * L; idx += bs) {
     const int m = idx / np, pr = idx - m * np;
@@ -1456,6 +1566,13 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
   for (int i = 0; i < IB; ++i)
     for (int q = tid; q < npl; q += 256) bs[(size_t)i * maxpl + q] = make_double2(0.0, 0.0);
 
+  // this order's folded spectrum, loaded once per workgroup into the LDS that
+  // the synthesis partial sums reuse later (read into registers before then)
+  if (A.mode != 2)
+    for (int i = 0; i < nbi; ++i) {
+      const cpx<T>* src = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+      for (int q = tid; q < 2 * h; q += 256) gpart[(size_t)i * 2 * h + q] = src[q];
+    }
   double xj[C];
   const double2* ckp = reinterpret_cast<const double2*>(A.rck) + ((size_t)part * 4 + wave) * h;
   auto checkpoint = [&](int c) {
@@ -1479,7 +1596,7 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
         yE[c][i] = make_double2(0.0, 0.0);
         yO[c][i] = make_double2(0.0, 0.0);
         if (j < h && i < nbi) {
-          const cpx<T>* s = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+          const cpx<T>* s = gpart + (size_t)i * 2 * h;
           const cpx<T> e = s[2 * j], o = s[2 * j + 1];
           yE[c][i] = make_double2((double)e.x, (double)e.y);
           yO[c][i] = make_double2((double)o.x, (double)o.y);
@@ -1676,6 +1793,7 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using MT = MmaTraits<TT>;
   constexpr int NB = 16 * NT, KS = MT::KS, KV = MT::KV;
+  constexpr int KG = sizeof(TT) == 2 ? 8 : 16;  // k-steps whose A operands are loaded together
   const int L = A.L, h = A.h, kpad = A.hpad;
   const int m = blockIdx.x, nr = L - m;
   const int c0 = blockIdx.y * NB;
@@ -1689,16 +1807,22 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
   const long long toff = tri_off(m, L);
   const TT* tab = static_cast<const TT*>(A.tab) + toff * kpad;
 
-  // stage Y (zero beyond h and beyond the last column) and clear b
-  for (int idx = tid; idx < 2 * NB * kpad; idx += 256) {
-    const int par = idx / (NB * kpad), rem = idx % (NB * kpad), n = rem / kpad, j = rem % kpad;
-    float v = 0.f;
+  // stage Y (zero beyond h and beyond the last column) and clear b: one
+  // (parity, column) row per wave at a time, latitudes across the lanes
+  for (int pn = wave; pn < 2 * NB; pn += 4) {
+    const int par = pn / NB, n = pn - par * NB;
     const int col = c0 + n;
-    if (A.mode != 2 && j < h && col < ncol) {
-      const cpx<T> y = A.spec[A.items[A.item0 + (col >> 1)].soff + ((size_t)m * h + j) * 2 + par];
-      v = (float)((col & 1) ? y.y : y.x);
+    const bool cok = A.mode != 2 && col < ncol;
+    const cpx<T>* sp = A.spec + (cok ? A.items[A.item0 + (col >> 1)].soff : 0) + (size_t)m * h * 2 + par;
+    TT* dst = ys + ((size_t)par * NB + n) * ys_ld;
+    for (int j = lane; j < kpad; j += 64) {
+      float v = 0.f;
+      if (cok && j < h) {
+        const cpx<T> y = sp[2 * j];
+        v = (float)((col & 1) ? y.y : y.x);
+      }
+      dst[j] = MT::cvt(v);
     }
-    ys[((size_t)par * NB + n) * ys_ld + j] = MT::cvt(v);
   }
   for (int idx = tid; idx < 2 * NB * bs_ld; idx += 256) bs[idx] = MT::cvt(0.f);
   __syncthreads();
@@ -1715,13 +1839,20 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
         const int r = 2 * rp + par;
         const bool rok = rp < npar;
         const TT* arow = tab + (size_t)(rok ? r : 0) * kpad + lg * KV;
-        for (int k0 = 0; k0 < kpad; k0 += KS) {
-          TT a[KV];
-          MT::load_a(a, arow + k0, rok);
+        // A operands of KG k-steps are fetched together: one memory latency
+        // per group instead of one per step
+        for (int kg = 0; kg < kpad; kg += KG * KS) {
+          TT a[KG][KV];
 #pragma unroll
-          for (int c = 0; c < NT; ++c) {
-            const TT* bp = ys + ((size_t)par * NB + c * 16 + li) * ys_ld + k0 + lg * KV;
-            acc[c] = MT::mma(a, bp, acc[c]);
+          for (int s = 0; s < KG; ++s) MT::load_a(a[s], arow + kg + s * KS, rok && kg + s * KS < kpad);
+#pragma unroll
+          for (int s = 0; s < KG; ++s) {
+            if (kg + s * KS >= kpad) break;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+              const TT* bp = ys + ((size_t)par * NB + c * 16 + li) * ys_ld + kg + s * KS + lg * KV;
+              acc[c] = MT::mma(a[s], bp, acc[c]);
+            }
           }
         }
 #pragma unroll
@@ -1765,13 +1896,18 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
     f32x4_t acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < rpad; k0 += KS) {
-      TT a[KV];
-      MT::load_a(a, trow + k0, true);
+    for (int kg = 0; kg < rpad; kg += KG * KS) {
+      TT a[KG][KV];
 #pragma unroll
-      for (int c = 0; c < NT; ++c) {
-        const TT* bp = bs + ((size_t)par * NB + c * 16 + li) * bs_ld + k0 + lg * KV;
-        acc[c] = MT::mma(a, bp, acc[c]);
+      for (int s = 0; s < KG; ++s) MT::load_a(a[s], trow + kg + s * KS, kg + s * KS < rpad);
+#pragma unroll
+      for (int s = 0; s < KG; ++s) {
+        if (kg + s * KS >= rpad) break;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+          const TT* bp = bs + ((size_t)par * NB + c * 16 + li) * bs_ld + kg + s * KS + lg * KV;
+          acc[c] = MT::mma(a[s], bp, acc[c]);
+        }
       }
     }
 #pragma unroll
@@ -1828,6 +1964,27 @@ __global__ void __launch_bounds__(256) reduce_kernel(RowArgs<T> A, int nchk_done
 // ---------------------------------------------------------------------------
 // Gauge of iteration k per item (g_k = s_k for balanced items), one block per item.
 // ---------------------------------------------------------------------------
+// (g_k, S_A, S_B) of iteration k per item, from the partial sums of its two halves.
+template <typename T>
+__global__ void __launch_bounds__(256) gauge3_kernel(RowArgs<T> A, int k, double* gout) {
+  __shared__ double sh[16];
+  const int it = A.item0 + blockIdx.x;
+  const ItemDev I = A.items[it];
+  const double* R = A.red + ((size_t)(k & 1) * A.nitems_all + it) * (size_t)A.hs * RED_SLOTS;
+  double s0 = 0.0, s1 = 0.0;
+  for (int q = threadIdx.x; q < A.h; q += blockDim.x) {
+    s0 += R[(size_t)q * RED_SLOTS + 0];
+    s1 += R[(size_t)q * RED_SLOTS + 1];
+  }
+  s0 = block_sum(s0, sh);
+  s1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) {
+    gout[3 * it] = I.balanced ? s0 : exp(-(0.5 * I.tau * (log(s0) - log(s1))) / I.eps);
+    gout[3 * it + 1] = s0;
+    gout[3 * it + 2] = s1;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) gauge_kernel(RowArgs<T> A, int k, double* gout) {
   __shared__ double sh[16];
@@ -1836,6 +1993,53 @@ __global__ void __launch_bounds__(256) gauge_kernel(RowArgs<T> A, int k, double*
   const double g = gauge(A, I, it, k, sh);
   if (threadIdx.x == 0) gout[it] = g;
 }
+
+// ---------------------------------------------------------------------------
+// Row statistics of a gradient field for the regional attribution: per
+// (row, item) the float64 sums sum a, sum a g and sum a g^2 of g = d / a over
+// the row's points (d: the field, a: the point areas).  grid = (nlat, items).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) row_stats_kernel(RowArgs<T> A, const T* d, const long long* foff,
+                                                        const double* aw, double* out) {
+  __shared__ double sh[16];
+  const int row = blockIdx.x, it = blockIdx.y;
+  const int nlat = A.nlat;
+  const int jp = row < A.h ? row : nlat - 1 - row;
+  int len = A.nlon;
+  long long start = (long long)row * A.nlon;
+  if (A.ring) {
+    len = A.ring[jp].len;
+    start = row == jp ? A.ring[jp].off1 : A.ring[jp].off2;
+  }
+  const double a = aw[jp];  // double even for float fields: the statistic is taken in double
+  const T* x = d + foff[it] + start;
+  double s1 = 0.0, s2 = 0.0;
+  for (int c = threadIdx.x; c < len; c += blockDim.x) {
+    const double v = (double)x[c];
+    s1 += v;           // a g = d
+    s2 += v * v / a;   // a g^2 = d^2 / a
+  }
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    double* o = out + ((size_t)it * nlat + row) * 3;
+    o[0] = a * len;
+    o[1] = s1;
+    o[2] = s2;
+  }
+}
+
+template <typename T>
+hipError_t launch_row_stats(const RowArgs<T>& a, int nitems, const T* d, const long long* foff, const double* aw,
+                            double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(row_stats_kernel<T>, dim3(a.nlat, nitems), dim3(256), 0, stream, a, d, foff, aw, out);
+  return hipGetLastError();
+}
+template hipError_t launch_row_stats<float>(const RowArgs<float>&, int, const float*, const long long*,
+                                            const double*, double*, hipStream_t);
+template hipError_t launch_row_stats<double>(const RowArgs<double>&, int, const double*, const long long*,
+                                             const double*, double*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Per-pair gradient combination: out = wa (x1 - (x2 + x3)/2) + coef a.
@@ -1891,7 +2095,7 @@ int row_pairs_per_group(int h, int nlon, int nb, size_t cs) {
   return rpw;
 }
 
-template <typename T, int RPW, int NC>
+template <typename T, int RPW, int NC, int BS = 256>
 static hipError_t launch_rows_nc(const RowArgs<T>& a, int nb, hipStream_t stream) {
   dim3 grid((a.h + RPW - 1) / RPW, nb);
   RowArgs<T> b = a;
@@ -1899,7 +2103,7 @@ static hipError_t launch_rows_nc(const RowArgs<T>& a, int nb, hipStream_t stream
   const size_t base = (size_t)2 * RPW * a.nlon * sizeof(cpx<T>);
   b.tw_lds = base + (size_t)a.nlon * sizeof(cpx<T>) <= 65536 - 1024 ? 1 : 0;
   const size_t lds = base + (b.tw_lds ? (size_t)a.nlon * sizeof(cpx<T>) : 0);
-  SHOT_LAUNCH((row_kernel<T, RPW, NC>), grid, dim3(256), lds, stream, b);
+  SHOT_LAUNCH((row_kernel<T, RPW, NC, BS>), grid, dim3(BS), lds, stream, b);
   return hipGetLastError();
 }
 
@@ -1944,7 +2148,15 @@ static hipError_t launch_sink_nc(const RowArgs<T>& a, int nb, hipStream_t stream
 
 template <typename T>
 hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream) {
-  if (a.ring) return launch_rows_nc<T, 1, 0>(a, nb, stream);  // HEALPix: one ring pair per group
+  // HEALPix: one ring pair per group; from Nside 64 on, rings of 4p pixels with
+  // a large prime p make the generic-radix FFT stage the longest part of the
+  // launch, so those groups get 1024 threads (512 in double precision, whose
+  // registers would not fit 1024)
+  if (a.ring && a.nlon >= 256) {
+    if constexpr (sizeof(T) == 4) return launch_rows_nc<T, 1, 0, 1024>(a, nb, stream);
+    else return launch_rows_nc<T, 1, 0, 512>(a, nb, stream);
+  }
+  if (a.ring) return launch_rows_nc<T, 1, 0, 256>(a, nb, stream);
   if constexpr (sizeof(T) == 4) {
     if ((a.mode == ROW_SINK_U || a.mode == ROW_SINK_V) && a.tw) {
       switch (a.nlon) {
@@ -2024,6 +2236,8 @@ static hipError_t launch_split_ib(const LegArgs<T>& a, hipStream_t stream) {
     case 4: return launch_split<T, IB, 4>(a, stream);
     case 5: return launch_split<T, IB, 5>(a, stream);
     case 6: return launch_split<T, IB, 6>(a, stream);
+    case 7: if constexpr (IB == 1) return launch_split<T, 1, 7>(a, stream); else return hipErrorInvalidValue;
+    case 8: if constexpr (IB == 1) return launch_split<T, 1, 8>(a, stream); else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -2035,7 +2249,7 @@ size_t split_lds_bytes(int maxlen, int h, int ib, int real_bytes) {
 
 template <typename T>
 hipError_t launch_legendre_split(const LegArgs<T>& a, int ib, hipStream_t stream) {
-  if (a.h > 384) return hipErrorInvalidValue;
+  if (a.h > 512 || (ib >= 2 && a.h > 384)) return hipErrorInvalidValue;
   return ib >= 2 ? launch_split_ib<T, 2>(a, stream) : launch_split_ib<T, 1>(a, stream);
 }
 template hipError_t launch_legendre_split<float>(const LegArgs<float>&, int, hipStream_t);
@@ -2100,6 +2314,14 @@ hipError_t launch_reduce(const RowArgs<T>& a, int nb, int nchk_done, double* res
   hipLaunchKernelGGL(reduce_kernel<T>, dim3(nb), dim3(256), 0, stream, a, nchk_done, res, ehist);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_gauge3(const RowArgs<T>& a, int nb, int k, double* gout, hipStream_t stream) {
+  hipLaunchKernelGGL(gauge3_kernel<T>, dim3(nb), dim3(256), 0, stream, a, k, gout);
+  return hipGetLastError();
+}
+template hipError_t launch_gauge3<float>(const RowArgs<float>&, int, int, double*, hipStream_t);
+template hipError_t launch_gauge3<double>(const RowArgs<double>&, int, int, double*, hipStream_t);
 
 template <typename T>
 hipError_t launch_gauge(const RowArgs<T>& a, int nb, int k, double* gout, hipStream_t stream) {

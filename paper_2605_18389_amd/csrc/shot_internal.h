@@ -55,6 +55,10 @@ enum RowMode : int {
   ROW_ADJ_START = 7,  // final-cost adjoints of u_T, v_T -> B-bar_T; spectrum of B-bar_T
   ROW_ADJ_A = 8,      // K^T B-bar -> u-hat-bar -> A-bar, p-bar; spectrum of A-bar
   ROW_ADJ_VB = 9,     // K^T A-bar = v-bar_{k-1} -> B-bar_{k-1}, q-bar; spectrum of B-bar_{k-1}
+  // adjoint sweep of the unbalanced iteration (see kernels.hip): per step k
+  ROW_ADJU_V1 = 10,   // v-bar_k (from the cost at k = T, else K^T A-bar_{k+1}) -> vbar, g-bar partials
+  ROW_ADJU_B = 11,    // g-bar -> v-hat-bar, q-bar, B-bar_k; spectrum of B-bar_k
+  ROW_ADJU_A = 12,    // K^T B-bar -> u-hat-bar, p-bar, A-bar_k; spectrum of A-bar_k
 };
 
 template <typename T>
@@ -94,6 +98,7 @@ struct RowArgs {
   const double* gk;   // [nitems] SINK_U: gauge of iteration k-1 to use instead of the partial sums;
                       // adjoint modes: s of the iteration whose u-hat / v-hat are read
   int kT;             // adjoint: last iteration T (its u-bar term enters ROW_ADJ_A)
+  T* vbar;            // unbalanced adjoint: v-bar_k field (layout of fields)
   // spectrum written by a row-split Legendre launch that cut long orders into
   // parts: cut[m] = (parts, first partial slot); nullptr when nothing was cut
   const int2* cut;
@@ -170,6 +175,15 @@ hipError_t launch_reduce(const RowArgs<T>& a, int nb, int nchk_done, double* res
                          hipStream_t stream);
 template <typename T>
 hipError_t launch_gauge(const RowArgs<T>& a, int nb, int k, double* gout, hipStream_t stream);
+// Per (row, item) float64 (sum a, sum a g, sum a g^2) of g = d / a; items of one
+// grid, item i's field at d + foff[i] (foff device), aw[j] the float64 area
+// weight of row pair j (device).  out: [items][nlat][3].
+template <typename T>
+hipError_t launch_row_stats(const RowArgs<T>& a, int nitems, const T* d, const long long* foff, const double* aw,
+                            double* out, hipStream_t stream);
+// Per item (g_k, S_A, S_B) of iteration k: gout[3 it + {0, 1, 2}].
+template <typename T>
+hipError_t launch_gauge3(const RowArgs<T>& a, int nb, int k, double* gout, hipStream_t stream);
 template <typename T>
 hipError_t launch_combine(const CombineDev* d, int npairs, long long maxn, T* out, hipStream_t stream);
 

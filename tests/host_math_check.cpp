@@ -171,6 +171,25 @@ static int check_factors() {
   return 0;
 }
 
+// Gauss-Lobatto: the 5-point textbook rule, and exactness to degree 2n - 3.
+static int check_lobatto() {
+  std::vector<double> x, w;
+  gauss_lobatto(5, x, w);
+  const double xs[5] = {1.0, std::sqrt(3.0 / 7.0), 0.0, -std::sqrt(3.0 / 7.0), -1.0};
+  const double ws[5] = {0.1, 49.0 / 90.0, 32.0 / 45.0, 49.0 / 90.0, 0.1};
+  for (int j = 0; j < 5; ++j)
+    if (std::fabs(x[j] - xs[j]) > 1e-15 || std::fabs(w[j] - ws[j]) > 1e-14) return fail("lobatto 5-point", j, 0);
+  for (int n : {3, 8, 33, 181}) {
+    gauss_lobatto(n, x, w);
+    for (int k = 0; k <= 2 * n - 3; k += 2) {
+      double s = 0;
+      for (int j = 0; j < n; ++j) s += w[j] * std::pow(x[j], k);
+      if (std::fabs(s - 2.0 / (k + 1)) > 1e-12) return fail("lobatto exactness", n, k);
+    }
+  }
+  return 0;
+}
+
 int main() {
   int rc = 0;
   for (int L : {1, 15, 16, 17, 90, 181, 720})
@@ -183,6 +202,7 @@ int main() {
   rc |= check_checkpoints(150, 75, 64);
   for (int nside : {1, 2, 3, 7, 8, 64, 256}) rc |= check_healpix(nside);
   rc |= check_factors();
+  rc |= check_lobatto();
   if (!rc) std::printf("OK\n");
   return rc;
 }

@@ -59,6 +59,50 @@ def test_unrolled_gradient_matches_oracle_fd(prec, tol, ck):
     assert np.abs(an - fd).max() <= tol * scale, (an, fd)
 
 
+@pytest.mark.parametrize("prec,tol,ck,tau", [("fp64", 1e-7, 0, 1.0), ("fp64", 1e-7, 7, 0.1), ("fp64", 1e-7, 0, 10.0),
+                                              ("fp32", 2e-4, 0, 1.0)])
+def test_unbalanced_gradient_matches_oracle_fd(prec, tol, ck, tau):
+    """Unbalanced pairs (masses 1 and 1.05): the adjoint of Alg. 1's unbalanced
+    branch, gauge included, against central differences of the oracle's
+    fixed-T computation along raw (not mass-preserving) directions."""
+    grid = ("gl", 16, 32, 16)
+    announce(f"unbalanced grad FD {grid} {prec} ck={ck} tau={tau}")
+    g = O.make_grid(*grid)
+    p, q = synth.temperature_pair(23, g.x, g.w, g.nlon, K=4, q_mass=1.05)
+    eps, T = 0.2, 30
+    P = _plan([grid], prec)
+    S, G, info = P.divergence_grad(to_dev(p, P.dtype), to_dev(q, P.dtype), eps, T=T, checkpoint_every=ck,
+                                   tau=tau)
+    assert all(i["status"] == 0 for i in info)
+    Sref = O.divergence(p, q, g, eps, tau=tau, T=T)
+    assert abs(S[0] - Sref) <= (1e-10 if prec == "fp64" else 1e-4) * abs(Sref)
+    G = to_np(G).reshape(p.shape)
+    rng = np.random.default_rng(8)
+    D = np.stack([p * rng.standard_normal(p.shape) for _ in range(4)])
+    fd = O.fd_directional(p, q, D, g, eps, T, h=1e-4, tau=tau)
+    an = np.array([(G * d).sum() for d in D])
+    scale = np.abs(fd).max()
+    assert np.abs(an - fd).max() <= tol * scale, (an, fd)
+
+
+def test_unbalanced_gradient_through_autograd():
+    import torch
+    from paper_2605_18389_amd.autograd import sinkhorn_divergence
+    grid = ("gl", 12, 24, 12)
+    announce("unbalanced autograd")
+    g = O.make_grid(*grid)
+    p, q = synth.temperature_pair(24, g.x, g.w, g.nlon, K=3, q_mass=1.05)
+    P = _plan([grid], "fp64")
+    pt = to_dev(p, P.dtype).requires_grad_(True)
+    S = sinkhorn_divergence(pt, to_dev(q, P.dtype), P, 0.3, T=20, tau=1.0)
+    S.sum().backward()
+    _, G, _ = P.divergence_grad(to_dev(p, P.dtype), to_dev(q, P.dtype), 0.3, T=20, tau=1.0)
+    np.testing.assert_allclose(to_np(pt.grad), to_np(G), rtol=1e-13, atol=0)
+    d = np.random.default_rng(2).standard_normal(p.shape) * p
+    fd = O.fd_directional(p, q, d[None], g, 0.3, 20, h=1e-5, tau=1.0)[0]
+    assert abs((to_np(pt.grad).reshape(p.shape) * d).sum() - fd) <= 1e-6 * abs(fd)
+
+
 def test_unrolled_gradient_non_mass_preserving_direction():
     grid = ("gl", 12, 24, 12)
     announce("grad FD raw direction")
@@ -179,3 +223,48 @@ def test_full_batch_360x720(T):
             assert abs(S32[i] - S64[i]) <= tol * abs(S64[i])
     if T == 30:
         assert graded >= 8
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-12)])
+@pytest.mark.parametrize("grid", [("gl", 32, 64, 32), ("cc", 721, 1440, 720), ("hp", 16, 32)])
+def test_regional_rms_matches_oracle(grid, prec, tol):
+    """The five regions of the attribution on a gradient-like field, per pair;
+    float32 fields are compared through the same float32 values."""
+    announce(f"regional rms {grid} {prec}")
+    from paper_2605_18389_amd.binding import PAPER_REGIONS
+    g = O.HealpixGrid(grid[1], grid[2]) if grid[0] == "hp" else O.make_grid(*grid)
+    P = _plan([grid], prec)
+    rng = np.random.default_rng(12)
+    d = np.stack([rng.standard_normal(g.area.shape) * g.area for _ in range(3)])
+    dd = to_dev(d, P.dtype)
+    got = P.regional_rms(dd)
+    dv = to_np(dd).reshape(d.shape)
+    bands = list(PAPER_REGIONS.values())
+    for i in range(3):
+        ref = O.regional_rms(dv[i], g, bands)
+        for b, name in enumerate(PAPER_REGIONS):
+            assert got[name][i] == pytest.approx(ref[b], rel=tol), (name, i)
+
+
+def test_regional_attribution_of_unbalanced_gradient_on_healpix():
+    """End to end on the climate grid family: unbalanced divergence gradient on
+    HEALPix, then the five regional indices, against the oracle's attribution of
+    the same gradient and the oracle gradient's directional derivatives."""
+    nside, L = 8, 16
+    announce("healpix unbalanced gradient + attribution")
+    g = O.HealpixGrid(nside, L)
+    p, q = synth.temperature_pair_at(synth.pair_seed(6, 3), g.pixel_z, g.pixel_phi, g.area[0], K=5, q_mass=1.05)
+    P = _plan([("hp", nside, L)], "fp64")
+    eps, T, tau = 0.1, 30, 1.0
+    S, G, info = P.divergence_grad(to_dev(p, P.dtype), to_dev(q, P.dtype), eps, T=T, tau=tau)
+    assert all(i["status"] == 0 for i in info)
+    Gn = to_np(G).reshape(-1)
+    rng = np.random.default_rng(13)
+    D = np.stack([p * rng.standard_normal(p.shape) for _ in range(2)])
+    fd = O.fd_directional(p[None], q[None], D[:, None], g, eps, T, h=1e-4, tau=tau)
+    np.testing.assert_allclose(D @ Gn, fd, rtol=1e-7, atol=1e-7 * np.abs(fd).max())
+    from paper_2605_18389_amd.binding import PAPER_REGIONS
+    got = P.regional_rms(G)
+    ref = O.regional_rms(Gn[None], g, list(PAPER_REGIONS.values()))
+    for b, name in enumerate(PAPER_REGIONS):
+        assert got[name][0] == pytest.approx(ref[b], rel=1e-12)

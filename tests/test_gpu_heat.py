@@ -29,7 +29,7 @@ def _plan(grids, precision, legendre="table"):
 
 
 GRIDS = [("gl", 32, 64, 32), ("cc", 33, 64, 32), ("gl", 17, 36, 18), ("cc", 9, 16, 8),
-         ("gl", 180, 360, 180)]
+         ("gl", 180, 360, 180), ("lob", 17, 34, 16), ("lob", 33, 64, 32)]
 
 
 @pytest.mark.parametrize("grid", GRIDS)
