@@ -24,6 +24,9 @@ Everything is float64 NumPy, written step by step from the paper:
                     (App. C.3), divergence (Def. 2.3), envelope gradient (Sec. 4.2.2).
 * ``attribution`` -- centred gradient field and its area-weighted RMS per
                     latitude band (Sec. 4.2.2, regional attribution).
+* ``convolution`` -- heat versus matrix convolution of a measure (appendix on
+                    convolution on S^2): C(eps), the dense geodesic-Gaussian
+                    convolution, the rescaled mean absolute error.
 
 Readings where the paper is silent or inconsistent are listed in the design doc
 (heat time t = eps/4 everywhere, l < L, Alg. 1 taken literally, ...).
@@ -36,6 +39,7 @@ from .sht import analysis, synthesis, heat_apply, heat_multipliers
 from .dense import dense_heat_matrix, dense_heat_apply
 from .sinkhorn import sinkhorn, divergence, envelope_gradient, fd_directional
 from .attribution import regional_rms, latitudes
+from .convolution import geodesic_kernel_integral, matrix_convolution, heat_convolution, rescaled_mae, heat_vs_matrix
 
 __all__ = [
     "Grid", "gauss_legendre", "gauss_lobatto", "clenshaw_curtis", "make_grid", "HealpixGrid", "ring_geometry",
@@ -43,4 +47,5 @@ __all__ = [
     "analysis", "synthesis", "heat_apply", "heat_multipliers",
     "dense_heat_matrix", "dense_heat_apply",
     "sinkhorn", "divergence", "envelope_gradient", "fd_directional", "regional_rms", "latitudes",
+    "geodesic_kernel_integral", "matrix_convolution", "heat_convolution", "rescaled_mae", "heat_vs_matrix",
 ]

@@ -18,6 +18,9 @@ Generators (all draws from numpy's PCG64 ``default_rng(seed)`` in a fixed order)
                        a 1e-6 floor.  Per measure: K centres, K kappa ~ U[5, 50],
                        K amplitudes ~ U[-0.2, 0.2].
 * ``uniform_field`` -- i.i.d. U[0, 1] per point, normalised.
+* ``vmf_at``        -- one von Mises-Fisher density (the convolution study's input):
+                       one centre (3 normals, normalised), fixed kappa, unit mass on
+                       the sphere (not renormalised on the grid).
 
 The ``*_at`` variants take any point set instead of a latitude-longitude grid
 (e.g. HEALPix pixel centres): per point z = cos(colatitude), longitude phi
@@ -154,3 +157,12 @@ def uniform_pair_at(seed, area):
     """Two ``uniform_at`` probability measures (the paper's runtime workload)."""
     rng = np.random.default_rng(seed)
     return uniform_at(rng, area), uniform_at(rng, area)
+
+
+def vmf_at(seed, z, phi, kappa=10.0):
+    """One vMF density with a seeded random mean direction at points (z, phi); returns (f, mu)."""
+    rng = np.random.default_rng(seed)
+    mu = _centres(rng, 1)[0]
+    X = _points_at(z, phi)
+    c = kappa / (2.0 * np.pi * (1.0 - math.exp(-2.0 * kappa)))
+    return c * np.exp(kappa * (X @ mu - 1.0)), mu

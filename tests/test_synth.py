@@ -38,3 +38,18 @@ def test_batch_params():
             assert math.isinf(tau) and qm == 1.0
         else:
             assert tau in (0.1, 1.0, 10.0) and qm == 1.05
+
+
+def test_vmf_at_unit_mass_and_seeded_centre():
+    g = O.make_grid("gl", 96, 192, 96)
+    X = g.points()
+    z, phi = X[..., 2], np.arctan2(X[..., 1], X[..., 0])
+    for kappa in (1.0, 10.0, 50.0):
+        f, mu = synth.vmf_at(3, z, phi, kappa)
+        assert abs((g.area * f).sum() - 1.0) < 1e-12
+        assert abs(np.linalg.norm(mu) - 1.0) < 1e-15
+        # the density peaks at the grid point closest to the centre
+        k = np.argmax(f)
+        assert np.isclose((X.reshape(-1, 3) @ mu).max(), X.reshape(-1, 3)[k] @ mu)
+    f2, mu2 = synth.vmf_at(3, z, phi, 50.0)
+    assert np.array_equal(mu, mu2) and np.array_equal(f, f2)
