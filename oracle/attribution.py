@@ -6,10 +6,15 @@ constant, so it is centred by subtracting its area-weighted mean; the
 area-weighted RMS of the centred field over a latitude band is that band's
 bias index.  Here g = dS_dp / a, dS_dp being the derivative with respect to
 the density array (it carries the point areas a).  A point belongs to the band
-(lat_lo, lat_hi) when its latitude lies strictly between the bounds.
+(lat_lo, lat_hi) when its latitude lies strictly between the bounds; a
+latitude within EDGE degrees of a bound counts as lying on it (equiangular
+rows sit exactly on bounds such as 30 degrees, where the last bit of the
+arcsine would otherwise decide membership).
 """
 
 import numpy as np
+
+EDGE = 1e-9   # degrees
 
 
 def latitudes(grid):
@@ -29,7 +34,7 @@ def regional_rms(dS_dp, grid, bands):
     lat = latitudes(grid)
     out = []
     for lo, hi in bands:
-        m = (lat > lo) & (lat < hi)
+        m = (lat > lo + EDGE) & (lat < hi - EDGE)
         w = a[m]
         out.append(np.sqrt((w * gc[m] ** 2).sum() / w.sum()) if w.size else np.nan)
     return np.array(out)

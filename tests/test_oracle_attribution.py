@@ -31,3 +31,19 @@ def test_invariances(grid):
     np.testing.assert_allclose(O.regional_rms(7.0 * g.area, g, bands), 0.0, atol=1e-12)
     # an empty band
     assert np.isnan(O.regional_rms(f * g.area, g, [(89.99, 89.995)])[0])
+
+
+def test_rows_on_a_bound_are_outside_the_band():
+    # 7 equiangular rows at latitudes 90, 60, 30, 0, -30, -60, -90 (exactly, up to
+    # the arcsine's rounding): (30, 60) holds none of them, (29.9, 60.1) two
+    g = O.make_grid("cc", 7, 12, 6)
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal(g.area.shape)
+    assert np.isnan(O.regional_rms(f * g.area, g, [(30.0, 60.0)])[0])
+    assert np.isnan(O.regional_rms(f * g.area, g, [(-60.0, -30.0)])[0])
+    got = O.regional_rms(f * g.area, g, [(29.9, 60.1)])[0]
+    a = g.area
+    mean = (a * f).sum() / a.sum()
+    rows = [1, 2]
+    want = math.sqrt(sum((a[j] * (f[j] - mean) ** 2).sum() for j in rows) / sum(a[j].sum() for j in rows))
+    assert got == pytest.approx(want, rel=1e-13)
