@@ -15,7 +15,8 @@
  * Grids.  Iso-latitude grids of nlat rows x nlon columns.  Row 0 is the
  *   northernmost row (colatitude closest to 0), column k sits at longitude
  *   2*pi*k/nlon.  The band limit L keeps degrees and orders l, m < L and needs
- *   nlon >= 2L-1.  nlon must factor into 2, 3 and 5 and be at most 2048, and
+ *   nlon >= 2L-1.  nlon must be at most 2048 (any factorisation: prime factors
+ *   above 5 run as direct stages, slower than radices 2 to 5), and
  *   (2*ceil(nlat/2) + L) complex values of the field precision must fit in
  *   60 KiB (SHOT_E_UNSUPPORTED otherwise).  Area weights a_{jk} = w_j * 2*pi/nlon
  *   sum to 4*pi.
@@ -71,8 +72,7 @@ enum { SHOT_LEG_AUTO = 0, SHOT_LEG_TABLE = 1, SHOT_LEG_RECURRENCE = 2 };
  * SHOT_GRID_CLENSHAW_CURTIS (equiangular rows theta_j = j*pi/(nlat-1), poles
  * included) or SHOT_GRID_LOBATTO (rows at the poles and at the zeros of
  * P'_{nlat-1}, Gauss-Lobatto weights, exact to degree 2 nlat - 3) -- App. C.1:
- * a field is [nlat][nlon] row-major, requires nlon >= 2L-1, nlon a product of
- * 2, 3 and 5, nlon <= 2048.
+ * a field is [nlat][nlon] row-major, requires nlon >= 2L-1, nlon <= 2048.
  *
  * SHOT_GRID_HEALPIX (Sec. 3.3, App. C.1; Gorski et al. 2005): nlat = 4 Nside - 1
  * iso-latitude rings, nlon = 4 Nside (the longest ring), Nside <= 512; a field
@@ -195,7 +195,9 @@ shot_status shot_sinkhorn_divergence_grad(shot_plan_t plan, const int32_t* grid_
  * latitude band is returned.  dS_dp: device, the layout of
  * shot_sinkhorn_divergence_grad's output for these pairs.  bands: host,
  * nbands (lat_lo, lat_hi) pairs in degrees; a row (ring) belongs to a band
- * when lat_lo < its latitude < lat_hi (rows on an edge are excluded).
+ * when lat_lo < its latitude < lat_hi (rows on an edge are excluded; a
+ * latitude within 1e-9 degree of a bound counts as on it, so that rounding of
+ * the arcsine cannot move a row across a bound).
  * rms_out: host, npairs * nbands (NaN for a band holding no row).  The
  * per-row sums run on the device in float64, the band combination on the
  * host.  Synchronises `stream`. */

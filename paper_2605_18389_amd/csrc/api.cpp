@@ -231,7 +231,7 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
   g.h = (d.nlat + 1) / 2;
   // table rows padded to the matrix-core K step (32) for fp32/bf16 tables
   g.hpad = P->prec == SHOT_FP64 ? (g.h + 3) / 4 * 4 : (g.h + 31) / 32 * 32;
-  g.fac = g.hp ? std::vector<int>() : fft_radices(d.nlon);
+  g.fac = g.hp ? std::vector<int>() : fft_factors(d.nlon);
   const bool f64 = P->prec == SHOT_FP64;
   // area weights of rows 0..h-1 and twiddles in field precision
   std::vector<double> aw(g.h);
@@ -1518,7 +1518,8 @@ shot_status regional_rms_impl(shot_plan_s* P, const int32_t* gop, int npairs, co
         double B0 = 0, B1 = 0, B2 = 0;
         for (int j = 0; j < nlat; ++j) {
           const double lat = std::asin(std::max(-1.0, std::min(1.0, g.x[j]))) * 180.0 / M_PI;
-          if (lat > bands[2 * b] && lat < bands[2 * b + 1]) {
+          // rows within 1e-9 degree of a bound lie on it (equiangular rows hit bounds exactly)
+          if (lat > bands[2 * b] + 1e-9 && lat < bands[2 * b + 1] - 1e-9) {
             B0 += r[3 * j];
             B1 += r[3 * j + 1];
             B2 += r[3 * j + 2];
@@ -1568,8 +1569,8 @@ shot_status shot_sht_plan(shot_plan_t* out, const shot_grid_desc* grids, int32_t
       if (d.nlon > 2048) return SHOT_E_UNSUPPORTED;
     } else {
       if (d.nlat < 2 || d.L < 1 || d.nlon < 2 * d.L - 1) return SHOT_E_INVALID;
-      if (fft_radices(d.nlon).empty() || d.nlon > 2048) return SHOT_E_UNSUPPORTED;
-      if (fft_radices(d.nlon).size() > 8) return SHOT_E_UNSUPPORTED;
+      // any row length: radices 4, 2, 3, 5 and a direct stage per larger prime
+      if (d.nlon > 2048 || fft_factors(d.nlon).size() > 8) return SHOT_E_UNSUPPORTED;
     }
     // one order's inputs and coefficients must fit the Legendre kernel's LDS
     const size_t cs = precision == SHOT_FP64 ? 16 : 8;

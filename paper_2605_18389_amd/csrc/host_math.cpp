@@ -160,18 +160,6 @@ void healpix_rings(int nside, std::vector<double>& z, std::vector<int>& npix, st
   }
 }
 
-std::vector<int> fft_radices(int n) {
-  std::vector<int> f;
-  for (int r : {4, 2, 3, 5}) {
-    while (n % r == 0) {
-      f.push_back(r);
-      n /= r;
-    }
-  }
-  if (n != 1) f.clear();
-  return f;
-}
-
 namespace {
 
 // One order m: P̄_l^m(x) for l = m..L-1 at a single node, into out[l-m].

@@ -40,10 +40,6 @@ void gauss_lobatto(int n, std::vector<double>& x, std::vector<double>& w);
 // Clenshaw-Curtis rule on theta_j = j pi/(n-1), poles included (App. C.1).
 void clenshaw_curtis(int n, std::vector<double>& x, std::vector<double>& w);
 
-// Radices (4, 2, 3, 5 in that order of extraction) whose product is n, or
-// empty when n has another prime factor.
-std::vector<int> fft_radices(int n);
-
 // Factors of any n >= 1: 4, 2, 3, 5 extracted first, then the remaining
 // primes in increasing order (the device FFT runs those as generic stages).
 std::vector<int> fft_factors(int n);

@@ -28,8 +28,11 @@ def _plan(grids, precision, legendre="table"):
     return Plan(grids, precision=precision, legendre=legendre)
 
 
+# rows of 34 = 2 x 17, 77 = 7 x 11 and 26 = 2 x 13 columns take direct stages
+# for their prime factors above 5
 GRIDS = [("gl", 32, 64, 32), ("cc", 33, 64, 32), ("gl", 17, 36, 18), ("cc", 9, 16, 8),
-         ("gl", 180, 360, 180), ("lob", 17, 34, 16), ("lob", 33, 64, 32)]
+         ("gl", 180, 360, 180), ("lob", 17, 34, 16), ("lob", 33, 64, 32), ("gl", 20, 77, 20),
+         ("cc", 13, 26, 12)]
 
 
 @pytest.mark.parametrize("grid", GRIDS)
