@@ -270,14 +270,105 @@ __device__ __forceinline__ cpx<T>* fft_any(cpx<T>* a, cpx<T>* b, int N, const in
 }
 
 // ---------------------------------------------------------------------------
+// Cross-lane exchanges without LDS round trips: DPP row permutes for lane
+// bits 0-3, permlane swaps (gfx950) for bits 4 and 5.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dpp_f(float v, int ctrl_sel) {
+  int x = __float_as_int(v);
+  int r;
+  switch (ctrl_sel) {
+    case 0: r = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false); break;  // row_mirror (bit 3)
+    case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false); break;  // row_half_mirror (bit 2)
+    case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x4e, 0xf, 0xf, false); break;   // quad_perm [2,3,0,1] (bit 1)
+    default: r = __builtin_amdgcn_update_dpp(0, x, 0xb1, 0xf, 0xf, false); break;  // quad_perm [1,0,3,2] (bit 0)
+  }
+  return __int_as_float(r);
+}
+
+__device__ __forceinline__ double dpp_d(double v, int ctrl_sel) {
+  const unsigned long long u = __double_as_longlong(v);
+  float lo = __int_as_float((int)(u & 0xffffffffull)), hi = __int_as_float((int)(u >> 32));
+  const unsigned long long rl = (unsigned)__float_as_int(dpp_f(lo, ctrl_sel));
+  const unsigned long long rh = (unsigned)__float_as_int(dpp_f(hi, ctrl_sel));
+  return __longlong_as_double((long long)(rl | (rh << 32)));
+}
+
+// new value = X(lane) + X(lane ^ 32) for lanes < 32, Y(lane ^ 32) + Y(lane) above.
+__device__ __forceinline__ float swap_add32(float X, float Y) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(X), __float_as_uint(Y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_add16(float X, float Y) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(X), __float_as_uint(Y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double swap_add32(double X, double Y) {
+  const unsigned long long x = __double_as_longlong(X), y = __double_as_longlong(Y);
+  auto lo = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
+  auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+  const double a = __longlong_as_double((long long)((unsigned long long)lo[0] | ((unsigned long long)hi[0] << 32)));
+  const double b = __longlong_as_double((long long)((unsigned long long)lo[1] | ((unsigned long long)hi[1] << 32)));
+  return a + b;
+}
+__device__ __forceinline__ double swap_add16(double X, double Y) {
+  const unsigned long long x = __double_as_longlong(X), y = __double_as_longlong(Y);
+  auto lo = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)y, false, false);
+  auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+  const double a = __longlong_as_double((long long)((unsigned long long)lo[0] | ((unsigned long long)hi[0] << 32)));
+  const double b = __longlong_as_double((long long)((unsigned long long)lo[1] | ((unsigned long long)hi[1] << 32)));
+  return a + b;
+}
+
+// v of the lane and of its partner across lane bit 4 (permlane16) or bit 5
+// (permlane32), returned as (value of the lower lane, value of the upper lane)
+// so that both partners see the same ordered pair.
+__device__ __forceinline__ void lane_pair16(double v, double& lo, double& hi) {
+  const unsigned long long x = __double_as_longlong(v);
+  auto a = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)x, false, false);
+  auto b = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(x >> 32), false, false);
+  lo = __longlong_as_double((long long)((unsigned long long)a[0] | ((unsigned long long)b[0] << 32)));
+  hi = __longlong_as_double((long long)((unsigned long long)a[1] | ((unsigned long long)b[1] << 32)));
+}
+__device__ __forceinline__ void lane_pair32(double v, double& lo, double& hi) {
+  const unsigned long long x = __double_as_longlong(v);
+  auto a = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
+  auto b = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(x >> 32), false, false);
+  lo = __longlong_as_double((long long)((unsigned long long)a[0] | ((unsigned long long)b[0] << 32)));
+  hi = __longlong_as_double((long long)((unsigned long long)a[1] | ((unsigned long long)b[1] << 32)));
+}
+
+// Wave-wide all-reduction with a commutative op (sum, min, max): at every
+// step a lane and its partner combine the same two values, so all 64 lanes
+// end with the identical, run-to-run deterministic result.
+template <typename Op>
+__device__ __forceinline__ double wave_allreduce(double v, Op op) {
+  v = op(v, dpp_d(v, 3));  // lane ^ 1
+  v = op(v, dpp_d(v, 2));  // lane ^ 2
+  v = op(v, dpp_d(v, 1));  // mirror within 8 lanes
+  v = op(v, dpp_d(v, 0));  // mirror within 16 lanes
+  double lo, hi;
+  lane_pair16(v, lo, hi);
+  v = op(lo, hi);
+  lane_pair32(v, lo, hi);
+  return op(lo, hi);
+}
+struct OpAdd {
+  __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct OpMin {
+  __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+struct OpMax {
+  __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+__device__ __forceinline__ double wave_sum(double v) { return wave_allreduce(v, OpAdd()); }
+__device__ __forceinline__ double wave_min(double v) { return wave_allreduce(v, OpMin()); }
+__device__ __forceinline__ double wave_max(double v) { return wave_allreduce(v, OpMax()); }
+
+// ---------------------------------------------------------------------------
 // Deterministic block reduction: every thread receives the same value (the
 // wave partials are combined in wave order by each thread).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 __device__ double block_sum(double v, double* sh) {
   v = wave_sum(v);
@@ -291,8 +382,7 @@ __device__ double block_sum(double v, double* sh) {
 }
 
 __device__ double block_min(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  v = wave_min(v);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
   __syncthreads();
   if (lane == 0) sh[w] = v;
@@ -303,8 +393,7 @@ __device__ double block_min(double v, double* sh) {
 }
 
 __device__ double block_max(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  v = wave_max(v);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
   __syncthreads();
   if (lane == 0) sh[w] = v;
@@ -920,36 +1009,22 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
       }
     }
   }
-  // (2) partial sums: gauge of the previous iteration, previous half's kernel range
-  {
-    double s0 = 0.0, s1 = 0.0, mn = INFINITY, mx = -INFINITY;
-    if (gsum || kfold) {
-      const double* Rg = A.red + ((size_t)((A.k - 1) & 1) * A.nitems_all + it) * (size_t)A.hs * RED_SLOTS;
-      const double* Rk = A.red + ((size_t)((umode ? A.k - 1 : A.k) & 1) * A.nitems_all + it) * (size_t)A.hs * RED_SLOTS;
-      const int ks = umode ? 4 : 2;
-      for (int q = tid; q < h; q += BS) {
-        if (gsum) {
-          s0 += Rg[(size_t)q * RED_SLOTS + 0];
-          s1 += Rg[(size_t)q * RED_SLOTS + 1];
-        }
-        if (kfold) {
-          mn = fmin(mn, Rk[(size_t)q * RED_SLOTS + ks]);
-          mx = fmax(mx, Rk[(size_t)q * RED_SLOTS + ks + 1]);
-        }
-      }
-      s0 = wave_sum(s0);
-      s1 = wave_sum(s1);
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        mn = fmin(mn, __shfl_xor(mn, o, 64));
-        mx = fmax(mx, __shfl_xor(mx, o, 64));
-      }
+  // (2) partial sums of the previous iteration (gauge) and of the previous
+  // half (kernel range): with at most one row pair per thread they are loaded
+  // here and combined after the gather, so the two load rounds overlap
+  double s0 = 0.0, s1 = 0.0, mn = INFINITY, mx = -INFINITY;
+  const double* Rg = A.red + ((size_t)((A.k - 1) & 1) * A.nitems_all + it) * (size_t)A.hs * RED_SLOTS;
+  const double* Rk = A.red + ((size_t)((umode ? A.k - 1 : A.k) & 1) * A.nitems_all + it) * (size_t)A.hs * RED_SLOTS;
+  const int ks = umode ? 4 : 2;
+  const bool one_pass = h <= BS;
+  if (one_pass && tid < h) {
+    if (gsum) {
+      s0 = Rg[(size_t)tid * RED_SLOTS + 0];
+      s1 = Rg[(size_t)tid * RED_SLOTS + 1];
     }
-    if (lane == 0) {
-      shw[wave][0] = s0;
-      shw[wave][1] = s1;
-      shw[wave][2] = mn;
-      shw[wave][3] = mx;
+    if (kfold) {
+      mn = Rk[(size_t)tid * RED_SLOTS + ks];
+      mx = Rk[(size_t)tid * RED_SLOTS + ks + 1];
     }
   }
   // (3) twiddles, spectral gather into the Hermitian spectra of the pairs
@@ -968,6 +1043,31 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
     const cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : csub(ge, go);
     buf0[pr * N + m] = {a.x - b.y, a.y + b.x};
     if (m > 0) buf0[pr * N + N - m] = {a.x + b.y, -a.y + b.x};
+  }
+  if (!one_pass)
+    for (int q = tid; q < h; q += BS) {
+      if (gsum) {
+        s0 += Rg[(size_t)q * RED_SLOTS + 0];
+        s1 += Rg[(size_t)q * RED_SLOTS + 1];
+      }
+      if (kfold) {
+        mn = fmin(mn, Rk[(size_t)q * RED_SLOTS + ks]);
+        mx = fmax(mx, Rk[(size_t)q * RED_SLOTS + ks + 1]);
+      }
+    }
+  if (gsum) {
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+  }
+  if (kfold) {
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+  }
+  if (lane == 0) {
+    shw[wave][0] = s0;
+    shw[wave][1] = s1;
+    shw[wave][2] = mn;
+    shw[wave][3] = mx;
   }
   __syncthreads();
   cpx<T>* X = fft_any<T, NC, RPW>(buf0, buf1, N, A.fac, A.nfac, twl, (T)1);
@@ -1026,13 +1126,10 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
     }
     X[pr * N + c] = {nv[0], nv[1]};
   }
-  acc = wave_sum(acc);
-  acc2 = wave_sum(acc2);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    kmin = fmin(kmin, __shfl_xor(kmin, o, 64));
-    kmax = fmax(kmax, __shfl_xor(kmax, o, 64));
-  }
+  if (umode || !I.balanced) acc = wave_sum(acc);  // balanced V halves keep no sum
+  if (chk) acc2 = wave_sum(acc2);
+  kmin = wave_min(kmin);
+  kmax = wave_max(kmax);
   if (lane == 0) {
     shr[wave][0] = acc;
     shr[wave][1] = acc2;
@@ -1223,52 +1320,6 @@ __global__ void __launch_bounds__(256) legendre_table_kernel(LegArgs<T> A) {
 // inputs are staged in LDS, zero-padded to whole blocks so the row loops need
 // no bounds tests.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float dpp_f(float v, int ctrl_sel) {
-  int x = __float_as_int(v);
-  int r;
-  switch (ctrl_sel) {
-    case 0: r = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false); break;  // row_mirror (bit 3)
-    case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false); break;  // row_half_mirror (bit 2)
-    case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x4e, 0xf, 0xf, false); break;   // quad_perm [2,3,0,1] (bit 1)
-    default: r = __builtin_amdgcn_update_dpp(0, x, 0xb1, 0xf, 0xf, false); break;  // quad_perm [1,0,3,2] (bit 0)
-  }
-  return __int_as_float(r);
-}
-
-__device__ __forceinline__ double dpp_d(double v, int ctrl_sel) {
-  const unsigned long long u = __double_as_longlong(v);
-  float lo = __int_as_float((int)(u & 0xffffffffull)), hi = __int_as_float((int)(u >> 32));
-  const unsigned long long rl = (unsigned)__float_as_int(dpp_f(lo, ctrl_sel));
-  const unsigned long long rh = (unsigned)__float_as_int(dpp_f(hi, ctrl_sel));
-  return __longlong_as_double((long long)(rl | (rh << 32)));
-}
-
-// new value = X(lane) + X(lane ^ 32) for lanes < 32, Y(lane ^ 32) + Y(lane) above.
-__device__ __forceinline__ float swap_add32(float X, float Y) {
-  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(X), __float_as_uint(Y), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-__device__ __forceinline__ float swap_add16(float X, float Y) {
-  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(X), __float_as_uint(Y), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-__device__ __forceinline__ double swap_add32(double X, double Y) {
-  const unsigned long long x = __double_as_longlong(X), y = __double_as_longlong(Y);
-  auto lo = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
-  auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
-  const double a = __longlong_as_double((long long)((unsigned long long)lo[0] | ((unsigned long long)hi[0] << 32)));
-  const double b = __longlong_as_double((long long)((unsigned long long)lo[1] | ((unsigned long long)hi[1] << 32)));
-  return a + b;
-}
-__device__ __forceinline__ double swap_add16(double X, double Y) {
-  const unsigned long long x = __double_as_longlong(X), y = __double_as_longlong(Y);
-  auto lo = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)y, false, false);
-  auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
-  const double a = __longlong_as_double((long long)((unsigned long long)lo[0] | ((unsigned long long)hi[0] << 32)));
-  const double b = __longlong_as_double((long long)((unsigned long long)lo[1] | ((unsigned long long)hi[1] << 32)));
-  return a + b;
-}
-
 template <typename R>
 __device__ __forceinline__ R dpp_any(R v, int sel) {
   if constexpr (sizeof(R) == 4) return dpp_f(v, sel);
