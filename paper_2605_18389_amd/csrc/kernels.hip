@@ -1001,11 +1001,11 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
     if (pr < np) {
       const int jp = jp0 + pr, j2 = nlat - 1 - jp;
       const long long r1 = I.foff + (long long)jp * N + c, r2 = I.foff + (long long)j2 * N + c;
-      fv[e][0] = F[r1];
-      if (jp != j2) fv[e][1] = F[r2];
+      fv[e][0] = __builtin_nontemporal_load(F + r1);
+      if (jp != j2) fv[e][1] = __builtin_nontemporal_load(F + r2);
       if (chk) {
-        uv[e][0] = uo[r1 - I.foff];
-        if (jp != j2) uv[e][1] = uo[r2 - I.foff];
+        uv[e][0] = __builtin_nontemporal_load(uo + (r1 - I.foff));
+        if (jp != j2) uv[e][1] = __builtin_nontemporal_load(uo + (r2 - I.foff));
       }
     }
   }
@@ -1122,7 +1122,7 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
       }
       nv[rr] = x;
       const int jr = rr ? nlat - 1 - jp : jp;
-      outf[(long long)jr * N + c] = x;
+      __builtin_nontemporal_store(x, outf + (long long)jr * N + c);
     }
     X[pr * N + c] = {nv[0], nv[1]};
   }
@@ -1582,6 +1582,17 @@ __global__ void __launch_bounds__(256) legendre_recur_kernel(LegArgs<T> A) {
 // part order, which keeps the result independent of timing.
 // ---------------------------------------------------------------------------
 
+// Wave issue priority from the blocks of rows a wave still has to run (both
+// passes): the three waves sharing a SIMD come from different orders, and
+// running the one with the most work left first makes them finish together
+// instead of leaving one long wave alone on the SIMD at the end.
+__device__ __forceinline__ void prio_by_blocks(int left) {
+  if (left >= 18) __builtin_amdgcn_s_setprio(3);
+  else if (left >= 10) __builtin_amdgcn_s_setprio(2);
+  else if (left >= 4) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
 // Three waves per SIMD where the registers allow it without spilling: then
 // a launch of up to 3 x 256 workgroups is resident at once, and the host's
 // dispatch order balances the rows that meet on one compute unit.
@@ -1600,7 +1611,8 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
   const int npl = (len + 15) / 16 * 16 + 16;  // one extra block: the look-ahead coefficient
   const int ib0 = blockIdx.y * IB;
   const int nbi = min(IB, A.nb - ib0);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: row range in scalars
   const int maxpl = (A.maxlen + 15) / 16 * 16 + 16;
   double* cf = reinterpret_cast<double*>(smem_raw);                   // [maxpl], local row index
   double* gm = cf + maxpl;
@@ -1661,7 +1673,10 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
       R1[c] = ck.x;
       R2[c] = ck.y;
     }
+    const int nblk = (r_hi - r_lo + RB - 1) / RB;  // this wave's blocks in each of the two passes
+    int left = 2 * nblk;
     for (int r0 = r_lo; r0 < r_hi; r0 += RB) {
+      prio_by_blocks(left--);
       double acc[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] = 0.0;
@@ -1723,7 +1738,9 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
 #pragma unroll
     for (int i = 0; i < IB; ++i) { gE[c][i] = make_double2(0.0, 0.0); gO[c][i] = make_double2(0.0, 0.0); }
   }
+  int left = (r_hi - r_lo + 15) / 16;
   for (int r0 = r_lo; r0 < r_hi; r0 += 16) {
+    prio_by_blocks(left--);
     const int q0 = r0 - P.r_lo;
 #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
@@ -1749,6 +1766,7 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
       }
     }
   }
+  __builtin_amdgcn_s_setprio(0);
   // combine the four waves' partial sums (fixed order)
 #pragma unroll
   for (int c = 0; c < C; ++c) {
