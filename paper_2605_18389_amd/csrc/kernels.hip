@@ -990,59 +990,91 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
   if (tid < RPW) awl[tid] = (tid < np) ? A.aw[jp0 + tid] : (T)0;
   if (tid == 0) sh_bad = 0;
 
-  // (1) field loads for the pointwise step
+  // Every global load of the group is issued before anything waits on one:
+  // unconditional loads at in-bounds addresses into registers (entries the
+  // group does not own are loaded from a valid row and never used), then the
+  // LDS writes.  A load under a branch makes the join wait for it, which
+  // chained the loads into one memory round trip each.
+  // (1) field values for the pointwise step (pairs beyond np and the
+  // equator's second row are skipped there)
   T fv[PER][2], uv[PER][2];
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const int idx = tid + e * BS;
-    const int pr = idx / N, c = idx - pr * N;
-    fv[e][0] = fv[e][1] = (T)1;
+    const int pr = min(idx / N, np - 1), c = idx % N;
+    const int jp = jp0 + pr, j2 = nlat - 1 - jp;
+    const long long r1 = I.foff + (long long)jp * N + c, r2 = I.foff + (long long)j2 * N + c;
+    fv[e][0] = __builtin_nontemporal_load(F + r1);
+    fv[e][1] = __builtin_nontemporal_load(F + r2);
     uv[e][0] = uv[e][1] = (T)0;
-    if (pr < np) {
-      const int jp = jp0 + pr, j2 = nlat - 1 - jp;
-      const long long r1 = I.foff + (long long)jp * N + c, r2 = I.foff + (long long)j2 * N + c;
-      fv[e][0] = __builtin_nontemporal_load(F + r1);
-      if (jp != j2) fv[e][1] = __builtin_nontemporal_load(F + r2);
-      if (chk) {
-        uv[e][0] = __builtin_nontemporal_load(uo + (r1 - I.foff));
-        if (jp != j2) uv[e][1] = __builtin_nontemporal_load(uo + (r2 - I.foff));
-      }
+    if (chk) {
+      uv[e][0] = __builtin_nontemporal_load(uo + (r1 - I.foff));
+      uv[e][1] = __builtin_nontemporal_load(uo + (r2 - I.foff));
     }
   }
   // (2) partial sums of the previous iteration (gauge) and of the previous
-  // half (kernel range): with at most one row pair per thread they are loaded
-  // here and combined after the gather, so the two load rounds overlap
+  // half (kernel range), one row pair per thread when h <= BS
   double s0 = 0.0, s1 = 0.0, mn = INFINITY, mx = -INFINITY;
   const double* Rg = A.red + ((size_t)((A.k - 1) & 1) * A.nitems_all + it) * (size_t)A.hs * RED_SLOTS;
   const double* Rk = A.red + ((size_t)((umode ? A.k - 1 : A.k) & 1) * A.nitems_all + it) * (size_t)A.hs * RED_SLOTS;
   const int ks = umode ? 4 : 2;
   const bool one_pass = h <= BS;
-  if (one_pass && tid < h) {
-    if (gsum) {
-      s0 = Rg[(size_t)tid * RED_SLOTS + 0];
-      s1 = Rg[(size_t)tid * RED_SLOTS + 1];
-    }
-    if (kfold) {
-      mn = Rk[(size_t)tid * RED_SLOTS + ks];
-      mx = Rk[(size_t)tid * RED_SLOTS + ks + 1];
+  const int qp = min(tid, h - 1);
+  if (one_pass && gsum) {
+    s0 = Rg[(size_t)qp * RED_SLOTS + 0];
+    s1 = Rg[(size_t)qp * RED_SLOTS + 1];
+  }
+  if (one_pass && kfold) {
+    mn = Rk[(size_t)qp * RED_SLOTS + ks];
+    mx = Rk[(size_t)qp * RED_SLOTS + ks + 1];
+  }
+  // (3) twiddles and the pairs' spectral entries (L <= (N + 1) / 2 orders)
+  constexpr int TI = (N + BS - 1) / BS;
+  constexpr int GI = (RPW * ((N + 1) / 2) + BS - 1) / BS;
+  cpx<T> twv[TI], ge[GI], go[GI];
+#pragma unroll
+  for (int i = 0; i < TI; ++i) twv[i] = A.tw[min(tid + i * BS, N - 1)];
+  if (!A.cut) {
+#pragma unroll
+    for (int gi = 0; gi < GI; ++gi) {
+      const int idx = tid + gi * BS;
+      const int m = idx / RPW, pr = idx - m * RPW;
+      const bool ok = m < L && pr < np;
+      const cpx<T>* sp = spec + ((size_t)(ok ? m : 0) * h + jp0 + (ok ? pr : 0)) * 2;
+      ge[gi] = sp[0];
+      go[gi] = sp[1];
     }
   }
-  // (3) twiddles, spectral gather into the Hermitian spectra of the pairs
-  for (int i = tid; i < N; i += BS) twl[i] = A.tw[i];
   for (int idx = tid; idx < RPW * (N - 2 * L + 1); idx += BS) {
     const int pr = idx / (N - 2 * L + 1), c = L + idx % (N - 2 * L + 1);
     buf0[pr * N + c] = {(T)0, (T)0};
   }
-  for (int idx = tid; idx < RPW * L; idx += BS) {
-    const int m = idx / RPW, pr = idx - m * RPW;
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+    if (tid + i * BS < N) twl[tid + i * BS] = twv[i];
+  // Hermitian spectrum of the pair: Z[m] = G_j[m] + i G_j'[m], Z[N-m] its mirror
+  auto put = [&](int m, int pr, cpx<T> e, cpx<T> o) {
     const int jp = jp0 + pr;
-    cpx<T> ge = {(T)0, (T)0}, go = {(T)0, (T)0};
-    if (pr < np) load_spec_pair(A, spec, it, m, jp, ge, go);
     const bool eq = (jp == nlat - 1 - jp);
-    const cpx<T> a = cadd(ge, go);
-    const cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : csub(ge, go);
+    const cpx<T> a = cadd(e, o);
+    const cpx<T> b = eq ? cpx<T>{(T)0, (T)0} : csub(e, o);
     buf0[pr * N + m] = {a.x - b.y, a.y + b.x};
     if (m > 0) buf0[pr * N + N - m] = {a.x + b.y, -a.y + b.x};
+  };
+  if (!A.cut) {
+#pragma unroll
+    for (int gi = 0; gi < GI; ++gi) {
+      const int idx = tid + gi * BS;
+      const int m = idx / RPW, pr = idx - m * RPW;
+      if (m < L) put(m, pr, pr < np ? ge[gi] : cpx<T>{(T)0, (T)0}, pr < np ? go[gi] : cpx<T>{(T)0, (T)0});
+    }
+  } else {
+    for (int idx = tid; idx < RPW * L; idx += BS) {
+      const int m = idx / RPW, pr = idx - m * RPW;
+      cpx<T> e = {(T)0, (T)0}, o = {(T)0, (T)0};
+      if (pr < np) load_spec_pair(A, spec, it, m, jp0 + pr, e, o);
+      put(m, pr, e, o);
+    }
   }
   if (!one_pass)
     for (int q = tid; q < h; q += BS) {
@@ -1055,6 +1087,11 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
         mx = fmax(mx, Rk[(size_t)q * RED_SLOTS + ks + 1]);
       }
     }
+  else if (tid >= h) {
+    s0 = s1 = 0.0;
+    mn = INFINITY;
+    mx = -INFINITY;
+  }
   if (gsum) {
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
@@ -1638,9 +1675,13 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
     }
   double xj[C];
   const double2* ckp = reinterpret_cast<const double2*>(A.rck) + ((size_t)part * 4 + wave) * h;
+  // the first wave of a part that starts an order resumes from the seed
+  // (P̄_m^m, 0) itself: half the bytes of its checkpoint
+  const bool from_seed = wave == 0 && P.r_lo == 0;
   auto checkpoint = [&](int c) {
     const int j = lane + 64 * c;
-    return j < h ? ckp[j] : make_double2(0.0, 0.0);
+    if (j >= h) return make_double2(0.0, 0.0);
+    return from_seed ? make_double2(A.rseed[(size_t)m * h + j], 0.0) : ckp[j];
   };
 #pragma unroll
   for (int c = 0; c < C; ++c) {
