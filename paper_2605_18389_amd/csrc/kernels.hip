@@ -381,6 +381,32 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// Sums of r[0] and r[3], minimum of r[1], maximum of r[2] over the block,
+// combined in wave order (as block_sum) with one pair of barriers; sh holds
+// 4 doubles per wave.
+__device__ void block_reduce4(double* r, double* sh) {
+  r[0] = wave_sum(r[0]);
+  r[1] = wave_min(r[1]);
+  r[2] = wave_max(r[2]);
+  r[3] = wave_sum(r[3]);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0)
+    for (int i = 0; i < 4; ++i) sh[4 * w + i] = r[i];
+  __syncthreads();
+  double a = 0.0, b = INFINITY, c = -INFINITY, d = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    a += sh[4 * i];
+    b = fmin(b, sh[4 * i + 1]);
+    c = fmax(c, sh[4 * i + 2]);
+    d += sh[4 * i + 3];
+  }
+  r[0] = a;
+  r[1] = b;
+  r[2] = c;
+  r[3] = d;
+}
+
 __device__ double block_min(double v, double* sh) {
   v = wave_min(v);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
@@ -526,6 +552,14 @@ __device__ void kratio_fold(const RowArgs<T>& A, int it, int k, int slot, double
 // partial sums are written at the group's first pair (the other slots of the
 // group get the neutral element) so all consumers still reduce over j < h.
 // ---------------------------------------------------------------------------
+// a[e][r] for e, r in {0, 1} by selects (a run-time index would put the
+// array in scratch memory)
+template <typename T>
+__device__ __forceinline__ T pick2(const T (&a)[2][2], int e, int r) {
+  const T x = r ? a[0][1] : a[0][0], y = r ? a[1][1] : a[1][0];
+  return e ? y : x;
+}
+
 template <typename T, int RPW, int NC, int BS = 256>
 __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -610,6 +644,32 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
   const bool has_inverse = (mode == ROW_INV || mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK ||
                             mode == ROW_ADJ_A || mode == ROW_ADJ_VB || mode == ROW_ADJU_A ||
                             (mode == ROW_ADJU_V1 && A.k < A.kT));
+  // Sinkhorn halves: the marginal (and, on check iterations, the previous u)
+  // at this thread's columns are loaded now, at in-bounds addresses, so that
+  // their latency hides behind the inverse FFT (up to PF columns per thread)
+  constexpr int PF = 2;
+  const bool sink = (mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK);
+  const bool pre = sink && np * N <= PF * bs;
+  const bool chk_u = (mode == ROW_SINK_U || mode == ROW_CHECK) && A.chk_slot >= 0;
+  T pfv[PF][2], pfu[PF][2];
+  if (pre) {
+    const T* Fm = mode == ROW_SINK_V ? Q : P;
+    const T* uo = ubuf_of(A, A.k - 1);
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+      const int idx = min(tid + e * bs, np * N - 1);
+      ROW_PAIR_SETUP(idx)
+      (void)eq;
+      (void)aj;
+      pfv[e][0] = Fm[r1 + c];
+      pfv[e][1] = Fm[r2 + c];
+      pfu[e][0] = pfu[e][1] = (T)0;
+      if (chk_u) {
+        pfu[e][0] = uo[r1 + c];
+        pfu[e][1] = uo[r2 + c];
+      }
+    }
+  }
   if (has_inverse && RG) {
     // HEALPix ring pair: row r's field is sum_{|m| < L} G_m e^{i m (phi0 + 2 pi k/N)}
     // with G_{-m} = conj(G_m); with P_m = G_m e^{i m phi0}, order m lands in bin
@@ -698,7 +758,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
     const T* uo = ubuf_of(A, A.k - 1) + I.foff;
     T* un = ubuf_of(A, A.k) + I.foff;
     const bool chk = (A.chk_slot >= 0);
-    for (int idx = tid; idx < np * N; idx += bs) {
+    for (int idx = tid, e = 0; idx < np * N; idx += bs, ++e) {
       ROW_PAIR_SETUP(idx)
       const cpx<T> z = X[pr * N + c];
       T nv[2];
@@ -706,9 +766,9 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
         const long long fidx = (rr ? r2 : r1) + c;
         const long long fi = fidx - I.foff;
         const T kraw = rr ? z.y : z.x;
-        const T pv = P[fidx];
+        const T pv = pre ? pick2(pfv, e, rr) : P[fidx];
         if (chk) {
-          const double r = (double)uo[fi] * (double)kraw - (double)pv;
+          const double r = (double)(pre ? pick2(pfu, e, rr) : uo[fi]) * (double)kraw - (double)pv;
           acc2 += r * r;
         }
         if (mode == ROW_CHECK) { nv[rr] = (T)0; continue; }
@@ -726,7 +786,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
   } else if (mode == ROW_SINK_V) {
     // v_hat_k = f(q / K u_hat_k): Alg. 1 updates v from u before the gauge step.
     T* vn = vbuf_of(A, A.k) + I.foff;
-    for (int idx = tid; idx < np * N; idx += bs) {
+    for (int idx = tid, e = 0; idx < np * N; idx += bs, ++e) {
       ROW_PAIR_SETUP(idx)
       const cpx<T> z = X[pr * N + c];
       T nv[2];
@@ -735,7 +795,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
         const T kraw = rr ? z.y : z.x;
         bad |= bad_kernel_value(kraw);
         track_minmax(kmin, kmax, kraw);
-        const T qv = Q[fidx];
+        const T qv = pre ? pick2(pfv, e, rr) : Q[fidx];
         T v = qv / kraw;
         if (!I.balanced) {
           v = pow(v, (T)I.lam);
@@ -885,18 +945,19 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
     if (tid < np) A.adjp[(size_t)it * A.hs + jp0 + tid] = tid == 0 ? acc0 : 0.0;
     if (mode == ROW_ADJU_V1) return;  // v-bar is consumed pointwise by the next launch
   } else if (mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK) {
-    if (A.chk_slot >= 0) {
-      acc2 = block_sum(acc2, sh);
-      if (tid < np) A.rhist[((size_t)it * A.nslot + A.chk_slot) * A.hs + jp0 + tid] = tid == 0 ? acc2 : 0.0;
-    }
+    // residual, kernel range and the half's sum in one block reduction
+    __shared__ double sh4[4 * 16];
+    double r4[4] = {acc2, kmin, kmax, mode == ROW_SINK_U ? acc0 : acc1};
+    block_reduce4(r4, sh4);
+    if (A.chk_slot >= 0 && tid < np)
+      A.rhist[((size_t)it * A.nslot + A.chk_slot) * A.hs + jp0 + tid] = tid == 0 ? r4[0] : 0.0;
     if (mode != ROW_CHECK) {
-      const double kmn = block_min(kmin, sh), kmx = block_max(kmax, sh);
+      const double kmn = r4[1], kmx = r4[2], s = r4[3];
       // fold the previous half-iteration's kernel ratio into the item's running minimum
       if (A.kr && blockIdx.x == 0) {
         if (mode == ROW_SINK_V) kratio_fold(A, it, A.k, 2, sh);
         else if (A.k > 1) kratio_fold(A, it, A.k - 1, 4, sh);
       }
-      const double s = block_sum(mode == ROW_SINK_U ? acc0 : acc1, sh);
       if (tid < np) {
         double* rp = A.red + (((size_t)(A.k & 1) * A.nitems_all + it) * A.hs + jp0 + tid) * RED_SLOTS;
         rp[mode == ROW_SINK_U ? 0 : 1] = tid == 0 ? s : 0.0;
@@ -2258,11 +2319,11 @@ static hipError_t launch_sink_nc(const RowArgs<T>& a, int nb, hipStream_t stream
 
 template <typename T>
 hipError_t launch_rows(const RowArgs<T>& a, int nb, hipStream_t stream) {
-  // HEALPix: one ring pair per group; from Nside 64 on, rings of 4p pixels with
+  // HEALPix: one ring pair per group; above Nside 64, rings of 4p pixels with
   // a large prime p make the generic-radix FFT stage the longest part of the
   // launch, so those groups get 1024 threads (512 in double precision, whose
   // registers would not fit 1024)
-  if (a.ring && a.nlon >= 256) {
+  if (a.ring && a.nlon > 256) {
     if constexpr (sizeof(T) == 4) return launch_rows_nc<T, 1, 0, 1024>(a, nb, stream);
     else return launch_rows_nc<T, 1, 0, 512>(a, nb, stream);
   }
