@@ -51,6 +51,27 @@ __device__ __forceinline__ cpx<T> cmul_si(cpx<T> a, T s) { return {-s * a.y, s *
 // +1 inverse (unnormalised).  All threads of the block must call it.  Returns
 // the buffer that holds the result (natural order).
 // ---------------------------------------------------------------------------
+// cos and sin of 2 pi e / R, e = 0 .. R-1: the internal twiddles of the
+// register-level composite radices
+template <int R>
+struct UnitRoots;
+template <>
+struct UnitRoots<8> {
+  static constexpr double c[8] = {1.0, 0.70710678118654752440, 0.0, -0.70710678118654752440,
+                                  -1.0, -0.70710678118654752440, 0.0, 0.70710678118654752440};
+  static constexpr double s[8] = {0.0, 0.70710678118654752440, 1.0, 0.70710678118654752440,
+                                  0.0, -0.70710678118654752440, -1.0, -0.70710678118654752440};
+};
+template <>
+struct UnitRoots<9> {
+  static constexpr double c[9] = {1.0, 0.76604444311897803520, 0.17364817766693034885, -0.5,
+                                  -0.93969262078590838405, -0.93969262078590838405, -0.5,
+                                  0.17364817766693034885, 0.76604444311897803520};
+  static constexpr double s[9] = {0.0, 0.64278760968653932632, 0.98480775301220805937, 0.86602540378443864676,
+                                  0.34202014332566873304, -0.34202014332566873304, -0.86602540378443864676,
+                                  -0.98480775301220805937, -0.64278760968653932632};
+};
+
 template <typename T, int R>
 __device__ __forceinline__ void butterfly(cpx<T>* v, T s) {
   if constexpr (R == 2) {
@@ -87,6 +108,33 @@ __device__ __forceinline__ void butterfly(cpx<T>* v, T s) {
     v[4] = csub(b1, r1);
     v[2] = cadd(b2, r2);
     v[3] = csub(b2, r2);
+  } else if constexpr (R == 8 || R == 9) {
+    // R = R1 R2 in registers: with r = R2 r1 + r2 and q = q1 + R1 q2,
+    // X[q] = sum_r2 w_R2^(r2 q2) w_R^(r2 q1) sum_r1 w_R1^(r1 q1) v[R2 r1 + r2]
+    constexpr int R1 = R == 9 ? 3 : 4, R2 = R / R1;
+    cpx<T> y[R2][R1];
+#pragma unroll
+    for (int r2 = 0; r2 < R2; ++r2) {
+#pragma unroll
+      for (int r1 = 0; r1 < R1; ++r1) y[r2][r1] = v[R2 * r1 + r2];
+      butterfly<T, R1>(y[r2], s);
+    }
+#pragma unroll
+    for (int r2 = 1; r2 < R2; ++r2)
+#pragma unroll
+      for (int q1 = 1; q1 < R1; ++q1) {
+        const int e = r2 * q1;  // w_R^e = cos(2 pi e / R) + i s sin(2 pi e / R)
+        y[r2][q1] = cmul(y[r2][q1], cpx<T>{(T)UnitRoots<R>::c[e], s * (T)UnitRoots<R>::s[e]});
+      }
+#pragma unroll
+    for (int q1 = 0; q1 < R1; ++q1) {
+      cpx<T> z[R2];
+#pragma unroll
+      for (int r2 = 0; r2 < R2; ++r2) z[r2] = y[r2][q1];
+      butterfly<T, R2>(z, s);
+#pragma unroll
+      for (int q2 = 0; q2 < R2; ++q2) v[q1 + R1 * q2] = z[q2];
+    }
   }
 }
 
@@ -208,6 +256,29 @@ __host__ __device__ constexpr FacList factorize(int N) {
     }
   return f;
 }
+// The compile-time stages fuse a radix 4 with the radix 2 and pairs of
+// radix 3 into register-level radix-8 and radix-9 stages: fewer LDS passes
+// and barriers, and every stage of a 1440-point row fits one pass of 512
+// threads (4, 8, 9, 5 instead of 4, 4, 2, 3, 3, 5; three heavier stages
+// 16, 10, 9 leave too few threads busy and measured slower).
+__host__ __device__ constexpr FacList fuse_factors(FacList f) {
+  FacList g{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  int n4 = 0, n2 = 0, n3 = 0, n5 = 0;
+  for (int i = 0; i < f.n; ++i) {
+    if (f.r[i] == 4) ++n4;
+    else if (f.r[i] == 2) ++n2;
+    else if (f.r[i] == 3) ++n3;
+    else ++n5;
+  }
+  const int n8 = (n4 > 0 && n2 > 0) ? 1 : 0;
+  for (int i = 0; i < n4 - n8; ++i) g.r[g.n++] = 4;
+  for (int i = 0; i < n8; ++i) g.r[g.n++] = 8;
+  for (int i = 0; i < n2 - n8; ++i) g.r[g.n++] = 2;
+  for (int i = 0; i < n3 / 2; ++i) g.r[g.n++] = 9;
+  for (int i = 0; i < n3 % 2; ++i) g.r[g.n++] = 3;
+  for (int i = 0; i < n5; ++i) g.r[g.n++] = 5;
+  return g;
+}
 __host__ __device__ constexpr int fac_prefix(FacList f, int s) {
   int p = 1;
   for (int i = 0; i < s; ++i) p *= f.r[i];
@@ -242,7 +313,7 @@ __device__ __forceinline__ void stockham_stage_c(const cpx<T>* __restrict__ src,
 
 template <typename T, int N, int NB, int S>
 __device__ __forceinline__ void fft_stages_c(cpx<T>*& src, cpx<T>*& dst, const cpx<T>* tw, T sign) {
-  constexpr FacList F = factorize(N);
+  constexpr FacList F = fuse_factors(factorize(N));
   if constexpr (S < F.n) {
     constexpr int R = F.r[S];
     constexpr int Ns = fac_prefix(F, S);
