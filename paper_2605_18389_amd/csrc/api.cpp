@@ -16,6 +16,7 @@
 #include <new>
 #include <numeric>
 #include <thread>
+#include <map>
 #include <vector>
 
 #include "../../include/shot.h"
@@ -62,6 +63,8 @@ struct GridRec {
   RingDev* d_ring = nullptr;
   void* d_ring_tw = nullptr;
   void* d_ring_ph = nullptr;
+  void* d_ring_blu = nullptr;        // Bluestein chirps and filter spectra of long-prime rings
+  int ring_nbuf = 0;                 // LDS length of a ring FFT buffer
   int tune_ib = 0;   // Legendre items per workgroup (0 = automatic)
   int tune_jpt = 0;  // recurrence chains per thread (0 = automatic); table grids: MFMA column
                      // tiles (1, 2, 4), 0 = automatic, -1 = VALU kernel only
@@ -200,9 +203,9 @@ uint16_t to_bf16(double v) {
 void free_grid(GridRec& g) {
   for (void* p : {g.d_tab, g.d_tabT, (void*)g.d_toffT, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam,
                   (void*)g.d_rseed, (void*)g.sw.d_parts, (void*)g.sw.d_ck, (void*)g.ss.d_parts,
-                  (void*)g.ss.d_ck, (void*)g.sw.d_order, (void*)g.ss.d_order, (void*)g.d_ring, g.d_ring_tw, g.d_ring_ph, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
+                  (void*)g.ss.d_ck, (void*)g.sw.d_order, (void*)g.ss.d_order, (void*)g.d_ring, g.d_ring_tw, g.d_ring_ph, g.d_ring_blu, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
     if (p) (void)hipFree(p);
-  g.d_tab = g.d_tabT = g.d_aw = g.d_tw = g.d_pbuf = g.d_ring_tw = g.d_ring_ph = nullptr;
+  g.d_tab = g.d_tabT = g.d_aw = g.d_tw = g.d_pbuf = g.d_ring_tw = g.d_ring_ph = g.d_ring_blu = nullptr;
   g.d_ring = nullptr;
   g.d_toffT = nullptr;
   g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = nullptr;
@@ -242,7 +245,9 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
     // ring pairs: geometry, twiddles per distinct length (4k pixels, k = 1..nside), phases
     std::vector<RingDev> rings(g.h);
     std::vector<long long> twoff(g.nside + 1, -1);
-    std::vector<double> rtw;
+    std::vector<double> rtw, blu;
+    std::map<int, long long> mtwoff, bluoff;
+    int nbuf = d.nlon;
     std::vector<long long> start(d.nlat + 1, 0);
     for (int r = 0; r < d.nlat; ++r) start[r + 1] = start[r] + g.ring_npix[r];
     for (int j = 0; j < g.h; ++j) {
@@ -265,6 +270,36 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
       if ((int)f.size() > RING_MAXFAC) return SHOT_E_UNSUPPORTED;
       R.nfac = (int)f.size();
       for (int q = 0; q < RING_MAXFAC; ++q) R.fac[q] = q < R.nfac ? f[q] : 0;
+      // a prime factor above 64 (polar rings of 4p pixels beyond Nside 64):
+      // Bluestein, a cyclic convolution of power-of-two length M >= 2 len - 1
+      R.bm = 0;
+      if (f.back() > 64) {
+        int M = 1;
+        while (M < 2 * len - 1) M *= 2;
+        R.bm = M;
+        const std::vector<int> fm = fft_factors(M);
+        R.bm_nfac = (int)fm.size();
+        for (int q = 0; q < RING_MAXFAC; ++q) R.bm_fac[q] = q < R.bm_nfac ? fm[q] : 0;
+        if (!mtwoff.count(M)) {
+          mtwoff[M] = (long long)rtw.size() / 2;
+          for (int q = 0; q < M; ++q) {
+            const long double ang = -2.0L * (long double)M_PI * (long double)q / (long double)M;
+            rtw.push_back((double)cosl(ang));
+            rtw.push_back((double)sinl(ang));
+          }
+        }
+        R.bm_twoff = (int)mtwoff[M];
+        if (!bluoff.count(len)) {
+          std::vector<double> ch, bh;
+          bluestein_tables(len, M, ch, bh);
+          bluoff[len] = (long long)blu.size() / 2;
+          blu.insert(blu.end(), ch.begin(), ch.end());
+          blu.insert(blu.end(), bh.begin(), bh.end());
+        }
+        R.ch_off = (int)bluoff[len];
+        R.bh_off = R.ch_off + len;
+        nbuf = std::max(nbuf, M);
+      }
     }
     std::vector<double> ph((size_t)g.h * d.L * 2);
     for (int j = 0; j < g.h; ++j)
@@ -274,14 +309,25 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
         ph[((size_t)j * d.L + m) * 2 + 1] = (double)sinl(ang);
       }
     shot_status st2;
+    // the row kernel holds two buffers and the twiddles of nbuf entries in
+    // LDS: where Bluestein's buffers would not fit (float64 at Nside 512),
+    // every ring keeps its direct stages
+    if ((size_t)3 * nbuf * (f64 ? 16 : 8) > 160 * 1024) {
+      for (auto& R : rings) R.bm = 0;
+      nbuf = d.nlon;
+    }
+    if (blu.empty()) blu.assign(2, 0.0);
+    g.ring_nbuf = nbuf;
     if ((st2 = upload((void**)&g.d_ring, rings, s)) != SHOT_OK) return st2;
     if (f64) {
       if ((st2 = upload(&g.d_ring_tw, rtw, s)) != SHOT_OK) return st2;
       if ((st2 = upload(&g.d_ring_ph, ph, s)) != SHOT_OK) return st2;
+      if ((st2 = upload(&g.d_ring_blu, blu, s)) != SHOT_OK) return st2;
     } else {
-      std::vector<float> a(rtw.begin(), rtw.end()), b(ph.begin(), ph.end());
+      std::vector<float> a(rtw.begin(), rtw.end()), b(ph.begin(), ph.end()), c(blu.begin(), blu.end());
       if ((st2 = upload(&g.d_ring_tw, a, s)) != SHOT_OK) return st2;
       if ((st2 = upload(&g.d_ring_ph, b, s)) != SHOT_OK) return st2;
+      if ((st2 = upload(&g.d_ring_blu, c, s)) != SHOT_OK) return st2;
     }
   }
   std::vector<double> tw(2 * (size_t)d.nlon);
@@ -590,6 +636,8 @@ RowArgs<T> row_args(const shot_plan_s* P, const GridRec& g, const Layout& Lo, co
     a.ring = g.d_ring;
     a.ring_tw = static_cast<const cpx<T>*>(g.d_ring_tw);
     a.ring_ph = static_cast<const cpx<T>*>(g.d_ring_ph);
+    a.ring_blu = static_cast<const cpx<T>*>(g.d_ring_blu);
+    a.nbuf = g.ring_nbuf;
   }
   a.item0 = G.first;
   a.items = W.items;

@@ -137,6 +137,56 @@ std::vector<int> fft_factors(int n) {
   return f;
 }
 
+void fft_pow2(std::vector<double>& re, std::vector<double>& im, int sign) {
+  const size_t n = re.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {  // bit reversal
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) {
+      std::swap(re[i], re[j]);
+      std::swap(im[i], im[j]);
+    }
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    for (size_t k = 0; k < len / 2; ++k) {
+      const long double ang = (long double)sign * 2.0L * (long double)M_PI * (long double)k / (long double)len;
+      const double wr = (double)cosl(ang), wi = (double)sinl(ang);
+      for (size_t i = 0; i < n; i += len) {
+        const size_t u = i + k, v = i + k + len / 2;
+        const double xr = re[v] * wr - im[v] * wi, xi = re[v] * wi + im[v] * wr;
+        re[v] = re[u] - xr;
+        im[v] = im[u] - xi;
+        re[u] += xr;
+        im[u] += xi;
+      }
+    }
+  }
+}
+
+void bluestein_tables(int n, int m, std::vector<double>& chirp, std::vector<double>& bhat) {
+  chirp.assign(2 * (size_t)n, 0.0);
+  std::vector<double> br(m, 0.0), bi(m, 0.0);
+  for (int k = 0; k < n; ++k) {
+    const long long q = ((long long)k * k) % (2LL * n);
+    const long double ang = -(long double)M_PI * (long double)q / (long double)n;
+    chirp[2 * k] = (double)cosl(ang);
+    chirp[2 * k + 1] = (double)sinl(ang);
+    br[k] = chirp[2 * k];
+    bi[k] = -chirp[2 * k + 1];
+    if (k > 0) {
+      br[m - k] = br[k];
+      bi[m - k] = bi[k];
+    }
+  }
+  fft_pow2(br, bi, -1);
+  bhat.assign(2 * (size_t)m, 0.0);
+  for (int k = 0; k < m; ++k) {
+    bhat[2 * k] = br[k] / m;
+    bhat[2 * k + 1] = bi[k] / m;
+  }
+}
+
 void healpix_rings(int nside, std::vector<double>& z, std::vector<int>& npix, std::vector<double>& phi0) {
   const int nr = 4 * nside - 1;
   z.assign(nr, 0.0);

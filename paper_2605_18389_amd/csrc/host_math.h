@@ -44,6 +44,17 @@ void clenshaw_curtis(int n, std::vector<double>& x, std::vector<double>& w);
 // primes in increasing order (the device FFT runs those as generic stages).
 std::vector<int> fft_factors(int n);
 
+// In-place radix-2 FFT of a power-of-two length in double precision:
+// a[k] <- sum_n a[n] exp(sign 2 pi i n k / n_len) (no scaling).
+void fft_pow2(std::vector<double>& re, std::vector<double>& im, int sign);
+
+// Bluestein tables for a transform of length n with convolution length m
+// (a power of two >= 2n - 1): chirp[k] = exp(-i pi k^2 / n), k < n (angle
+// reduced exactly as k^2 mod 2n), and bhat = FFT_m(b) / m with sign -1, where
+// b[k] = b[m - k] = conj(chirp[k]) for k < n and 0 between; interleaved
+// (re, im) pairs.
+void bluestein_tables(int n, int m, std::vector<double>& chirp, std::vector<double>& bhat);
+
 // HEALPix rings (Gorski et al. 2005), north to south, i = 1 .. 4 nside - 1:
 // z = cos(colatitude) of the ring, its pixel count and the longitude of its
 // first pixel in RING order.  North polar cap (i < nside): z = 1 - i^2/(3 nside^2),

@@ -623,6 +623,57 @@ __device__ void kratio_fold(const RowArgs<T>& A, int it, int k, int slot, double
 // partial sums are written at the group's first pair (the other slots of the
 // group get the neutral element) so all consumers still reduce over j < h.
 // ---------------------------------------------------------------------------
+// Transform of one ring pair's packed row (length n = RG->len), in LDS
+// buffers a and b of at least max(n, RG->bm) entries; returns the buffer
+// holding the result in its first n entries.  Lengths with a prime factor
+// above 64 use Bluestein's identity nk = (n^2 + k^2 - (k - n)^2) / 2: with
+// c_j = exp(sign i pi j^2 / n), X_k = c_k sum_j (x_j c_j) conj(c_{k-j}), a
+// cyclic convolution of length bm evaluated with two power-of-two FFTs and
+// the plan's spectrum of the conjugate chirp (the inverse direction uses the
+// complex conjugates of both tables).  tw: twiddles of the FFT length used.
+template <typename T>
+__device__ __forceinline__ cpx<T>* ring_fft(cpx<T>* a, cpx<T>* b, int n, const RingDev* RG, const cpx<T>* tw,
+                                            const cpx<T>* __restrict__ blu, T sign) {
+  // one inlined FFT, run once (direct) or twice (the convolution's forward
+  // and inverse transforms): each inlined copy carries every radix stage
+  const int M = RG->bm;
+  const bool bs = M > 0;
+  const cpx<T>* ch = blu + RG->ch_off;
+  const cpx<T>* bh = blu + RG->bh_off;
+  const bool conj = sign > (T)0;
+  if (bs) {
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+      cpx<T> c = j < n ? ch[j] : cpx<T>{(T)0, (T)0};
+      if (conj) c.y = -c.y;
+      a[j] = j < n ? cmul(a[j], c) : cpx<T>{(T)0, (T)0};
+    }
+    __syncthreads();
+  }
+  cpx<T>* y = a;
+  for (int pass = 0; pass < (bs ? 2 : 1); ++pass) {
+    const T sg = bs ? (pass ? (T)1 : (T)-1) : sign;
+    y = fft_lds<T>(y, y == a ? b : a, bs ? M : n, 1, bs ? RG->bm_fac : RG->fac, bs ? RG->bm_nfac : RG->nfac, tw,
+                   sg);
+    if (bs && pass == 0) {
+      for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        cpx<T> f = bh[k];
+        if (conj) f.y = -f.y;
+        y[k] = cmul(y[k], f);
+      }
+      __syncthreads();
+    }
+  }
+  if (bs) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      cpx<T> c = ch[k];
+      if (conj) c.y = -c.y;
+      y[k] = cmul(y[k], c);
+    }
+    __syncthreads();
+  }
+  return y;
+}
+
 // a[e][r] for e, r in {0, 1} by selects (a run-time index would put the
 // array in scratch memory)
 template <typename T>
@@ -643,7 +694,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
   // HEALPix: this pair's rings (one pair per group), else uniform rows
   const RingDev* RG = A.ring ? A.ring + jp0 : nullptr;
   const int N = RG ? RG->len : (NC > 0 ? NC : A.nlon);
-  const int NB = RG ? A.nlon : N;  // LDS stride: the longest row
+  const int NB = RG ? A.nbuf : N;  // LDS stride: the longest ring or Bluestein convolution
   cpx<T>* buf0 = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* buf1 = buf0 + RPW * NB;
   cpx<T>* twl = buf1 + RPW * NB;
@@ -705,10 +756,12 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
     return;
   }
 
-  const cpx<T>* twsrc = RG ? A.ring_tw + RG->twoff : A.tw;
+  // twiddles of the row length, or of the convolution length of a Bluestein ring
+  const cpx<T>* twsrc = RG ? A.ring_tw + (RG->bm ? RG->bm_twoff : RG->twoff) : A.tw;
+  const int ntw = (RG && RG->bm) ? RG->bm : N;
   const cpx<T>* tws = twsrc;
   if (A.tw_lds) {
-    for (int i = tid; i < N; i += bs) twl[i] = twsrc[i];
+    for (int i = tid; i < ntw; i += bs) twl[i] = twsrc[i];
     tws = twl;
   }
   cpx<T>* X = buf0;
@@ -783,7 +836,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
       }
     }
     __syncthreads();
-    X = fft_lds<T>(buf0, buf1, N, 1, RG->fac, RG->nfac, tws, (T)1);
+    X = ring_fft<T>(buf0, buf1, N, RG, tws, A.ring_blu, (T)1);
   } else if (has_inverse) {
     // G_j[m] = GE + GO, G_j'[m] = GE - GO; Z[m] = G_j[m] + i G_j'[m] and its
     // Hermitian mirror Z[N-m] = conj(G_j[m]) + i conj(G_j'[m]); zero elsewhere.
@@ -1043,7 +1096,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
 
   // forward FFT of the rows now in X, fold, weight, store
   cpx<T>* other = (X == buf0) ? buf1 : buf0;
-  cpx<T>* Z = RG ? fft_lds<T>(X, other, N, 1, RG->fac, RG->nfac, tws, (T)-1)
+  cpx<T>* Z = RG ? ring_fft<T>(X, other, N, RG, tws, A.ring_blu, (T)-1)
                  : fft_any<T, NC, RPW>(X, other, N, A.fac, A.nfac, tws, (T)-1);
   const bool adj = (mode == ROW_ADJ_START || mode == ROW_ADJ_A || mode == ROW_ADJ_VB || mode == ROW_ADJU_B ||
                    mode == ROW_ADJU_A);
@@ -2341,10 +2394,22 @@ template <typename T, int RPW, int NC, int BS = 256>
 static hipError_t launch_rows_nc(const RowArgs<T>& a, int nb, hipStream_t stream) {
   dim3 grid((a.h + RPW - 1) / RPW, nb);
   RowArgs<T> b = a;
-  // two FFT buffers per pair, plus the twiddles when they fit in 64 KiB of LDS
-  const size_t base = (size_t)2 * RPW * a.nlon * sizeof(cpx<T>);
-  b.tw_lds = base + (size_t)a.nlon * sizeof(cpx<T>) <= 65536 - 1024 ? 1 : 0;
-  const size_t lds = base + (b.tw_lds ? (size_t)a.nlon * sizeof(cpx<T>) : 0);
+  // two FFT buffers per pair, plus the twiddles when they fit in 64 KiB of
+  // LDS; ring grids size the buffers by their longest ring or Bluestein
+  // convolution and always keep the twiddles in LDS (up to 160 KiB)
+  const size_t nbuf = a.ring ? (size_t)a.nbuf : (size_t)a.nlon;
+  const size_t base = (size_t)2 * RPW * nbuf * sizeof(cpx<T>);
+  b.tw_lds = (a.ring || base + nbuf * sizeof(cpx<T>) <= 65536 - 1024) ? 1 : 0;
+  const size_t lds = base + (b.tw_lds ? nbuf * sizeof(cpx<T>) : 0);
+  if (lds > 65536) {
+    static size_t attr_bytes = 65536;  // dynamic LDS enabled so far, per kernel instantiation
+    if (lds > attr_bytes) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&row_kernel<T, RPW, NC, BS>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr_bytes = lds;
+    }
+  }
   SHOT_LAUNCH((row_kernel<T, RPW, NC, BS>), grid, dim3(BS), lds, stream, b);
   return hipGetLastError();
 }

@@ -40,6 +40,14 @@ struct RingDev {
   int twoff;               // offset of this length's twiddles exp(-2 pi i k/len) in ring_tw
   int nfac;                // factors of len (4, 2, 3, 5, then other primes)
   int fac[RING_MAXFAC];
+  // Bluestein transform for lengths with a large prime factor (bm > 0): the
+  // length-len DFT as a cyclic convolution of power-of-two length bm
+  int bm;                  // convolution length (0: direct stages)
+  int bm_nfac;             // factors of bm (4s and a 2)
+  int bm_fac[RING_MAXFAC];
+  int bm_twoff;            // offset of exp(-2 pi i k/bm), k < bm, in ring_tw
+  int ch_off;              // offset of the chirp exp(-i pi n^2/len), n < len, in ring_blu
+  int bh_off;              // offset of FFT_bm(filter) / bm in ring_blu
 };
 
 // Row kernel modes.
@@ -110,6 +118,8 @@ struct RowArgs {
   const RingDev* ring;
   const cpx<T>* ring_tw;
   const cpx<T>* ring_ph;
+  const cpx<T>* ring_blu;   // HEALPix: Bluestein chirps and filter spectra
+  int nbuf;                 // HEALPix: LDS length of each FFT buffer (longest ring or convolution)
 };
 
 // Pointwise combination of per-item fields into a per-pair gradient:

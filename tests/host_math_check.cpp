@@ -190,6 +190,54 @@ static int check_lobatto() {
   return 0;
 }
 
+// Bluestein tables: the length-n DFT assembled from them (pre-multiply by the
+// chirp, power-of-two FFT, multiply by the filter spectrum, inverse FFT,
+// post-multiply; conjugated tables for the inverse direction) equals the
+// direct sum to 1e-12 of its largest value, in both directions.
+static int check_bluestein(int n) {
+  int m = 1;
+  while (m < 2 * n - 1) m *= 2;
+  std::vector<double> ch, bh;
+  bluestein_tables(n, m, ch, bh);
+  std::vector<double> xr(n), xi(n);
+  for (int j = 0; j < n; ++j) {
+    xr[j] = std::sin(0.37 * j * j + 1.0);
+    xi[j] = std::cos(1.3 * j + 0.2);
+  }
+  for (int sign : {-1, 1}) {
+    const double cs = sign < 0 ? 1.0 : -1.0;  // conjugate the tables for sign +1
+    std::vector<double> ar(m, 0.0), ai(m, 0.0);
+    for (int j = 0; j < n; ++j) {
+      const double cr = ch[2 * j], ci = cs * ch[2 * j + 1];
+      ar[j] = xr[j] * cr - xi[j] * ci;
+      ai[j] = xr[j] * ci + xi[j] * cr;
+    }
+    fft_pow2(ar, ai, -1);
+    for (int k = 0; k < m; ++k) {
+      const double fr = bh[2 * k], fi = cs * bh[2 * k + 1];
+      const double r = ar[k] * fr - ai[k] * fi, i = ar[k] * fi + ai[k] * fr;
+      ar[k] = r;
+      ai[k] = i;
+    }
+    fft_pow2(ar, ai, 1);
+    double err = 0, big = 0;
+    for (int k = 0; k < n; ++k) {
+      const double cr = ch[2 * k], ci = cs * ch[2 * k + 1];
+      const double yr = ar[k] * cr - ai[k] * ci, yi = ar[k] * ci + ai[k] * cr;
+      long double dr = 0, di = 0;
+      for (int j = 0; j < n; ++j) {
+        const long double ang = (long double)sign * 2.0L * (long double)M_PI * (long double)(((long long)j * k) % n) / n;
+        dr += xr[j] * cosl(ang) - xi[j] * sinl(ang);
+        di += xr[j] * sinl(ang) + xi[j] * cosl(ang);
+      }
+      err = std::fmax(err, std::hypot(yr - (double)dr, yi - (double)di));
+      big = std::fmax(big, std::hypot((double)dr, (double)di));
+    }
+    if (err > 1e-12 * big) return fail("bluestein", n, sign);
+  }
+  return 0;
+}
+
 int main() {
   int rc = 0;
   for (int L : {1, 15, 16, 17, 90, 181, 720})
@@ -202,6 +250,7 @@ int main() {
   rc |= check_checkpoints(150, 75, 64);
   for (int nside : {1, 2, 3, 7, 8, 64, 256}) rc |= check_healpix(nside);
   rc |= check_factors();
+  for (int n : {268, 404, 1004}) rc |= check_bluestein(n);
   rc |= check_lobatto();
   if (!rc) std::printf("OK\n");
   return rc;

@@ -197,3 +197,22 @@ def test_nside64_fp32():
            cost_ref=r["cost"])
     if graded:
         assert abs(info[0]["cost"] - r["cost"]) <= tolerance(r, "fp32") * abs(r["cost"])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_bluestein_rings_match_oracle(prec, tol):
+    """Nside = 80, L = 160: the polar rings of 4p pixels with p = 67, 71, 73 and
+    79 (prime factors above 64) take the Bluestein transform in both
+    directions; heat apply and its transpose against the direct ring sums."""
+    nside, L = 80, 160
+    announce(f"healpix bluestein nside={nside} {prec}")
+    P = _plan([("hp", nside, L)], prec)
+    g = O.HealpixGrid(nside, L)
+    v = _fields(g, 2, 80)
+    t = np.array([2e-4, 3e-3])
+    out = to_np(P.heat_apply(to_dev(v, P.dtype), t)).reshape(v.shape)
+    ref = np.stack([O.heat_apply(v[i][None], g, t[i])[0] for i in range(2)])
+    assert rel_l2(out, ref) < tol
+    outT = to_np(P.heat_apply(to_dev(v, P.dtype), t, transpose=True)).reshape(v.shape)
+    refT = np.stack([O.heat_apply(v[i][None], g, t[i], transpose=True)[0] for i in range(2)])
+    assert rel_l2(outT, refT) < tol
