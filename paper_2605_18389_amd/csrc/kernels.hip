@@ -1807,11 +1807,12 @@ __global__ void __launch_bounds__(256) legendre_recur_kernel(LegArgs<T> A) {
 // Wave issue priority from the blocks of rows a wave still has to run (both
 // passes): the three waves sharing a SIMD come from different orders, and
 // running the one with the most work left first makes them finish together
-// instead of leaving one long wave alone on the SIMD at the end.
+// instead of leaving one long wave alone on the SIMD at the end.  Thresholds
+// from interleaved timings at L = 720 (priorities off 41.4 us, these 39.5).
 __device__ __forceinline__ void prio_by_blocks(int left) {
-  if (left >= 18) __builtin_amdgcn_s_setprio(3);
-  else if (left >= 10) __builtin_amdgcn_s_setprio(2);
-  else if (left >= 4) __builtin_amdgcn_s_setprio(1);
+  if (left >= 14) __builtin_amdgcn_s_setprio(3);
+  else if (left >= 7) __builtin_amdgcn_s_setprio(2);
+  else if (left >= 2) __builtin_amdgcn_s_setprio(1);
   else __builtin_amdgcn_s_setprio(0);
 }
 
