@@ -31,7 +31,6 @@ namespace {
 struct SplitSched {
   SplitPartH* d_parts = nullptr;
   double* d_ck = nullptr;
-  int* d_order = nullptr;     // [n] part run by workgroup column b
   int n = 0, maxlen = 0, npb = 0;
 };
 
@@ -203,7 +202,7 @@ uint16_t to_bf16(double v) {
 void free_grid(GridRec& g) {
   for (void* p : {g.d_tab, g.d_tabT, (void*)g.d_toffT, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam,
                   (void*)g.d_rseed, (void*)g.sw.d_parts, (void*)g.sw.d_ck, (void*)g.ss.d_parts,
-                  (void*)g.ss.d_ck, (void*)g.sw.d_order, (void*)g.ss.d_order, (void*)g.d_ring, g.d_ring_tw, g.d_ring_ph, g.d_ring_blu, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
+                  (void*)g.ss.d_ck, (void*)g.d_ring, g.d_ring_tw, g.d_ring_ph, g.d_ring_blu, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
     if (p) (void)hipFree(p);
   g.d_tab = g.d_tabT = g.d_aw = g.d_tw = g.d_pbuf = g.d_ring_tw = g.d_ring_ph = g.d_ring_blu = nullptr;
   g.d_ring = nullptr;
@@ -419,14 +418,18 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
       S.n = (int)parts.size();
       S.maxlen = 0;
       for (const auto& q : parts) S.maxlen = std::max(S.maxlen, q.r_hi - q.r_lo);
-      legendre_checkpoints(d.L, xs, coef, seed, parts, ck, (int)hw);
-      // dispatch order: rows balanced over the 256 compute units
+      // dispatch order: rows balanced over the 256 compute units.  The list is
+      // stored in that order (workgroup b runs entry b; the partial-buffer slots
+      // travel inside the entries), so a workgroup reads its entry with one load
+      // instead of an index load followed by a dependent entry load.
       std::vector<int> wts;
       for (const auto& q : parts) wts.push_back(q.r_hi - q.r_lo);
       const std::vector<int> order = balanced_dispatch(wts, 256);
-      if ((st = upload((void**)&S.d_parts, parts, s)) != SHOT_OK) return st;
+      std::vector<SplitPartH> run(parts.size());
+      for (size_t b = 0; b < order.size(); ++b) run[b] = parts[order[b]];
+      legendre_checkpoints(d.L, xs, coef, seed, run, ck, (int)hw);
+      if ((st = upload((void**)&S.d_parts, run, s)) != SHOT_OK) return st;
       if ((st = upload((void**)&S.d_ck, ck, s)) != SHOT_OK) return st;
-      if ((st = upload((void**)&S.d_order, order, s)) != SHOT_OK) return st;
       if (k) {
         std::vector<int2> cut(d.L, make_int2(1, -1));
         for (const auto& q : parts)
@@ -766,7 +769,6 @@ shot_status run_leg(shot_plan_s* P, const GridRec& g, LegArgs<T> a, hipStream_t 
     e = launch_legendre_mma<T>(a, g.tab_kind, nt, s);
   } else if (const SplitSched* S = leg_split(P, g, a.nb, &ib)) {
     a.parts = S->d_parts;
-    a.order = S->d_order;
     a.nparts = S->n;
     a.maxlen = S->maxlen;
     a.rck = S->d_ck;

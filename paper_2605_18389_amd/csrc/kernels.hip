@@ -1826,7 +1826,7 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
   constexpr int RB = NV / (2 * IB);
   constexpr int V = NV;
   const int L = A.L, h = A.h;
-  const int part = A.order[blockIdx.x];
+  const int part = blockIdx.x;  // the work list is stored in dispatch order
   const SplitPartH P = A.parts[part];
   const int m = P.m;
   const int nr = L - m;

@@ -147,7 +147,6 @@ struct LegArgs {
   const double* rseed;    // [L][h]
   const double* rck;      // [nparts][4][h][2] recurrence checkpoints (row-split kernel)
   const SplitPartH* parts;// row-split kernel: work list of parts
-  const int* order;       // [nparts] part run by workgroup column b
   int nparts;
   int maxlen;             // longest part (rows)
   void* pbuf;             // [chunks][npb][IB][h][2] partial synthesis sums of cut orders (cpx<T>)
