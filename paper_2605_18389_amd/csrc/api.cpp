@@ -525,7 +525,8 @@ shot_status carve(shot_plan_s* P, const Layout& Lo, int nitems, bool sinkhorn, i
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   const size_t o_items = take(sizeof(ItemDev) * nitems);
   const size_t o_spec = take(sizeof(cpx<T>) * Lo.spec_total);
-  const size_t o_hl = take(sizeof(T) * (size_t)nitems * Lo.Lmax);
+  // (+ 32 entries: the row-split Legendre kernel prefetches up to 15 rows past an order's end)
+  const size_t o_hl = take(sizeof(T) * ((size_t)nitems * Lo.Lmax + 32));
   size_t o_u0 = 0, o_u1 = 0, o_v0 = 0, o_v1 = 0, o_red = 0, o_rh = 0, o_prep = 0, o_res = 0, o_eh = 0, o_brk = 0,
          o_kr = 0;
   if (sinkhorn) {

@@ -1809,6 +1809,15 @@ __global__ void __launch_bounds__(256) legendre_recur_kernel(LegArgs<T> A) {
 // running the one with the most work left first makes them finish together
 // instead of leaving one long wave alone on the SIMD at the end.  Thresholds
 // from interleaved timings at L = 720 (priorities off 41.4 us, these 39.5).
+// A copy of a lane-varying index that the compiler cannot see through: the
+// addresses derived from it are recomputed where they are used instead of
+// being shared with (and kept live across the loops until) a later use of the
+// same expression.
+__device__ __forceinline__ int opaque_index(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 __device__ __forceinline__ void prio_by_blocks(int left) {
   if (left >= 14) __builtin_amdgcn_s_setprio(3);
   else if (left >= 7) __builtin_amdgcn_s_setprio(2);
@@ -1844,36 +1853,81 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
   const long long toff = tri_off(m, L);
   const int r_lo = P.r_lo + split_row(len, wave), r_hi = P.r_lo + split_row(len, wave + 1);
 
-  for (int q = tid; q < npl; q += 256) {
+  // Every global load of the prologue is issued before the first wait:
+  // unconditional loads at clamped, in-bounds addresses into registers (values
+  // a thread does not own are dropped at the LDS store or replaced at their
+  // use).  A load under a branch makes the join wait for it, which chained the
+  // coefficient, spectrum and checkpoint loads into one round trip each.
+  constexpr int NQ = 3;  // per-thread coefficient rows and spectrum entries staged at once
+  const int ptid = opaque_index(tid), plane = ptid & 63;
+  long long soff[IB];
+#pragma unroll
+  for (int i = 0; i < IB; ++i) soff[i] = A.items[A.item0 + ib0 + min(i, nbi - 1)].soff;
+  double cv[NQ], gv[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int r = min(P.r_lo + ptid + k * 256, nr - 1);
+    cv[k] = A.rcoef[toff + r];
+    gv[k] = A.rgam[toff + r];
+  }
+  cpx<T> sv[IB][NQ];
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+      sv[i][k] = A.spec[soff[i] + (size_t)(2 * m) * h + min(ptid + k * 256, 2 * h - 1)];
+  double xj[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) xj[c] = A.xs[min(plane + 64 * c, h - 1)];
+  const double2* ckp = reinterpret_cast<const double2*>(A.rck) + ((size_t)part * 4 + wave) * h;
+  // the first wave of a part that starts an order resumes from the seed
+  // (P̄_m^m, 0) itself: half the bytes of its checkpoint (the second value is
+  // then a re-read of the first and replaced by zero)
+  const bool from_seed = wave == 0 && P.r_lo == 0;
+  auto ck_load = [&](int c, int ln) {
+    const int j = min(ln + 64 * c, h - 1);
+    const double* p = from_seed ? A.rseed + (size_t)m * h + j : reinterpret_cast<const double*>(ckp + j);
+    return make_double2(p[0], p[from_seed ? 0 : 1]);
+  };
+  auto ck_use = [&](double2 v, int c) {
+    const bool ok = lane + 64 * c < h;
+    return make_double2(ok ? v.x : 0.0, ok && !from_seed ? v.y : 0.0);
+  };
+  double2 ck[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) ck[c] = ck_load(c, plane);
+
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = ptid + k * 256, r = P.r_lo + q;
+    if (q < npl) {
+      cf[q] = (r < nr && r > 0) ? cv[k] : 0.0;
+      gm[q] = (r < nr) ? gv[k] : 0.0;
+    }
+  }
+  for (int q = tid + NQ * 256; q < npl; q += 256) {  // longer parts than one staging round
     const int r = P.r_lo + q;
     cf[q] = (r < nr && r > 0) ? A.rcoef[toff + r] : 0.0;
     gm[q] = (r < nr) ? A.rgam[toff + r] : 0.0;
   }
   for (int i = 0; i < IB; ++i)
     for (int q = tid; q < npl; q += 256) bs[(size_t)i * maxpl + q] = make_double2(0.0, 0.0);
-
-  // this order's folded spectrum, loaded once per workgroup into the LDS that
+  // this order's folded spectrum, staged once per workgroup in the LDS that
   // the synthesis partial sums reuse later (read into registers before then)
   if (A.mode != 2)
-    for (int i = 0; i < nbi; ++i) {
-      const cpx<T>* src = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
-      for (int q = tid; q < 2 * h; q += 256) gpart[(size_t)i * 2 * h + q] = src[q];
-    }
-  double xj[C];
-  const double2* ckp = reinterpret_cast<const double2*>(A.rck) + ((size_t)part * 4 + wave) * h;
-  // the first wave of a part that starts an order resumes from the seed
-  // (P̄_m^m, 0) itself: half the bytes of its checkpoint
-  const bool from_seed = wave == 0 && P.r_lo == 0;
-  auto checkpoint = [&](int c) {
-    const int j = lane + 64 * c;
-    if (j >= h) return make_double2(0.0, 0.0);
-    return from_seed ? make_double2(A.rseed[(size_t)m * h + j], 0.0) : ckp[j];
-  };
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int j = lane + 64 * c;
-    xj[c] = j < h ? A.xs[j] : 0.0;
-  }
+    for (int i = 0; i < IB; ++i) {
+      if (i >= nbi) break;
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) {
+        const int q = ptid + k * 256;
+        if (q < 2 * h) gpart[(size_t)i * 2 * h + q] = sv[i][k];
+      }
+      const cpx<T>* src = A.spec + soff[i] + (size_t)(2 * m) * h;
+      for (int q = tid + NQ * 256; q < 2 * h; q += 256) gpart[(size_t)i * 2 * h + q] = src[q];
+    }
+#pragma unroll
+  for (int c = 0; c < C; ++c) xj[c] = lane + 64 * c < h ? xj[c] : 0.0;
   __syncthreads();
 
   if (A.mode != 2) {
@@ -1896,14 +1950,21 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
     double R1[C], R2[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const double2 ck = checkpoint(c);
-      R1[c] = ck.x;
-      R2[c] = ck.y;
+      const double2 v = ck_use(ck[c], c);
+      R1[c] = v.x;
+      R2[c] = v.y;
     }
     const int nblk = (r_hi - r_lo + RB - 1) / RB;  // this wave's blocks in each of the two passes
     int left = 2 * nblk;
+    constexpr int SH = NV == 32 ? 1 : 2;  // lanes per reduced value after the transpose-reduction
+    // this lane's heat multiplier for row r0 + (its row in the block): loaded
+    // at the start of each block, used after the block's arithmetic (rows past
+    // the order's end read the array's padding and are dropped)
+    const int hoff = (A.item0 + ib0 + min(((lane >> SH) >> 1) % IB, nbi - 1)) * A.hl_stride + m +
+                     ((lane >> SH) >> 1) / IB;
     for (int r0 = r_lo; r0 < r_hi; r0 += RB) {
       prio_by_blocks(left--);
+      const T hlv = A.hl[hoff + r0];
       double acc[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] = 0.0;
@@ -1928,14 +1989,13 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
 #pragma unroll
       for (int v = 0; v < V; ++v) red[v] = (R)acc[v];
       const R s = transpose_reduce<R, NV>(red, lane);
-      constexpr int SH = NV == 32 ? 1 : 2;
       if ((lane & ((1 << SH) - 1)) == 0) {
         const int vv = lane >> SH, comp = vv & 1, i = (vv >> 1) % IB, rr = (vv >> 1) / IB, r = r0 + rr;
         if (r < r_hi && i < nbi) {
           const int q = r - P.r_lo;
           const double g = gm[q];
           if (A.mode == 0) {
-            const double sc = g * g * (double)A.hl[(size_t)(A.item0 + ib0 + i) * A.hl_stride + m + r];
+            const double sc = g * g * (double)hlv;
             reinterpret_cast<double*>(&bs[(size_t)i * maxpl + q])[comp] = (double)s * sc;
           } else {
             T* dst = reinterpret_cast<T*>(&A.coeff[A.items[A.item0 + ib0 + i].coff + toff + r]);
@@ -1952,6 +2012,13 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
         bs[(size_t)i * maxpl + q] = make_double2((double)c.x * gm[q], (double)c.y * gm[q]);
       }
   }
+  // the synthesis pass restarts from the same checkpoints: issue their loads
+  // before the barrier so that they arrive while the workgroup's waves meet
+  {
+    const int ln = opaque_index(lane);
+#pragma unroll
+    for (int c = 0; c < C; ++c) ck[c] = ck_load(c, ln);
+  }
   __syncthreads();
 
   // synthesis over this wave's rows: G^{E|O}_m(j) += (b_l gamma_l) R_l(x_j)
@@ -1959,9 +2026,9 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
   double R1[C], R2[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const double2 ck = checkpoint(c);
-    R1[c] = ck.x;
-    R2[c] = ck.y;
+    const double2 v = ck_use(ck[c], c);
+    R1[c] = v.x;
+    R2[c] = v.y;
 #pragma unroll
     for (int i = 0; i < IB; ++i) { gE[c][i] = make_double2(0.0, 0.0); gO[c][i] = make_double2(0.0, 0.0); }
   }
@@ -2008,8 +2075,10 @@ __global__ void __launch_bounds__(256, IB * C > 6 ? 2 : 3) legendre_split_kernel
   }
   __syncthreads();
   if (P.ns == 1) {
-    for (int i = 0; i < nbi; ++i) {
-      cpx<T>* dst = A.spec + A.items[A.item0 + ib0 + i].soff + (size_t)(2 * m) * h;
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      if (i >= nbi) break;
+      cpx<T>* dst = A.spec + soff[i] + (size_t)(2 * m) * h;
       for (int q = tid; q < 2 * h; q += 256) {
         cpx<T> s = {(T)0, (T)0};
 #pragma unroll

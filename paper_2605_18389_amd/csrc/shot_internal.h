@@ -154,7 +154,7 @@ struct LegArgs {
   int item0, nb;
   const ItemDev* items;
   cpx<T>* spec;
-  const T* hl;            // [nitems][hl_stride] heat multipliers (by absolute item index)
+  const T* hl;            // [nitems][hl_stride] heat multipliers (by absolute item index), + 32 readable entries
   int hl_stride;
   int mode;               // 0 fused (analysis, x h, synthesis), 1 analysis -> coeff, 2 coeff -> synthesis
   int jpt;                // RECURRENCE mode: latitude chains per thread (0 = automatic)
