@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <numeric>
 #include <queue>
+#include <random>
 #include <cmath>
 #include <thread>
 
@@ -364,6 +365,32 @@ std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu) {
     load[s] += weight[i];
     used[i] = 1;
     if ((int)slot[s].size() < cap[s]) pq.push({load[s], s});
+  }
+  // The filling above leaves a staircase of slot loads (at L = 720: 930 to
+  // 1089 rows against a mean of 1014) that no swap lowering the heaviest slot
+  // alone can flatten.  Random swaps of one item between two slots (slot sizes
+  // kept) that do not raise the sum of squared deviations from the mean accept
+  // the sideways moves that can (1011 to 1017 at L = 720); the generator's
+  // fixed seed keeps the plan deterministic.
+  std::mt19937 rng(20240607u);
+  auto sq = [](double v) { return v * v; };
+  for (int sweep = 0; sweep < 200; ++sweep) {
+    for (int k = 0; k < 8 * ncu; ++k) {
+      const int s = (int)(rng() % (unsigned)ncu), t = (int)(rng() % (unsigned)ncu);
+      if (s == t || slot[s].empty() || slot[t].empty()) continue;
+      const int i = (int)(rng() % slot[s].size()), j = (int)(rng() % slot[t].size());
+      const long long d = (long long)weight[slot[s][i]] - weight[slot[t][j]];
+      if (d == 0) continue;
+      const double before = sq((double)load[s] - target) + sq((double)load[t] - target);
+      const double after = sq((double)(load[s] - d) - target) + sq((double)(load[t] + d) - target);
+      if (after <= before) {
+        std::swap(slot[s][i], slot[t][j]);
+        load[s] -= d;
+        load[t] += d;
+      }
+    }
+    const auto mm = std::minmax_element(load.begin(), load.end());
+    if (*mm.second - *mm.first <= 1) break;
   }
   for (int s = 0; s < ncu; ++s) {
     std::stable_sort(slot[s].begin(), slot[s].end(), [&](int a, int b) { return weight[a] > weight[b]; });

@@ -104,8 +104,10 @@ int split_schedule(int L, int part_rows, std::vector<SplitPartH>& parts);
 // order (a permutation of the item indices) such that the weights summed per
 // slot are nearly equal: slots with fewer rounds take the heaviest items,
 // each topped up toward the mean with the best-fitting remaining item; the
-// others are filled heaviest first onto the least loaded slot; within a slot
-// the heaviest item runs in round 0.
+// others are filled heaviest first onto the least loaded slot; then swaps of
+// single items between slots that do not raise the squared deviation from the
+// mean even the loads out (deterministic: fixed-seed generator); within a
+// slot the heaviest item runs in round 0.
 std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu);
 
 // Recurrence checkpoints for the row-split kernel: for every part k and wave
