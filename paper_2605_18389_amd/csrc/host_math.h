@@ -16,11 +16,15 @@ namespace shot {
 
 // Row-split of one order's nr = L - m rows over the four waves of a Legendre
 // workgroup: wave w handles rows [split_row(nr, w), split_row(nr, w + 1)),
-// boundaries on multiples of 16 rows.
+// boundaries on multiples of 16 rows.  The blocks of 16 rows are dealt as
+// evenly as they go (waves 0 .. nb16 % 4 - 1 take one more): the hardware puts
+// the four waves of a workgroup on the four SIMDs of a compute unit starting
+// at a SIMD it chooses, so with three workgroups per unit a split that leaves
+// one light wave per workgroup always leaves some SIMD with only heavy waves.
 inline SHOT_HD int split_row(int nr, int w) {
   const int nb16 = (nr + 15) / 16;
-  const int bpw = (nb16 + 3) / 4;
-  const int r = w * bpw * 16;
+  const int base = nb16 / 4, rem = nb16 % 4;
+  const int r = (w * base + (w < rem ? w : rem)) * 16;
   return r < nr ? r : nr;
 }
 
