@@ -709,8 +709,11 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
   const int tid = threadIdx.x, bs = blockDim.x;
   cpx<T>* spec = A.spec + I.soff;  // [m][j][E/O]
   const int mode = A.mode;
-  const T* P = static_cast<const T*>(I.p);
-  const T* Q = static_cast<const T*>(I.q);
+  // the marginals, as global pointers (from the descriptor in memory the
+  // compiler could not tell, and flat loads also count as LDS operations)
+  using GT = const __attribute__((address_space(1))) T;
+  GT* P = (GT*)static_cast<const T*>(I.p);
+  GT* Q = (GT*)static_cast<const T*>(I.q);
   if (tid < RPW) awl[tid] = (tid < np) ? A.aw[jp0 + tid] : (T)0;
   if (tid == 0) sh_bad = 0;
 
@@ -759,11 +762,10 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
   // twiddles of the row length, or of the convolution length of a Bluestein ring
   const cpx<T>* twsrc = RG ? A.ring_tw + (RG->bm ? RG->bm_twoff : RG->twoff) : A.tw;
   const int ntw = (RG && RG->bm) ? RG->bm : N;
-  const cpx<T>* tws = twsrc;
-  if (A.tw_lds) {
-    for (int i = tid; i < ntw; i += bs) twl[i] = twsrc[i];
-    tws = twl;
-  }
+  // staged in LDS (always: a pointer that could point to LDS or to global
+  // memory would turn every twiddle read of the FFT stages into a flat load)
+  for (int i = tid; i < ntw; i += bs) twl[i] = twsrc[i];
+  const cpx<T>* tws = twl;
   cpx<T>* X = buf0;
   const bool has_inverse = (mode == ROW_INV || mode == ROW_SINK_U || mode == ROW_SINK_V || mode == ROW_CHECK ||
                             mode == ROW_ADJ_A || mode == ROW_ADJ_VB || mode == ROW_ADJU_A ||
@@ -777,7 +779,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
   const bool chk_u = (mode == ROW_SINK_U || mode == ROW_CHECK) && A.chk_slot >= 0;
   T pfv[PF][2], pfu[PF][2];
   if (pre) {
-    const T* Fm = mode == ROW_SINK_V ? Q : P;
+    GT* Fm = mode == ROW_SINK_V ? Q : P;
     const T* uo = ubuf_of(A, A.k - 1);
 #pragma unroll
     for (int e = 0; e < PF; ++e) {
@@ -2464,13 +2466,12 @@ template <typename T, int RPW, int NC, int BS = 256>
 static hipError_t launch_rows_nc(const RowArgs<T>& a, int nb, hipStream_t stream) {
   dim3 grid((a.h + RPW - 1) / RPW, nb);
   RowArgs<T> b = a;
-  // two FFT buffers per pair, plus the twiddles when they fit in 64 KiB of
-  // LDS; ring grids size the buffers by their longest ring or Bluestein
-  // convolution and always keep the twiddles in LDS (up to 160 KiB)
+  // two FFT buffers per pair plus the twiddles, in LDS (ring grids size them
+  // by their longest ring or Bluestein convolution); beyond 64 KiB (fp64 rows
+  // of 1440 or more points, long rings) the dynamic-LDS limit is raised, up
+  // to 96 KiB for 2048-point fp64 rows and 160 KiB for rings
   const size_t nbuf = a.ring ? (size_t)a.nbuf : (size_t)a.nlon;
-  const size_t base = (size_t)2 * RPW * nbuf * sizeof(cpx<T>);
-  b.tw_lds = (a.ring || base + nbuf * sizeof(cpx<T>) <= 65536 - 1024) ? 1 : 0;
-  const size_t lds = base + (b.tw_lds ? nbuf * sizeof(cpx<T>) : 0);
+  const size_t lds = (size_t)(2 * RPW + 1) * nbuf * sizeof(cpx<T>);
   if (lds > 65536) {
     static size_t attr_bytes = 65536;  // dynamic LDS enabled so far, per kernel instantiation
     if (lds > attr_bytes) {

@@ -76,7 +76,6 @@ struct RowArgs {
   int nfac;
   int fac[8];
   const cpx<T>* tw;   // nlon forward twiddles exp(-2 pi i k / nlon)
-  int tw_lds;         // set by the launcher: stage the twiddles in LDS
   const T* aw;        // h area weights (rows 0..h-1)
   int item0;          // absolute index of this launch's first item
   const ItemDev* items;
