@@ -729,7 +729,10 @@ int mma_tiles(const shot_plan_s* P, const GridRec& g, int count) {
   if (!g.d_tabT || (g.tab_kind != TAB_F32 && g.tab_kind != TAB_BF16) || g.tune_jpt < 0) return 0;
   int nt = g.tune_jpt;
   if (nt == 0) {
-    if (count < 4) return 0;
+    // bf16 tables: the matrix-core kernel streams the table several times
+    // faster than the VALU table kernel even for a single item (one item at
+    // L = 720: 0.12 ms per launch against 0.58 ms); fp32 tables from 4 items
+    if (count < 4 && g.tab_kind != TAB_BF16) return 0;
     nt = count >= 32 ? 4 : (count >= 16 ? 2 : 1);
   }
   while (nt > 1 && mma_lds_bytes(g.d.L, g.hpad, nt, g.tab_kind) > 60 * 1024) nt >>= 1;

@@ -117,6 +117,21 @@ def test_heat_apply_climate_grid_fp32():
     assert rel_l2(out.reshape(ref.shape), ref) < 1e-5
 
 
+@pytest.mark.parametrize("tiles", [0, -1])
+@pytest.mark.parametrize("grid", [("gl", 90, 180, 90), ("cc", 33, 64, 32), ("gl", 17, 36, 18)])
+def test_single_item_bf16_table_heat_apply(grid, tiles):
+    """One item on a bf16 table plan: by default the matrix-core kernel (tiles 0), or the
+    VALU table kernel when matrix cores are switched off (tiles -1); both within the bf16
+    bound of the batched test."""
+    announce(f"bf16 single item {grid} tiles={tiles}")
+    P = _plan([grid], "bf16", "table")
+    P.set_tuning(0, 0, tiles)
+    g = O.make_grid(*grid)
+    v = synth.temperature_like(np.random.default_rng(9), g.x, g.w, g.nlon, K=6)
+    out = to_np(P.heat_apply(to_dev(v[None], P.dtype), [3e-3])).reshape(v.shape)
+    assert rel_l2(out, O.heat_apply(v, g, 3e-3)) < 1e-2
+
+
 @pytest.mark.parametrize("prec,tiles,tol", [("fp32", 0, 1e-5), ("fp32", 1, 1e-5), ("fp32", 2, 1e-5),
                                             ("bf16", 0, 1e-2), ("bf16", 4, 1e-2), ("bf16", -1, 1e-2)])
 @pytest.mark.parametrize("grid", [("gl", 90, 180, 90), ("cc", 33, 64, 32), ("gl", 17, 36, 18)])
