@@ -728,15 +728,15 @@ bool use_split(const shot_plan_s* P, const GridRec& g) {
 int mma_tiles(const shot_plan_s* P, const GridRec& g, int count) {
   if (!g.d_tabT || (g.tab_kind != TAB_F32 && g.tab_kind != TAB_BF16) || g.tune_jpt < 0) return 0;
   int nt = g.tune_jpt;
-  if (nt == 0) {
-    // bf16 tables: the matrix-core kernel streams the table several times
-    // faster than the VALU table kernel even for a single item (one item at
-    // L = 720: 0.12 ms per launch against 0.58 ms); fp32 tables from 4 items
-    if (count < 4 && g.tab_kind != TAB_BF16) return 0;
-    nt = count >= 32 ? 4 : (count >= 16 ? 2 : 1);
-  }
+  // Matrix cores for any item count: they stream the table faster than the
+  // VALU table kernel even for a single item (one item at L = 720: bf16
+  // 0.58 -> 0.12 ms per launch, fp32 0.80 -> 0.53 ms)
+  if (nt == 0) nt = count >= 32 ? 4 : (count >= 16 ? 2 : 1);
+  // fewer column tiles while they overflow 60 KiB of LDS (several workgroups
+  // per compute unit); one tile may take up to 150 KiB (fp32 tables of long
+  // orders, one workgroup per unit)
   while (nt > 1 && mma_lds_bytes(g.d.L, g.hpad, nt, g.tab_kind) > 60 * 1024) nt >>= 1;
-  if (mma_lds_bytes(g.d.L, g.hpad, nt, g.tab_kind) > 60 * 1024) return 0;
+  if (mma_lds_bytes(g.d.L, g.hpad, nt, g.tab_kind) > 150 * 1024) return 0;
   (void)P;
   return nt;
 }

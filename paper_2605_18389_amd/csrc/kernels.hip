@@ -2644,6 +2644,15 @@ template <typename T, typename TT, int NT>
 static hipError_t launch_mma_nt(const LegArgs<T>& a, hipStream_t stream) {
   dim3 grid(a.L, (2 * a.nb + 16 * NT - 1) / (16 * NT));
   const size_t lds = mma_lds_bytes(a.L, a.hpad, NT, sizeof(TT) == 2 ? TAB_BF16 : TAB_F32);
+  if (lds > 65536) {  // long orders of fp32 tables: one workgroup per compute unit
+    static size_t attr_bytes = 65536;  // dynamic LDS enabled so far for this instantiation
+    if (lds > attr_bytes) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&legendre_mma_kernel<T, TT, NT>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr_bytes = lds;
+    }
+  }
   SHOT_LAUNCH((legendre_mma_kernel<T, TT, NT>), grid, dim3(256), lds, stream, a);
   return hipGetLastError();
 }

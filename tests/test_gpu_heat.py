@@ -106,10 +106,13 @@ def test_multi_grid_items_land_at_their_offsets():
     assert off == out.size
 
 
-def test_heat_apply_climate_grid_fp32():
+@pytest.mark.parametrize("legendre", ["recurrence", "table"])
+def test_heat_apply_climate_grid_fp32(legendre):
+    """Full size, one item: the recurrence kernel and (table plan) the matrix-core
+    kernel with one column tile in 99 KiB of LDS."""
     grid = ("cc", 721, 1440, 720)
-    announce(f"heat_apply full size {grid}")
-    P = _plan([grid], "fp32", "recurrence")
+    announce(f"heat_apply full size {grid} {legendre}")
+    P = _plan([grid], "fp32", legendre)
     g = O.make_grid(*grid)
     p, _ = synth.temperature_pair(synth.pair_seed(2, 0), g.x, g.w, g.nlon, K=32)
     out = to_np(P.heat_apply(to_dev(p, P.dtype), [1e-4]))
