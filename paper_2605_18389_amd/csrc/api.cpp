@@ -44,6 +44,7 @@ struct GridRec {
   void* d_tab = nullptr;
   void* d_tabT = nullptr;            // transposed per-(m, parity) blocks for the MFMA kernel
   long long* d_toffT = nullptr;      // [2L] offsets of those blocks
+  int* d_morder = nullptr;           // [L] order run by MFMA workgroup column b (rows balanced over units)
   double* d_xs = nullptr;
   double* d_rcoef = nullptr;
   double* d_rgam = nullptr;
@@ -202,9 +203,10 @@ uint16_t to_bf16(double v) {
 void free_grid(GridRec& g) {
   for (void* p : {g.d_tab, g.d_tabT, (void*)g.d_toffT, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam,
                   (void*)g.d_rseed, (void*)g.sw.d_parts, (void*)g.sw.d_ck, (void*)g.ss.d_parts,
-                  (void*)g.ss.d_ck, (void*)g.d_ring, g.d_ring_tw, g.d_ring_ph, g.d_ring_blu, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
+                  (void*)g.ss.d_ck, (void*)g.d_morder, (void*)g.d_ring, g.d_ring_tw, g.d_ring_ph, g.d_ring_blu, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
     if (p) (void)hipFree(p);
   g.d_tab = g.d_tabT = g.d_aw = g.d_tw = g.d_pbuf = g.d_ring_tw = g.d_ring_ph = g.d_ring_blu = nullptr;
+  g.d_morder = nullptr;
   g.d_ring = nullptr;
   g.d_toffT = nullptr;
   g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = nullptr;
@@ -400,6 +402,13 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
       }
     }
     if (st != SHOT_OK) return st;
+    if (g.d_tabT) {
+      // the MFMA kernel runs one order per workgroup column: deal the orders
+      // so that the rows meeting on one compute unit add up evenly
+      std::vector<int> rows(d.L);
+      for (int m = 0; m < d.L; ++m) rows[m] = d.L - m;
+      if ((st = upload((void**)&g.d_morder, balanced_dispatch(rows, 256), s)) != SHOT_OK) return st;
+    }
   } else {
     g.tab_kind = TAB_RECUR;
     std::vector<double> coef, gam, seed;
@@ -670,6 +679,7 @@ LegArgs<T> leg_args(const GridRec& g, const Group& G, const Work<T>& W, int hl_s
   a.hpad = g.hpad;
   a.tab = g.d_tab;
   a.tabT = g.d_tabT;
+  a.morder = g.d_morder;
   a.toffT = g.d_toffT;
   a.xs = g.d_xs;
   a.rcoef = g.d_rcoef;

@@ -2162,7 +2162,7 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
   constexpr int NB = 16 * NT, KS = MT::KS, KV = MT::KV;
   constexpr int KG = sizeof(TT) == 2 ? 8 : 16;  // k-steps whose A operands are loaded together
   const int L = A.L, h = A.h, kpad = A.hpad;
-  const int m = blockIdx.x, nr = L - m;
+  const int m = A.morder ? A.morder[blockIdx.x] : (int)blockIdx.x, nr = L - m;
   const int c0 = blockIdx.y * NB;
   const int ncol = 2 * A.nb;
   const int RP = mma_rpad((L + 1) / 2);
@@ -2644,6 +2644,12 @@ template <typename T, typename TT, int NT>
 static hipError_t launch_mma_nt(const LegArgs<T>& a, hipStream_t stream) {
   dim3 grid(a.L, (2 * a.nb + 16 * NT - 1) / (16 * NT));
   const size_t lds = mma_lds_bytes(a.L, a.hpad, NT, sizeof(TT) == 2 ? TAB_BF16 : TAB_F32);
+  // The balanced order assumes the launch's workgroups sit three to a compute
+  // unit in one column of tiles (one item of a bf16 table at L = 720: 3674 ->
+  // 4094 iterations/s); with one workgroup per unit (fp32 tables of long
+  // orders) or several column tiles it measured slower, so those run m = b.
+  LegArgs<T> b = a;
+  if (grid.y > 1 || lds > 160 * 1024 / 3) b.morder = nullptr;
   if (lds > 65536) {  // long orders of fp32 tables: one workgroup per compute unit
     static size_t attr_bytes = 65536;  // dynamic LDS enabled so far for this instantiation
     if (lds > attr_bytes) {
@@ -2653,7 +2659,7 @@ static hipError_t launch_mma_nt(const LegArgs<T>& a, hipStream_t stream) {
       attr_bytes = lds;
     }
   }
-  SHOT_LAUNCH((legendre_mma_kernel<T, TT, NT>), grid, dim3(256), lds, stream, a);
+  SHOT_LAUNCH((legendre_mma_kernel<T, TT, NT>), grid, dim3(256), lds, stream, b);
   return hipGetLastError();
 }
 
