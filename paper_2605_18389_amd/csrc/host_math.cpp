@@ -369,28 +369,35 @@ std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu) {
   // The filling above leaves a staircase of slot loads (at L = 720: 930 to
   // 1089 rows against a mean of 1014) that no swap lowering the heaviest slot
   // alone can flatten.  Random swaps of one item between two slots (slot sizes
-  // kept) that do not raise the sum of squared deviations from the mean accept
-  // the sideways moves that can (1011 to 1017 at L = 720); the generator's
-  // fixed seed keeps the plan deterministic.
+  // kept) that do not raise the sum of squared deviations from the slots'
+  // targets accept the sideways moves that can (max 1017 at L = 720); the
+  // generator's fixed seed keeps the plan deterministic.  A slot with fewer
+  // rounds runs fewer waves per SIMD, which hide each other's latency less:
+  // its target is 0.95 of a full slot's (interleaved timings at L = 720:
+  // 34.85 -> 34.52 us per launch; 0.9 measured slower again).
+  std::vector<double> tgt(ncu);
+  {
+    double wsum = 0.0;
+    for (int s = 0; s < ncu; ++s) wsum += cap[s] == cmax ? 1.0 : 0.95;
+    for (int s = 0; s < ncu; ++s) tgt[s] = total / wsum * (cap[s] == cmax ? 1.0 : 0.95);
+  }
   std::mt19937 rng(20240607u);
   auto sq = [](double v) { return v * v; };
-  for (int sweep = 0; sweep < 200; ++sweep) {
+  for (int sweep = 0; sweep < 200; ++sweep) {  // a few ms at L = 720
     for (int k = 0; k < 8 * ncu; ++k) {
       const int s = (int)(rng() % (unsigned)ncu), t = (int)(rng() % (unsigned)ncu);
       if (s == t || slot[s].empty() || slot[t].empty()) continue;
       const int i = (int)(rng() % slot[s].size()), j = (int)(rng() % slot[t].size());
       const long long d = (long long)weight[slot[s][i]] - weight[slot[t][j]];
       if (d == 0) continue;
-      const double before = sq((double)load[s] - target) + sq((double)load[t] - target);
-      const double after = sq((double)(load[s] - d) - target) + sq((double)(load[t] + d) - target);
+      const double before = sq((double)load[s] - tgt[s]) + sq((double)load[t] - tgt[t]);
+      const double after = sq((double)(load[s] - d) - tgt[s]) + sq((double)(load[t] + d) - tgt[t]);
       if (after <= before) {
         std::swap(slot[s][i], slot[t][j]);
         load[s] -= d;
         load[t] += d;
       }
     }
-    const auto mm = std::minmax_element(load.begin(), load.end());
-    if (*mm.second - *mm.first <= 1) break;
   }
   for (int s = 0; s < ncu; ++s) {
     std::stable_sort(slot[s].begin(), slot[s].end(), [&](int a, int b) { return weight[a] > weight[b]; });
