@@ -1806,11 +1806,6 @@ __global__ void __launch_bounds__(256) legendre_recur_kernel(LegArgs<T> A) {
 // part order, which keeps the result independent of timing.
 // ---------------------------------------------------------------------------
 
-// Wave issue priority from the blocks of rows a wave still has to run (both
-// passes): the three waves sharing a SIMD come from different orders, and
-// running the one with the most work left first makes them finish together
-// instead of leaving one long wave alone on the SIMD at the end.  Thresholds
-// from interleaved timings at L = 720 (priorities off 41.4 us, these 39.5).
 // A copy of a lane-varying index that the compiler cannot see through: the
 // addresses derived from it are recomputed where they are used instead of
 // being shared with (and kept live across the loops until) a later use of the
@@ -1820,9 +1815,15 @@ __device__ __forceinline__ int opaque_index(int x) {
   return x;
 }
 
+// Wave issue priority from the blocks of rows a wave still has to run (both
+// passes): the three waves sharing a SIMD come from different orders, and
+// running the one with the most work left first makes them finish together
+// instead of leaving one long wave alone on the SIMD at the end.  Thresholds
+// from interleaved timings at L = 720 (priorities off 41.4 us, on 39.5; with
+// the current dispatch packing 12/6/2 beats 14/7/2, 10/5/2 and 16/8/3).
 __device__ __forceinline__ void prio_by_blocks(int left) {
-  if (left >= 14) __builtin_amdgcn_s_setprio(3);
-  else if (left >= 7) __builtin_amdgcn_s_setprio(2);
+  if (left >= 12) __builtin_amdgcn_s_setprio(3);
+  else if (left >= 6) __builtin_amdgcn_s_setprio(2);
   else if (left >= 2) __builtin_amdgcn_s_setprio(1);
   else __builtin_amdgcn_s_setprio(0);
 }
