@@ -407,7 +407,9 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
       // so that the rows meeting on one compute unit add up evenly
       std::vector<int> rows(d.L);
       for (int m = 0; m < d.L; ++m) rows[m] = d.L - m;
-      if ((st = upload((void**)&g.d_morder, balanced_dispatch(rows, 256), s)) != SHOT_OK) return st;
+      // (streaming the table, two workgroups per unit keep up: factor 1, which
+      // measured 4048 -> 4104 iterations/s for one bf16 item against 0.95)
+      if ((st = upload((void**)&g.d_morder, balanced_dispatch(rows, 256, 1.0), s)) != SHOT_OK) return st;
     }
   } else {
     g.tab_kind = TAB_RECUR;
@@ -432,7 +434,9 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
       // travel inside the entries), so a workgroup reads its entry with one load
       // instead of an index load followed by a dependent entry load.
       std::vector<int> wts;
-      for (const auto& q : parts) wts.push_back(q.r_hi - q.r_lo);
+      // weight = rows + 32: a workgroup's fixed cost (prologue, combine, store)
+      // in rows (interleaved timings at L = 720: 10163 -> 10203 iterations/s)
+      for (const auto& q : parts) wts.push_back(q.r_hi - q.r_lo + 32);
       const std::vector<int> order = balanced_dispatch(wts, 256);
       std::vector<SplitPartH> run(parts.size());
       for (size_t b = 0; b < order.size(); ++b) run[b] = parts[order[b]];

@@ -310,7 +310,7 @@ int split_schedule(int L, int part_rows, std::vector<SplitPartH>& parts) {
   return nslot;
 }
 
-std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu) {
+std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu, double short_factor) {
   const int n = (int)weight.size();
   std::vector<int> order(n);
   for (int b = 0; b < n; ++b) order[b] = b;
@@ -373,13 +373,13 @@ std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu) {
   // targets accept the sideways moves that can (max 1017 at L = 720); the
   // generator's fixed seed keeps the plan deterministic.  A slot with fewer
   // rounds runs fewer waves per SIMD, which hide each other's latency less:
-  // its target is 0.95 of a full slot's (interleaved timings at L = 720:
-  // 34.85 -> 34.52 us per launch; 0.9 measured slower again).
+  // its target is short_factor of a full slot's (the recurrence kernel at
+  // L = 720: 0.95 gives 34.85 -> 34.52 us per launch, 0.9 is slower again).
   std::vector<double> tgt(ncu);
   {
     double wsum = 0.0;
-    for (int s = 0; s < ncu; ++s) wsum += cap[s] == cmax ? 1.0 : 0.95;
-    for (int s = 0; s < ncu; ++s) tgt[s] = total / wsum * (cap[s] == cmax ? 1.0 : 0.95);
+    for (int s = 0; s < ncu; ++s) wsum += cap[s] == cmax ? 1.0 : short_factor;
+    for (int s = 0; s < ncu; ++s) tgt[s] = total / wsum * (cap[s] == cmax ? 1.0 : short_factor);
   }
   std::mt19937 rng(20240607u);
   auto sq = [](double v) { return v * v; };

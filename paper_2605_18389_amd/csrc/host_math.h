@@ -109,10 +109,11 @@ int split_schedule(int L, int part_rows, std::vector<SplitPartH>& parts);
 // slot are nearly equal: slots with fewer rounds take the heaviest items,
 // each topped up toward the mean with the best-fitting remaining item; the
 // others are filled heaviest first onto the least loaded slot; then swaps of
-// single items between slots that do not raise the squared deviation from the
-// mean even the loads out (deterministic: fixed-seed generator); within a
-// slot the heaviest item runs in round 0.
-std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu);
+// single items between slots that do not raise the squared deviation from
+// each slot's target even the loads out (deterministic: fixed-seed generator;
+// slots with fewer rounds target short_factor of a full slot's load); within
+// a slot the heaviest item runs in round 0.
+std::vector<int> balanced_dispatch(const std::vector<int>& weight, int ncu, double short_factor = 0.95);
 
 // Recurrence checkpoints for the row-split kernel: for every part k and wave
 // w = 0..3 of its workgroup, the pair (R_{r0}, R_{r0-1}) of the rescaled
