@@ -434,9 +434,10 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
       // travel inside the entries), so a workgroup reads its entry with one load
       // instead of an index load followed by a dependent entry load.
       std::vector<int> wts;
-      // weight = rows + 32: a workgroup's fixed cost (prologue, combine, store)
-      // in rows (interleaved timings at L = 720: 10163 -> 10203 iterations/s)
-      for (const auto& q : parts) wts.push_back(q.r_hi - q.r_lo + 32);
+      // weight = rows + 64: a workgroup's fixed cost (prologue, combine, store)
+      // in rows (interleaved timings at L = 720: +0 10163, +32 10203, +64
+      // 10223 iterations/s)
+      for (const auto& q : parts) wts.push_back(q.r_hi - q.r_lo + 64);
       const std::vector<int> order = balanced_dispatch(wts, 256);
       std::vector<SplitPartH> run(parts.size());
       for (size_t b = 0; b < order.size(); ++b) run[b] = parts[order[b]];
