@@ -211,8 +211,11 @@ shot_status shot_gradient_regional_rms(shot_plan_t plan, const int32_t* grid_of_
  * per thread of the latitude-split kernel (1, 2 or 4, at most 256 threads per
  * workgroup; 0 = the row-split kernel), for SHOT_LEG_TABLE grids of float32 and
  * bfloat16 plans the matrix-core kernel's column tiles per workgroup (1, 2 or 4
- * tiles of 16 columns = 8, 16 or 32 items; 0 = automatic, matrix cores for
- * batches of 4 items and more; -1 = VALU kernel only).  SHOT_E_INVALID otherwise. */
+ * tiles of 16 columns = 8, 16 or 32 items; 0 = automatic: matrix cores for any
+ * number of items, 1 tile below 16 items, 2 from 16, 4 from 32, fewer while
+ * they overflow 60 KiB of LDS; -1 = VALU kernel only; a table whose single
+ * tile would need more than 150 KiB of LDS runs the VALU kernel).
+ * SHOT_E_INVALID otherwise. */
 shot_status shot_plan_set_tuning(shot_plan_t plan, int32_t grid, int32_t items_per_block,
                                  int32_t chains_per_thread);
 shot_status shot_plan_get_tuning(shot_plan_t plan, int32_t grid, int32_t* items_per_block,
