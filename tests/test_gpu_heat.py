@@ -135,6 +135,20 @@ def test_single_item_bf16_table_heat_apply(grid, tiles):
     assert rel_l2(out, O.heat_apply(v, g, 3e-3)) < 1e-2
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+def test_single_item_table_heat_apply_dealt_orders(prec, tol):
+    """One item on a 360x720 table plan (L = 360 > 256 orders): the matrix-core kernel
+    runs the orders in the host's balanced dealing order (three workgroups per compute
+    unit), every order exactly once."""
+    grid = ("gl", 360, 720, 360)
+    announce(f"table single item dealt orders {grid} {prec}")
+    P = _plan([grid], prec, "table")
+    g = O.make_grid(*grid)
+    v = synth.temperature_like(np.random.default_rng(10), g.x, g.w, g.nlon, K=8)
+    out = to_np(P.heat_apply(to_dev(v[None], P.dtype), [1e-3])).reshape(v.shape)
+    assert rel_l2(out, O.heat_apply(v, g, 1e-3)) < tol
+
+
 @pytest.mark.parametrize("prec,tiles,tol", [("fp32", 0, 1e-5), ("fp32", 1, 1e-5), ("fp32", 2, 1e-5),
                                             ("bf16", 0, 1e-2), ("bf16", 4, 1e-2), ("bf16", -1, 1e-2)])
 @pytest.mark.parametrize("grid", [("gl", 90, 180, 90), ("cc", 33, 64, 32), ("gl", 17, 36, 18)])
