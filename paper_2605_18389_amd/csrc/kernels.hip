@@ -2156,11 +2156,16 @@ struct MmaTraits<float> {
   __device__ static void load_a(float* dst, const float* src, bool ok) { *dst = ok ? *src : 0.0f; }
 };
 
-template <typename T, typename TT, int NT>
+template <typename T, typename TT, int NT, bool NARROW>
 __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using MT = MmaTraits<TT>;
   constexpr int NB = 16 * NT, KS = MT::KS, KV = MT::KV;
+  // B-operand rows kept in LDS per parity: the tile's NB columns, or, for a
+  // single item (NARROW), its two columns and one zero row that the other 14
+  // lanes of a k-slice all read (a broadcast): 3 rows instead of 16
+  constexpr int NS = NARROW ? 3 : NB;
+  auto srow = [](int n) { return NARROW ? (n < 2 ? n : 2) : n; };
   constexpr int KG = sizeof(TT) == 2 ? 8 : 16;  // k-steps whose A operands are loaded together
   const int L = A.L, h = A.h, kpad = A.hpad;
   const int m = A.morder ? A.morder[blockIdx.x] : (int)blockIdx.x, nr = L - m;
@@ -2168,8 +2173,8 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
   const int ncol = 2 * A.nb;
   const int RP = mma_rpad((L + 1) / 2);
   const int ys_ld = kpad + MT::PAD, bs_ld = RP + MT::PAD;
-  TT* ys = reinterpret_cast<TT*>(smem_raw);                // [2][NB][ys_ld]
-  TT* bs = ys + (size_t)2 * NB * ys_ld;                    // [2][NB][bs_ld]
+  TT* ys = reinterpret_cast<TT*>(smem_raw);                // [2][NS][ys_ld]
+  TT* bs = ys + (size_t)2 * NS * ys_ld;                    // [2][NS][bs_ld]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const long long toff = tri_off(m, L);
@@ -2177,12 +2182,12 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
 
   // stage Y (zero beyond h and beyond the last column) and clear b: one
   // (parity, column) row per wave at a time, latitudes across the lanes
-  for (int pn = wave; pn < 2 * NB; pn += 4) {
-    const int par = pn / NB, n = pn - par * NB;
-    const int col = c0 + n;
+  for (int pn = wave; pn < 2 * NS; pn += 4) {
+    const int par = pn / NS, n = pn - par * NS;
+    const int col = c0 + n;  // (the zero row of a NARROW tile: col = 2 >= ncol)
     const bool cok = A.mode != 2 && col < ncol;
     const cpx<T>* sp = A.spec + (cok ? A.items[A.item0 + (col >> 1)].soff : 0) + (size_t)m * h * 2 + par;
-    TT* dst = ys + ((size_t)par * NB + n) * ys_ld;
+    TT* dst = ys + ((size_t)par * NS + n) * ys_ld;
     for (int j = lane; j < kpad; j += 64) {
       float v = 0.f;
       if (cok && j < h) {
@@ -2192,7 +2197,7 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
       dst[j] = MT::cvt(v);
     }
   }
-  for (int idx = tid; idx < 2 * NB * bs_ld; idx += 256) bs[idx] = MT::cvt(0.f);
+  for (int idx = tid; idx < 2 * NS * bs_ld; idx += 256) bs[idx] = MT::cvt(0.f);
   __syncthreads();
 
   if (A.mode != 2) {
@@ -2218,7 +2223,7 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
             if (kg + s * KS >= kpad) break;
 #pragma unroll
             for (int c = 0; c < NT; ++c) {
-              const TT* bp = ys + ((size_t)par * NB + c * 16 + li) * ys_ld + kg + s * KS + lg * KV;
+              const TT* bp = ys + ((size_t)par * NS + srow(c * 16 + li)) * ys_ld + kg + s * KS + lg * KV;
               acc[c] = MT::mma(a[s], bp, acc[c]);
             }
           }
@@ -2233,7 +2238,7 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
               const int item = A.item0 + (col >> 1);
               if (A.mode == 0) {
                 const float hv = (float)A.hl[(size_t)item * A.hl_stride + m + ro];
-                bs[((size_t)par * NB + n) * bs_ld + rpo] = MT::cvt(acc[c][i] * hv);
+                bs[((size_t)par * NS + n) * bs_ld + rpo] = MT::cvt(acc[c][i] * hv);  // n < ncol <= NS
               } else {
                 T* dst = reinterpret_cast<T*>(&A.coeff[A.items[item].coff + toff + ro]);
                 dst[col & 1] = (T)acc[c][i];
@@ -2249,7 +2254,7 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
       const int n = idx / nr, r = idx % nr, col = c0 + n;
       if (col >= ncol) continue;
       const cpx<T> c = A.coeff[A.items[A.item0 + (col >> 1)].coff + toff + r];
-      bs[((size_t)(r & 1) * NB + n) * bs_ld + (r >> 1)] = MT::cvt((float)((col & 1) ? c.y : c.x));
+      bs[((size_t)(r & 1) * NS + n) * bs_ld + (r >> 1)] = MT::cvt((float)((col & 1) ? c.y : c.x));
     }
   }
   __syncthreads();
@@ -2273,7 +2278,7 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
         if (kg + s * KS >= rpad) break;
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-          const TT* bp = bs + ((size_t)par * NB + c * 16 + li) * bs_ld + kg + s * KS + lg * KV;
+          const TT* bp = bs + ((size_t)par * NS + srow(c * 16 + li)) * bs_ld + kg + s * KS + lg * KV;
           acc[c] = MT::mma(a[s], bp, acc[c]);
         }
       }
@@ -2634,17 +2639,17 @@ hipError_t launch_legendre_split(const LegArgs<T>& a, int ib, hipStream_t stream
 template hipError_t launch_legendre_split<float>(const LegArgs<float>&, int, hipStream_t);
 template hipError_t launch_legendre_split<double>(const LegArgs<double>&, int, hipStream_t);
 
-size_t mma_lds_bytes(int L, int hpad, int nt, int table_kind) {
+size_t mma_lds_bytes(int L, int hpad, int nt, int table_kind, bool narrow) {
   const size_t es = table_kind == TAB_BF16 ? 2 : 4;
   const size_t pad = table_kind == TAB_BF16 ? 8 : 1;
-  const size_t NB = 16 * nt, RP = mma_rpad((L + 1) / 2);
+  const size_t NB = narrow ? 3 : 16 * nt, RP = mma_rpad((L + 1) / 2);
   return es * 2 * NB * ((size_t)hpad + pad) + es * 2 * NB * (RP + pad);
 }
 
-template <typename T, typename TT, int NT>
+template <typename T, typename TT, int NT, bool NARROW>
 static hipError_t launch_mma_nt(const LegArgs<T>& a, hipStream_t stream) {
   dim3 grid(a.L, (2 * a.nb + 16 * NT - 1) / (16 * NT));
-  const size_t lds = mma_lds_bytes(a.L, a.hpad, NT, sizeof(TT) == 2 ? TAB_BF16 : TAB_F32);
+  const size_t lds = mma_lds_bytes(a.L, a.hpad, NT, sizeof(TT) == 2 ? TAB_BF16 : TAB_F32, NARROW);
   // The balanced order assumes the launch's workgroups sit three to a compute
   // unit in one column of tiles (one item of a bf16 table at L = 720: 3674 ->
   // 4094 iterations/s); with one workgroup per unit (fp32 tables of long
@@ -2654,22 +2659,23 @@ static hipError_t launch_mma_nt(const LegArgs<T>& a, hipStream_t stream) {
   if (lds > 65536) {  // long orders of fp32 tables: one workgroup per compute unit
     static size_t attr_bytes = 65536;  // dynamic LDS enabled so far for this instantiation
     if (lds > attr_bytes) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&legendre_mma_kernel<T, TT, NT>),
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&legendre_mma_kernel<T, TT, NT, NARROW>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       attr_bytes = lds;
     }
   }
-  SHOT_LAUNCH((legendre_mma_kernel<T, TT, NT>), grid, dim3(256), lds, stream, b);
+  SHOT_LAUNCH((legendre_mma_kernel<T, TT, NT, NARROW>), grid, dim3(256), lds, stream, b);
   return hipGetLastError();
 }
 
 template <typename T, typename TT>
 static hipError_t launch_mma_tt(const LegArgs<T>& a, int nt, hipStream_t stream) {
   switch (nt) {
-    case 1: return launch_mma_nt<T, TT, 1>(a, stream);
-    case 2: return launch_mma_nt<T, TT, 2>(a, stream);
-    default: return launch_mma_nt<T, TT, 4>(a, stream);
+    case 1:  // one item: its two columns only
+      return a.nb == 1 ? launch_mma_nt<T, TT, 1, true>(a, stream) : launch_mma_nt<T, TT, 1, false>(a, stream);
+    case 2: return launch_mma_nt<T, TT, 2, false>(a, stream);
+    default: return launch_mma_nt<T, TT, 4, false>(a, stream);
   }
 }
 

@@ -177,7 +177,7 @@ hipError_t launch_legendre_split(const LegArgs<T>& a, int ib, hipStream_t stream
 // Batched MFMA Legendre GEMM (table plans): nt column tiles of 16 per workgroup.
 template <typename T>
 hipError_t launch_legendre_mma(const LegArgs<T>& a, int table_kind, int nt, hipStream_t stream);
-size_t mma_lds_bytes(int L, int hpad, int nt, int table_kind);
+size_t mma_lds_bytes(int L, int hpad, int nt, int table_kind, bool narrow = false);
 
 template <typename T>
 hipError_t launch_reduce(const RowArgs<T>& a, int nb, int nchk_done, double* res, double* ehist,
