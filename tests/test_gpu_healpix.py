@@ -216,3 +216,27 @@ def test_bluestein_rings_match_oracle(prec, tol):
     outT = to_np(P.heat_apply(to_dev(v, P.dtype), t, transpose=True)).reshape(v.shape)
     refT = np.stack([O.heat_apply(v[i][None], g, t[i], transpose=True)[0] for i in range(2)])
     assert rel_l2(outT, refT) < tol
+
+
+_HP256 = {}
+
+
+def _hp256_reference():
+    """Oracle heat apply (direct ring sums) of the Nside 256 workload's first field, once."""
+    if not _HP256:
+        g = O.HealpixGrid(256, 512)
+        p, _ = synth.uniform_pair_at(synth.pair_seed(7, 256), g.area[0])
+        _HP256.update(g=g, p=p, ref=O.heat_apply(p[None], g, 0.025)[0])
+    return _HP256["g"], _HP256["p"], _HP256["ref"]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_nside256_full_size_heat_apply(prec, tol):
+    """The HEALPix workload of the throughput measurement at full size: Nside 256
+    (786 432 pixels, 1023 rings, polar rings through the Bluestein transform), L = 512,
+    t = eps / 4 = 0.025, one heat apply of its first field against the oracle."""
+    announce(f"healpix nside=256 full size {prec}")
+    g, p, ref = _hp256_reference()
+    P = _plan([("hp", 256, 512)], prec)
+    out = to_np(P.heat_apply(to_dev(p[None], P.dtype), [0.025])).reshape(ref.shape)
+    assert rel_l2(out, ref) < tol, rel_l2(out, ref)
