@@ -106,18 +106,19 @@ def test_multi_grid_items_land_at_their_offsets():
     assert off == out.size
 
 
-@pytest.mark.parametrize("legendre", ["recurrence", "table"])
-def test_heat_apply_climate_grid_fp32(legendre):
-    """Full size, one item: the recurrence kernel and (table plan) the matrix-core
-    kernel with one column tile in 99 KiB of LDS."""
+@pytest.mark.parametrize("prec,legendre,tol", [("fp32", "recurrence", 1e-5), ("fp32", "table", 1e-5),
+                                                ("bf16", "table", 1e-2)])
+def test_heat_apply_climate_grid(prec, legendre, tol):
+    """Full size, one item: the recurrence kernel and (table plans) the matrix-core
+    kernel with a single item's two columns, fp32 and bf16 operands."""
     grid = ("cc", 721, 1440, 720)
-    announce(f"heat_apply full size {grid} {legendre}")
-    P = _plan([grid], "fp32", legendre)
+    announce(f"heat_apply full size {grid} {prec} {legendre}")
+    P = _plan([grid], prec, legendre)
     g = O.make_grid(*grid)
     p, _ = synth.temperature_pair(synth.pair_seed(2, 0), g.x, g.w, g.nlon, K=32)
     out = to_np(P.heat_apply(to_dev(p, P.dtype), [1e-4]))
     ref = O.heat_apply(p, g, 1e-4)
-    assert rel_l2(out.reshape(ref.shape), ref) < 1e-5
+    assert rel_l2(out.reshape(ref.shape), ref) < tol
 
 
 @pytest.mark.parametrize("tiles", [0, -1])

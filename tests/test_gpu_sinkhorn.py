@@ -218,6 +218,27 @@ def test_climate_grid_solve_matches_oracle_fp32():
     assert abs(info[0]["err"] - r["err"]) <= tol * max(r["err"], 1.0)
 
 
+def test_climate_grid_unbalanced_solve_matches_oracle_fp32():
+    """The unbalanced solve (tau = 1, masses 1 vs 1.05) on the 0.25-degree grid in the
+    same launch configuration, 12 iterations, graded against the oracle."""
+    announce("climate grid 721x1440 fp32 unbalanced T=12")
+    g = O.make_grid(*CLIMATE)
+    p, q = synth.temperature_pair(synth.pair_seed(2, 0), g.x, g.w, g.nlon, K=32, q_mass=1.05)
+    eps, tau = 4 * T_CLIMATE, 1.0
+    P = _plan([CLIMATE], "fp32", "recurrence")
+    phi, psi, info = P.sinkhorn(to_dev(p, P.dtype), to_dev(q, P.dtype), eps, tau, T=12, C=10)
+    r = O.sinkhorn(p, q, g, eps, tau, T=12, C=10)
+    graded = check_status(info[0], r, "fp32")
+    tol = tolerance(r, "fp32")
+    report("climate unbalanced T=12", graded=graded, kratio=r["kratio"], cost=info[0]["cost"],
+           cost_ref=r["cost"], tol=tol)
+    assert graded
+    assert abs(info[0]["cost"] - r["cost"]) <= tol * abs(r["cost"])
+    for got, ref in ((phi, r["phi"]), (psi, r["psi"])):
+        d = np.abs(to_np(got).reshape(ref.shape).astype(np.float64) - ref) / eps
+        assert np.sqrt(np.mean(d * d)) < tol, np.sqrt(np.mean(d * d))
+
+
 def test_climate_grid_full_solve_fp32():
     """The full 1000-iteration solve as timed (graph replay).  At t = 1e-4 the smallest
     heat-kernel output of this pair falls by about 0.6x per iteration relative to the
