@@ -239,6 +239,40 @@ def test_climate_grid_unbalanced_solve_matches_oracle_fp32():
         assert np.sqrt(np.mean(d * d)) < tol, np.sqrt(np.mean(d * d))
 
 
+def test_climate_grid_divergence_and_envelope_gradient_fp32():
+    """Def. 2.3 on the 0.25-degree pair (three solves advanced together, two items per
+    Legendre workgroup), 12 iterations, and its envelope gradient (Sec. 4.2.2) against the
+    oracle.  S is a small difference of large costs, so its bound is the sum of the three
+    costs' tolerances; the gradient divided by the area weights is compared after
+    removing its mean (potentials are defined up to a constant), in units of eps like
+    the potentials."""
+    announce("climate grid 721x1440 fp32 divergence T=12")
+    g, p, q = _climate_pair()
+    eps = 4 * T_CLIMATE
+    P = _plan([CLIMATE], "fp32", "recurrence")
+    pd, qd = to_dev(p, P.dtype), to_dev(q, P.dtype)
+    S, info = P.divergence(pd, qd, eps, T=12, C=10)
+    Sref, solves = O.divergence(p, q, g, eps, T=12, return_solves=True)
+    graded = [check_status(inf, r, "fp32") for inf, r in zip(info, solves)]
+    tols = [tolerance(r, "fp32") for r in solves]
+    report("climate divergence T=12", S=S[0], S_ref=Sref, graded=str(graded))
+    assert all(graded)
+    for inf, r, tol in zip(info, solves, tols):
+        assert abs(inf["cost"] - r["cost"]) <= tol * abs(r["cost"])
+    bound = sum(w * tol * abs(r["cost"]) for w, tol, r in zip((1.0, 0.5, 0.5), tols, solves))
+    assert abs(S[0] - Sref) <= bound, (S[0], Sref, bound)
+    _, G, _ = P.divergence_grad(pd, qd, eps, T=12, C=10, mode="envelope")
+    mass = O.sinkhorn.__globals__["mass"]
+    ref = O.envelope_gradient(solves[0], solves[1], g, eps, mass(p, g), mass(q, g))
+    a = g.area
+    cg = to_np(G).reshape(p.shape).astype(np.float64) / a
+    cr = ref / a
+    cg -= (a * cg).sum() / a.sum()
+    cr -= (a * cr).sum() / a.sum()
+    d = (cg - cr) / eps
+    assert np.sqrt(np.mean(d * d)) < 3 * max(tols), np.sqrt(np.mean(d * d))
+
+
 def test_climate_grid_full_solve_fp32():
     """The full 1000-iteration solve as timed (graph replay).  At t = 1e-4 the smallest
     heat-kernel output of this pair falls by about 0.6x per iteration relative to the
