@@ -690,7 +690,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
   // contiguous range of groups so that neighbouring rows' spectral entries
   // (adjacent in memory) meet in the same L2.
   const int ngroups = (h + RPW - 1) / RPW;
-  const int jp0 = xcd_row_pair(blockIdx.x, ngroups) * RPW;
+  const int jp0 = (A.rpair ? A.rpair[blockIdx.x] : xcd_row_pair(blockIdx.x, ngroups)) * RPW;
   // HEALPix: this pair's rings (one pair per group), else uniform rows
   const RingDev* RG = A.ring ? A.ring + jp0 : nullptr;
   const int N = RG ? RG->len : (NC > 0 ? NC : A.nlon);

@@ -79,6 +79,7 @@ struct RowArgs {
   const T* aw;        // h area weights (rows 0..h-1)
   int item0;          // absolute index of this launch's first item
   const ItemDev* items;
+  const int* rpair;   // ring grids: ring pair run by workgroup column b (nullptr: xcd_row_pair order)
   cpx<T>* spec;
   int mode;
   int k;              // iteration number (1-based) for SINK / CHECK / FINAL modes
