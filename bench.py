@@ -355,8 +355,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is "
-                                   "described in DESIGN.md but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding the path "
+                                   "over several GPUs is designed but not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
     if args.traffic_probe:

@@ -28,8 +28,9 @@ Everything is float64 NumPy, written step by step from the paper:
                     convolution on S^2): C(eps), the dense geodesic-Gaussian
                     convolution, the rescaled mean absolute error.
 
-Readings where the paper is silent or inconsistent are listed in the design doc
-(heat time t = eps/4 everywhere, l < L, Alg. 1 taken literally, ...).
+Where the paper is silent or inconsistent, each module's docstring states the
+reading it takes (heat time t = eps/4 everywhere, band limit l < L, Alg. 1
+taken literally, ...).
 """
 
 from .grids import Grid, gauss_legendre, gauss_lobatto, clenshaw_curtis, make_grid
