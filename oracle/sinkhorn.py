@@ -1,23 +1,34 @@
-"""Algorithm 1 (spherical-harmonic Sinkhorn), divergence and gradients (oracle; test infrastructure only).
+"""Spherical-harmonic Sinkhorn (Alg. 1), the divergence and its gradients (oracle; test infrastructure only).
 
-Steps are taken literally from Alg. 1 ("Spherical Harmonic Sinkhorn", App. C):
-  t = eps/4, h_l = exp(-t l(l+1)), u = v = 1, then for k = 1..T
-  balanced (tau = inf):  u = p / K v ; v = q / K u ; s = sum_i u_i ; u = u/s ; v = s v
-  unbalanced:            u = (p / K v)^(tau/(tau+eps)) ; v = (q / K u)^(tau/(tau+eps))
-                         c = tau/2 (log sum_i a_i p_i u_i^(-eps/tau) - log sum_i a_i q_i v_i^(-eps/tau))
-                         u = e^(c/eps) u ; v = e^(-c/eps) v
-  every C iterations:    e_marg = ||u (.) K v - p||_2 / ||p||_2  (App. C.3), stop if < delta
-  then phi = eps log u, psi = eps log v and the returned cost is
-  balanced   sum_i a_i (phi_i p_i + psi_i q_i)
-  unbalanced sum_i a_i (tau (1 - e^(-phi_i/tau)) p_i + tau (1 - e^(-psi_i/tau)) q_i)   (App. C.2).
-K is HeatConv (Sec. 3.2).  The divergence is Def. 2.3 (eq. sinkhorn-divergence):
-  S = OT(p,q) - (OT(p,p) + OT(q,q))/2 + eps/2 (m(p) - m(q))^2,  m(p) = sum_i a_i p_i.
-The envelope gradient follows Sec. 4.2.2 (gradient from the Kantorovich potentials).
+What this module computes, in plain terms:
+
+* ``sinkhorn`` runs the scaling iteration of Alg. 1 on a grid whose heat
+  operator K is HeatConv (Sec. 3.2) at heat time t = eps/4.  The two scalings
+  start at one and are refreshed alternately by dividing a marginal by K of the
+  other scaling.  In the balanced branch (tau = inf) the pair is then
+  re-gauged by the plain sum of u (a gauge only).  In the unbalanced branch
+  each quotient is raised to the power tau/(tau+eps) and the pair is
+  re-gauged by the translation of App. C.2, which balances the two
+  area-weighted sums of p u^(-eps/tau) and q v^(-eps/tau).  Every C
+  iterations the relative marginal error of App. C.3 is evaluated (and, with
+  a threshold delta > 0, the loop stops early).  The potentials are eps times
+  the logarithms of the final scalings; the returned cost is the area-weighted
+  sum of App. C.2 (plain potentials for the balanced branch, the
+  tau-saturated form for the unbalanced one).
+* ``divergence`` combines three such runs with identical parameters into the
+  debiased quantity of Def. 2.3, including its mass-difference term.
+* ``envelope_gradient`` is the potential-based gradient of Sec. 4.2.2;
+  ``fd_directional`` differentiates the whole fixed-T computation numerically.
 
 Arrays may carry leading batch dimensions (..., nlat, nlon); every sum is over
 the last two axes.  The positivity breakdown of App. C.4 (a truncated kernel
 that goes non-positive) is recorded as the first iteration k at which K v or
 K u has an entry <= 0 or non-finite; the iteration then simply continues.
+
+Parity unpinned: the coefficient eps/2 of the mass-difference term of
+Def. 2.3.  On constant densities every other part of the unbalanced branch
+has a closed-form fixed point that the tests check, but positivity (Prop. 3.2)
+does not constrain that coefficient there, so the tests can only restate it.
 """
 
 import math

@@ -23,6 +23,7 @@
 // Reductions are per-workgroup float64 partial sums written to fixed slots and
 // summed later in a fixed order, so results are deterministic (no float atomics).
 
+#include <cfloat>
 #include <climits>
 
 #include <hip/hip_ext.h>
@@ -1342,6 +1343,10 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
       const T r0 = __builtin_amdgcn_rcpf(kv);
       const T r1 = fmaf(fmaf(-kv, r0, (T)1), r0, r0);
       T x = f * r1;
+      // below the smallest normal float the hardware reciprocal returns inf
+      // and the Newton step NaN, where the quotient itself is large but
+      // finite: take the IEEE divide there (a branch no lane takes is skipped)
+      if (!(kv >= FLT_MIN)) x = f / kv;
       if (!I.balanced) {
         x = pow(x, (T)I.lam);
         acc += (double)aj * (double)f * pow((double)x, -I.eot);

@@ -198,3 +198,123 @@ def test_batched_matches_single():
     rb = O.sinkhorn(P, Q, g, 0.1, T=20)
     r0 = O.sinkhorn(p, q, g, 0.1, T=20)
     np.testing.assert_allclose(rb["cost"][0], r0["cost"], rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Marginal error, kernel ratio and the unbalanced branch against quantities
+# computed without the oracle's own iteration bookkeeping.
+# ---------------------------------------------------------------------------
+def _dense_H(g, eps):
+    K = O.dense_heat_matrix(g, eps / 4)          # (K v)_i = sum_j H_ij a_j v_j
+    a = g.area.ravel()
+    return K / a[None, :], a
+
+
+@pytest.mark.parametrize("tau,T", [(math.inf, 10), (math.inf, 7), (1.0, 10)])
+def test_emarg_is_the_dense_plan_marginal_error(tau, T):
+    """App. C.2-C.3: with scalings u, v the plan has density pi_ij = u_i H_ij v_j
+    with respect to a (x) a (H the dense radial kernel of Prop. 3.4), so its first
+    marginal density is sum_j pi_ij a_j.  e_marg is the relative L2 distance of
+    that marginal to p; the oracle's report at iteration k (history) and at the
+    end must equal it for the scalings of that iteration."""
+    g, p, q = _small_pair(qmass=1.0 if math.isinf(tau) else 1.05)
+    eps = 0.2
+    H, a = _dense_H(g, eps)
+
+    def dense_err(r):
+        pi = r["u"].ravel()[:, None] * H * r["v"].ravel()[None, :]
+        marg = pi @ a
+        return np.linalg.norm(marg - p.ravel()) / np.linalg.norm(p.ravel())
+
+    r = O.sinkhorn(p, q, g, eps, tau, T=T, C=5)
+    e = dense_err(r)
+    assert e > 1e-8                       # not at the rounding floor: the comparison has teeth
+    assert abs(r["err"] - e) <= 1e-10 * e
+    r5 = O.sinkhorn(p, q, g, eps, tau, T=5, C=5)
+    assert r["e_hist"][0][0] == 5
+    assert abs(r["e_hist"][0][1] - dense_err(r5)) <= 1e-10 * dense_err(r5)
+    if T % 5 == 0:
+        assert r["e_hist"][-1][1] == r["err"]
+
+
+def test_kernel_ratio_history_is_min_over_dense_outputs():
+    """kratio_hist[k-1] is the smaller of min(K v)/max(K v) and min(K u)/max(K u)
+    of iteration k (App. C.4's positivity margin), here with K applied as the
+    dense matrix to scalings carried along by plain NumPy; kratio is the
+    minimum of the history."""
+    g, p, q = _small_pair()
+    eps = 0.2
+    H, a = _dense_H(g, eps)
+    K = H * a[None, :]
+    T = 4
+    r = O.sinkhorn(p, q, g, eps, T=T)
+    pp, qq = p.ravel(), q.ravel()
+    v = np.ones_like(pp)
+    hist = []
+    for _ in range(T):
+        Kv = K @ v
+        u = pp / Kv
+        Ku = K @ u
+        v = qq / Ku
+        s = u.sum()
+        v = v * s
+        hist.append(min(Kv.min() / Kv.max(), Ku.min() / Ku.max()))
+    np.testing.assert_allclose(np.array(r["kratio_hist"], dtype=float), hist, rtol=1e-12)
+    assert r["kratio"] == min(r["kratio_hist"])
+
+
+def test_kernel_ratio_crosses_zero_at_the_breakdown_iteration():
+    """On the literal 32x64 vMF case the first iteration whose ratio is <= 0 (or
+    -inf) is exactly the reported breakdown iteration."""
+    for seed in range(3):
+        g, p, q, eps = _c1(seed)
+        r = O.sinkhorn(p, q, g, eps, T=8)
+        kb = int(r["breakdown"])
+        hist = np.array(r["kratio_hist"], dtype=float)
+        assert kb >= 1
+        assert np.all(hist[:kb - 1] > 0) and hist[kb - 1] <= 0
+
+
+def _constant_fixed_point(alpha, beta, eps, tau):
+    """Alg. 1's unbalanced branch on constant densities alpha/(4 pi), beta/(4 pi).
+
+    K maps a constant to itself (h_0 = 1; the quadrature integrates constants
+    exactly), so all iterates are constants.  In logarithms x = log u, y = log v,
+    with lam = tau/(tau+eps), eta = eps/tau, A = log(alpha/4pi), B = log(beta/4pi):
+    the updates give x^ = lam (A - y), y^ = lam (B - x^); the translation
+    c = tau/2 (log(alpha e^{-eta x^}) - log(beta e^{-eta y^})) then sets
+    x - y = log(alpha/beta)/eta =: D and leaves x + y = x^ + y^ =: s.  Hence
+    s_new = lam (1-lam) (A - (s_old - D)/2) + lam B, a contraction with factor
+    lam (1-lam)/2 <= 1/8 whose fixed point is
+    s* = (lam (1-lam) (A + D/2) + lam B) / (1 + lam (1-lam)/2).
+    Returns the cost tau (1 - e^{-eta x*}) alpha + tau (1 - e^{-eta y*}) beta and x*, y*."""
+    lam, eta = tau / (tau + eps), eps / tau
+    A, B = math.log(alpha / (4 * math.pi)), math.log(beta / (4 * math.pi))
+    D = math.log(alpha / beta) / eta
+    s = (lam * (1 - lam) * (A + D / 2) + lam * B) / (1 + lam * (1 - lam) / 2)
+    x, y = (s + D) / 2, (s - D) / 2
+    return tau * (1 - math.exp(-eta * x)) * alpha + tau * (1 - math.exp(-eta * y)) * beta, x, y
+
+
+@pytest.mark.parametrize("eps,tau", [(0.1, 0.1), (0.1, 1.0), (0.4, 10.0), (0.2, 5.0)])
+def test_unbalanced_branch_on_constant_densities_closed_form(eps, tau):
+    """The unbalanced exponent, gauge translation, potentials and returned cost
+    (Alg. 1, App. C.2) against the closed-form fixed point of the constant case.
+    The mass term of Def. 2.3 is retyped here from its definition; positivity
+    does not constrain its coefficient (the bracket alone is already positive
+    for constants), so that coefficient stays parity-unpinned."""
+    g = O.make_grid("gl", 8, 16, 8)
+    ones = np.ones(g.field_shape)
+    for alpha, beta in ((1.0, 1.05), (0.7, 1.3), (1.2, 1.2)):
+        p, q = ones * alpha / (4 * math.pi), ones * beta / (4 * math.pi)
+        r = O.sinkhorn(p, q, g, eps, tau, T=60)
+        R, x, y = _constant_fixed_point(alpha, beta, eps, tau)
+        np.testing.assert_allclose(r["phi"], eps * x, rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(r["psi"], eps * y, rtol=1e-11, atol=1e-13)
+        assert abs(r["cost"] - R) <= 1e-11 * abs(R)
+    S = O.divergence(ones * 0.7 / (4 * math.pi), ones * 1.3 / (4 * math.pi), g, eps, tau, T=60)
+    R_ab = _constant_fixed_point(0.7, 1.3, eps, tau)[0]
+    R_aa = _constant_fixed_point(0.7, 0.7, eps, tau)[0]
+    R_bb = _constant_fixed_point(1.3, 1.3, eps, tau)[0]
+    expect = R_ab - 0.5 * (R_aa + R_bb) + 0.5 * eps * (0.7 - 1.3) ** 2
+    assert abs(S - expect) <= 1e-10 * abs(expect)
