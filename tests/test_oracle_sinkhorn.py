@@ -318,3 +318,25 @@ def test_unbalanced_branch_on_constant_densities_closed_form(eps, tau):
     R_bb = _constant_fixed_point(1.3, 1.3, eps, tau)[0]
     expect = R_ab - 0.5 * (R_aa + R_bb) + 0.5 * eps * (0.7 - 1.3) ** 2
     assert abs(S - expect) <= 1e-10 * abs(expect)
+
+
+@pytest.mark.parametrize("eps,tau", [(0.1, 0.1), (0.4, 10.0)])
+def test_unbalanced_gauge_translation_transient_on_constants(eps, tau):
+    """The translation of App. C.2 vanishes at the fixed point, so it is pinned on
+    the first iterations: on constants it sets x - y = log(alpha/beta)/eta and
+    keeps x + y = x^ + y^ (derivation in _constant_fixed_point), which gives the
+    iterates in closed form step by step from v_0 = 1."""
+    g = O.make_grid("gl", 8, 16, 8)
+    ones = np.ones(g.field_shape)
+    alpha, beta = 0.8, 1.1
+    lam, eta = tau / (tau + eps), eps / tau
+    A, B = math.log(alpha / (4 * math.pi)), math.log(beta / (4 * math.pi))
+    D = math.log(alpha / beta) / eta
+    y = 0.0
+    for T in range(1, 4):
+        xh = lam * (A - y)
+        yh = lam * (B - xh)
+        x, y = (xh + yh + D) / 2, (xh + yh - D) / 2
+        r = O.sinkhorn(ones * alpha / (4 * math.pi), ones * beta / (4 * math.pi), g, eps, tau, T=T)
+        np.testing.assert_allclose(r["phi"], eps * x, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(r["psi"], eps * y, rtol=1e-12, atol=1e-14)
