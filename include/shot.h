@@ -135,6 +135,12 @@ shot_status shot_plan_grid(shot_plan_t plan, int32_t grid, double* x_out, double
  * NULL).  Latitude-longitude grids report nlon and 0 for every row. */
 shot_status shot_plan_ring(shot_plan_t plan, int32_t grid, int32_t* npix_out, double* phi0_out);
 
+/* Area weights of grid `grid` in field order (App. C.2: the discrete measure
+ * of point (j, k) of a latitude-longitude grid is a_{jk} = w_j * 2 pi / nlon;
+ * every HEALPix pixel has the area 4 pi / Npix).  a_out: host, one float64 per
+ * point of a field (nlat * nlon, or 12 Nside^2).  They sum to 4 pi. */
+shot_status shot_plan_area_weights(shot_plan_t plan, int32_t grid, double* a_out);
+
 /* Forward SHT (App. B: f_lm = <f, Y_lm>, evaluated by App. C.1's semi-naive
  * algorithm).  f: device, fields of the items.  coeffs: device, per item
  * L(L+1)/2 complex values (real, imag interleaved, field precision), ordered by
@@ -241,6 +247,12 @@ shot_status shot_plan_set_graphs(shot_plan_t plan, int32_t enable);
 shot_status shot_profile_enable(shot_plan_t plan, int32_t enable);
 shot_status shot_profile_read(shot_plan_t plan, int32_t kernel_class, int64_t* launches,
                               double* total_ms);
+
+/* Identifier of the sources this library was built from (a hash the build
+ * script computes over the C, HIP and header files and the compile flags;
+ * static storage).  Loaders compare it with the sources next to the library
+ * so that a stale build is refused instead of being run. */
+const char* shot_build_id(void);
 
 /* Human-readable name of a status code (static storage). */
 const char* shot_status_string(int32_t status);

@@ -44,6 +44,7 @@ EXPORTS = [
     "shot_sinkhorn_divergence_grad", "shot_profile_enable", "shot_profile_read",
     "shot_status_string", "shot_last_error", "shot_plan_set_tuning", "shot_plan_get_tuning",
     "shot_autotune", "shot_plan_set_graphs", "shot_plan_ring", "shot_gradient_regional_rms",
+    "shot_plan_area_weights", "shot_build_id",
 ]
 
 # The five latitude bands of the regional attribution (Sec. 4.2.2), degrees,
@@ -97,6 +98,14 @@ def load_library(path=None):
     # and streams (a second runtime loaded ahead of torch does not see the GPU).
     _torch()
     lib = ctypes.CDLL(path)
+    lib.shot_build_id.argtypes = []
+    lib.shot_build_id.restype = ctypes.c_char_p
+    if path == LIB_PATH:
+        from .build import source_hash
+        built, want = lib.shot_build_id().decode(), source_hash()
+        if built != want:
+            raise RuntimeError(f"libshot.so was built from other sources (build id {built}, sources {want}); "
+                               f"rebuild with `python -m paper_2605_18389_amd.build`")
     vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int32)
     sig = {
@@ -104,6 +113,7 @@ def load_library(path=None):
         "shot_plan_destroy": [vp],
         "shot_plan_grid": [vp, i32, dp, dp],
         "shot_plan_ring": [vp, i32, ip, dp],
+        "shot_plan_area_weights": [vp, i32, dp],
         "shot_gradient_regional_rms": [vp, ip, i32, vp, dp, i32, dp, vp],
         "shot_sht_analysis": [vp, ip, i32, vp, vp, vp],
         "shot_sht_synthesis": [vp, ip, i32, vp, vp, vp],
@@ -242,12 +252,13 @@ class Plan:
         return z, phi
 
     def area(self, grid=0):
+        """Area weights of the grid's points, shaped like one field ((nlat, nlon), or (Npix,))."""
         _, nlat, nlon, _ = self.grids[grid]
-        if self.is_healpix(grid):
-            n = self.field_size(grid)
-            return np.full(n, 4 * np.pi / n)
-        _, w = self.grid_nodes(grid)
-        return np.repeat((w * 2 * np.pi / nlon)[:, None], nlon, axis=1)
+        n = self.field_size(grid)
+        a = np.zeros(n)
+        _check("shot_plan_area_weights", self.lib.shot_plan_area_weights(
+            self.handle, grid, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return a if self.is_healpix(grid) else a.reshape(nlat, nlon)
 
     def field_size(self, grid):
         if self.is_healpix(grid):

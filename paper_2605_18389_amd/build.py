@@ -30,6 +30,24 @@ SOURCES = [
 ]
 
 
+HASHED = ["api.cpp", "host_math.cpp", "host_math.h", "shot_internal.h", "kernels.hip"]
+
+
+def source_hash():
+    """Hash of everything libshot.so is built from: the C/HIP sources, the
+    public header and the compile flags.  Stored in the library at build time
+    (shot_build_id) and compared by the loader, which refuses a stale build."""
+    import hashlib
+    hs = hashlib.sha256()
+    for name in HASHED:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            hs.update(name.encode() + b"\0" + f.read() + b"\0")
+    with open(os.path.join(INCLUDE, "shot.h"), "rb") as f:
+        hs.update(b"shot.h\0" + f.read() + b"\0")
+    hs.update(" ".join(COMMON[:5] + DEVICE + [ARCH]).encode())
+    return hs.hexdigest()[:24]
+
+
 def _hipcc():
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -42,9 +60,10 @@ def build(verbose=False, jobs=None):
     os.makedirs(BUILD_DIR, exist_ok=True)
     objs = []
     procs = []
+    build_id = source_hash()
     for src, is_hip in SOURCES:
         obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc] + COMMON
+        cmd = [hipcc] + COMMON + [f'-DSHOT_SOURCE_HASH="{build_id}"']
         if is_hip:
             cmd += ["-x", "hip"] + DEVICE
         cmd += ["-c", os.path.join(CSRC, src), "-o", obj]

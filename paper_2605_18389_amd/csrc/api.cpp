@@ -25,6 +25,11 @@
 
 using namespace shot;
 
+// Hash of the sources the library was built from (set by the build script).
+#ifndef SHOT_SOURCE_HASH
+#define SHOT_SOURCE_HASH "unknown"
+#endif
+
 namespace {
 
 // Work list of the row-split Legendre kernel (parts, their checkpoints).
@@ -1721,6 +1726,22 @@ shot_status shot_plan_grid(shot_plan_t P, int32_t grid, double* x_out, double* w
   if (w_out) std::copy(g.w.begin(), g.w.end(), w_out);
   return SHOT_OK;
 }
+
+shot_status shot_plan_area_weights(shot_plan_t P, int32_t grid, double* a_out) {
+  if (!P || grid < 0 || grid >= (int)P->grids.size() || !a_out) return SHOT_E_INVALID;
+  const GridRec& g = P->grids[grid];
+  if (g.hp) {
+    // every pixel of a HEALPix grid has the area 4 pi / Npix
+    std::fill(a_out, a_out + g.n(), 4.0 * M_PI / (double)g.n());
+    return SHOT_OK;
+  }
+  // latitude-longitude grids: a_{jk} = w_j * 2 pi / nlon, row-major
+  const int nlat = g.d.nlat, nlon = g.d.nlon;
+  for (int j = 0; j < nlat; ++j) std::fill(a_out + (size_t)j * nlon, a_out + (size_t)(j + 1) * nlon, g.w[j] * 2.0 * M_PI / nlon);
+  return SHOT_OK;
+}
+
+const char* shot_build_id(void) { return SHOT_SOURCE_HASH; }
 
 shot_status shot_gradient_regional_rms(shot_plan_t P, const int32_t* goi, int32_t npairs, const void* d,
                                        const double* bands, int32_t nbands, double* out, void* stream) {

@@ -61,3 +61,12 @@ def test_argument_errors_need_no_gpu(lib_path):
     assert lib.shot_sht_plan(ctypes.byref(h), bad, 1, 1, 0, None) == binding.E_UNSUPPORTED
     assert lib.shot_sht_plan(ctypes.byref(h), bad, 0, 1, 0, None) == binding.E_INVALID
     assert lib.shot_plan_destroy(None) == 0
+
+
+def test_library_was_built_from_these_sources(lib_path):
+    """The build id stored in libshot.so is the hash of the sources next to it
+    (the loader refuses a library whose id differs)."""
+    from paper_2605_18389_amd.build import source_hash
+    lib = ctypes.CDLL(lib_path)
+    lib.shot_build_id.restype = ctypes.c_char_p
+    assert lib.shot_build_id().decode() == source_hash()

@@ -45,6 +45,25 @@ def test_plan_quadrature_matches_oracle(grid):
     np.testing.assert_allclose(w, g.w, rtol=1e-12, atol=1e-17)
 
 
+@pytest.mark.parametrize("grid", GRIDS[:4] + [("cc", 721, 1440, 720)])
+def test_plan_area_weights_match_oracle(grid):
+    """Exported area weights (App. C.2) against the oracle's grid, point by point."""
+    announce(f"area weights {grid}")
+    P = _plan([grid], "fp32", "recurrence")
+    g = O.make_grid(*grid)
+    a = P.area(0)
+    assert a.shape == g.area.shape
+    np.testing.assert_allclose(a, g.area, rtol=1e-13, atol=0)
+    assert abs(a.sum() - 4 * math.pi) < 1e-12
+
+
+def test_plan_area_weights_healpix():
+    announce("area weights healpix")
+    P = _plan([("hp", 8, 16)], "fp64", "recurrence")
+    g = O.HealpixGrid(8, 16)
+    np.testing.assert_allclose(P.area(0), g.area.ravel(), rtol=1e-15, atol=0)
+
+
 @pytest.mark.parametrize("prec,legendre,tol", [("fp64", "table", 1e-12), ("fp32", "table", 1e-5),
                                                ("fp64", "recurrence", 1e-12),
                                                ("fp32", "recurrence", 1e-5)])
