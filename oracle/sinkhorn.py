@@ -136,11 +136,14 @@ def mass(p, grid):
     return _sum2(grid.area * np.asarray(p, dtype=np.float64))
 
 
-def divergence(p, q, grid, eps, tau=math.inf, T=100, K=None, return_solves=False):
-    """Sinkhorn divergence of Def. 2.3 from three Alg. 1 runs with identical parameters."""
+def divergence(p, q, grid, eps, tau=math.inf, T=100, K=None, return_solves=False, r_qq=None):
+    """Sinkhorn divergence of Def. 2.3 from three Alg. 1 runs with identical parameters.
+
+    ``r_qq``: an already computed (q, q) solve with these parameters, reused."""
     r_pq = sinkhorn(p, q, grid, eps, tau, T, K=K)
     r_pp = sinkhorn(p, p, grid, eps, tau, T, K=K)
-    r_qq = sinkhorn(q, q, grid, eps, tau, T, K=K)
+    if r_qq is None:
+        r_qq = sinkhorn(q, q, grid, eps, tau, T, K=K)
     S = (r_pq["cost"] - 0.5 * (r_pp["cost"] + r_qq["cost"])
          + 0.5 * eps * (mass(p, grid) - mass(q, grid)) ** 2)
     if return_solves:
@@ -163,6 +166,7 @@ def envelope_gradient(r_pq, r_pp, grid, eps, mp, mq):
 def fd_directional(p, q, deltas, grid, eps, T, h=1e-4, tau=math.inf):
     """Central finite differences of S(p, q) along each direction (fixed T)."""
     deltas = np.asarray(deltas, dtype=np.float64)
-    Sp = divergence(p[None] + h * deltas, q[None], grid, eps, tau, T)
-    Sm = divergence(p[None] - h * deltas, q[None], grid, eps, tau, T)
+    r_qq = sinkhorn(q, q, grid, eps, tau, T)      # does not depend on p
+    Sp = divergence(p[None] + h * deltas, q[None], grid, eps, tau, T, r_qq=r_qq)
+    Sm = divergence(p[None] - h * deltas, q[None], grid, eps, tau, T, r_qq=r_qq)
     return (Sp - Sm) / (2.0 * h)

@@ -166,3 +166,25 @@ def vmf_at(seed, z, phi, kappa=10.0):
     X = _points_at(z, phi)
     c = kappa / (2.0 * np.pi * (1.0 - math.exp(-2.0 * kappa)))
     return c * np.exp(kappa * (X @ mu - 1.0)), mu
+
+
+def mass_preserving_directions(seed, p, area, n):
+    """n perturbation directions of a density p for finite differences:
+    d = p (.) z - p <a, p (.) z> / <a, p> with z ~ N(0, 1) per point (numpy
+    PCG64 ``default_rng(seed)``, one field of normals per direction), so that
+    sum a d = 0 (the mass of p + h d stays that of p)."""
+    rng = np.random.default_rng(seed)
+    p = np.asarray(p, dtype=np.float64)
+    a = np.asarray(area, dtype=np.float64)
+    out = []
+    for _ in range(n):
+        d = p * rng.standard_normal(p.shape)
+        out.append(d - p * float((a * d).sum()) / float((a * p).sum()))
+    return np.array(out)
+
+
+def sample_indices(seed, n, count):
+    """`count` distinct flat point indices of an n-point field, sorted (PCG64
+    ``default_rng(seed)``): where full-size results are compared point by point."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=min(count, n), replace=False))
