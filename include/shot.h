@@ -162,6 +162,24 @@ shot_status shot_heat_apply(shot_plan_t plan, const int32_t* grid_of_item, int32
                             const double* t, const void* v, void* out, int32_t transpose,
                             void* stream);
 
+/* shot_heat_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, result and kernels as shot_heat_apply, but the per-call
+ * workspace (item descriptors, folded spectra, heat multipliers) lives in a
+ * fixed device array of SHOT_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends; the call allocates no device
+ * memory.  Needs a plan made on the current device (plan creation fetches the
+ * array's address).  A call whose workspace exceeds the array (about 4.2 MB per
+ * float32 item at 721 x 1440, 2 x L x ceil(nlat/2) complex values per item in
+ * general) returns SHOT_E_INVALID before any launch, with the sizes in
+ * shot_last_error().  Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (other streams or threads, any plan) race; serialise
+ * them. */
+#define SHOT_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+shot_status shot_heat_apply_noalloc(shot_plan_t plan, const int32_t* grid_of_item, int32_t nitems,
+                                    const double* t, const void* v, void* out, int32_t transpose,
+                                    void* stream);
+
 /* Alg. 1 on nitems independent items.  params: host, one per item.  p, q:
  * device marginals (densities with respect to the area weights, positive).
  * phi, psi: device outputs, eps*log(u) and eps*log(v) (either may be NULL).

@@ -44,7 +44,7 @@ EXPORTS = [
     "shot_sinkhorn_divergence_grad", "shot_profile_enable", "shot_profile_read",
     "shot_status_string", "shot_last_error", "shot_plan_set_tuning", "shot_plan_get_tuning",
     "shot_autotune", "shot_plan_set_graphs", "shot_plan_ring", "shot_gradient_regional_rms",
-    "shot_plan_area_weights", "shot_build_id",
+    "shot_plan_area_weights", "shot_build_id", "shot_heat_apply_noalloc",
 ]
 
 # The five latitude bands of the regional attribution (Sec. 4.2.2), degrees,
@@ -118,6 +118,7 @@ def load_library(path=None):
         "shot_sht_analysis": [vp, ip, i32, vp, vp, vp],
         "shot_sht_synthesis": [vp, ip, i32, vp, vp, vp],
         "shot_heat_apply": [vp, ip, i32, dp, vp, vp, i32, vp],
+        "shot_heat_apply_noalloc": [vp, ip, i32, dp, vp, vp, i32, vp],
         "shot_sinkhorn_solve": [vp, ip, i32, ctypes.POINTER(Params), vp, vp, vp, vp,
                                 ctypes.POINTER(SolveInfo), vp],
         "shot_sinkhorn_divergence": [vp, ip, i32, ctypes.POINTER(Params), vp, vp, dp,

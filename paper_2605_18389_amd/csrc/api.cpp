@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <mutex>
 #include <thread>
 #include <map>
 #include <vector>
@@ -565,8 +566,11 @@ struct Work {
   int nslot = 0;
 };
 
+// fixed_base != nullptr: carve from that device buffer of fixed_cap bytes
+// (the no-allocation entry point's scratch) instead of the plan's arena.
 template <typename T>
-shot_status carve(shot_plan_s* P, const Layout& Lo, int nitems, bool sinkhorn, int nslot, Work<T>& W) {
+shot_status carve(shot_plan_s* P, const Layout& Lo, int nitems, bool sinkhorn, int nslot, Work<T>& W,
+                  char* fixed_base = nullptr, size_t fixed_cap = 0) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   const size_t o_items = take(sizeof(ItemDev) * nitems);
@@ -588,9 +592,18 @@ shot_status carve(shot_plan_s* P, const Layout& Lo, int nitems, bool sinkhorn, i
     o_brk = take(sizeof(int) * (size_t)nitems);
     o_kr = take(sizeof(double) * (size_t)nitems);
   }
-  shot_status st = grow(P->ws, off);
-  if (st != SHOT_OK) return st;
-  char* b = static_cast<char*>(P->ws.p);
+  char* b = fixed_base;
+  if (b) {
+    if (off > fixed_cap) {
+      snprintf(g_last_error, sizeof(g_last_error),
+               "call needs %zu bytes of workspace, the no-allocation scratch holds %zu", off, fixed_cap);
+      return SHOT_E_INVALID;
+    }
+  } else {
+    shot_status st = grow(P->ws, off);
+    if (st != SHOT_OK) return st;
+    b = static_cast<char*>(P->ws.p);
+  }
   W.items = reinterpret_cast<ItemDev*>(b + o_items);
   W.spec = reinterpret_cast<cpx<T>*>(b + o_spec);
   W.hl = reinterpret_cast<T*>(b + o_hl);
@@ -849,11 +862,12 @@ shot_status run_leg(shot_plan_s* P, const GridRec& g, LegArgs<T> a, hipStream_t 
 // ---------------------------------------------------------------------------
 template <typename T>
 shot_status heat_apply_impl(shot_plan_s* P, const int32_t* goi, int nitems, const double* t,
-                            const void* v, void* out, int transpose, hipStream_t s) {
+                            const void* v, void* out, int transpose, hipStream_t s,
+                            char* fixed_base = nullptr, size_t fixed_cap = 0) {
   Layout Lo;
   ST_TRY(make_layout(P, goi, nitems, Lo));
   Work<T> W;
-  ST_TRY(carve<T>(P, Lo, nitems, false, 0, W));
+  ST_TRY(carve<T>(P, Lo, nitems, false, 0, W, fixed_base, fixed_cap));
   std::vector<double> tv(t, t + nitems);
   ST_TRY(upload_items<T>(P, Lo, goi, {}, {}, tv, {}, {}, W, s));
   for (const Group& G : Lo.groups) {
@@ -1210,6 +1224,41 @@ void combine_divergence(const shot_params* prm, int npairs, const shot_solve_inf
     const double dm = mp - mq;
     S[i] = inf[3 * i].cost - 0.5 * (inf[3 * i + 1].cost + inf[3 * i + 2].cost) + 0.5 * prm[i].eps * dm * dm;
   }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Scratch of the no-allocation heat apply.  A file-scope device array: every
+// GPU the library runs on holds its own copy until the process ends.  In host
+// code `scratch` names a host-side stand-in, not a device address, so host
+// code only ever uses the address hipGetSymbolAddress returns for the current
+// device, fetched once per device at plan creation and kept in g_scratch.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SHOT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Device `dev` must be current.
+shot_status scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return SHOT_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return SHOT_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)", __LINE__);
+  g_scratch[dev] = static_cast<char*>(ptr);
+  return SHOT_OK;
+}
+
+char* scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[dev];
 }
 
 }  // namespace
@@ -1692,6 +1741,10 @@ shot_status shot_sht_plan(shot_plan_t* out, const shot_grid_desc* grids, int32_t
     hipError_t e = hipGetDevice(&P->dev);
     if (e != hipSuccess) { delete P; return hip_fail(e, "hipGetDevice", __LINE__); }
   }
+  {
+    shot_status st = scratch_setup(P->dev);  // the device is current here
+    if (st != SHOT_OK) { delete P; return st; }
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   P->grids.resize(ngrids);
   for (int i = 0; i < ngrids; ++i) {
@@ -1789,6 +1842,20 @@ shot_status shot_heat_apply(shot_plan_t P, const int32_t* goi, int32_t nitems, c
   HIP_TRY(hipSetDevice(P->dev));
   return P->prec == SHOT_FP64 ? heat_apply_impl<double>(P, goi, nitems, t, v, out, transpose, s)
                               : heat_apply_impl<float>(P, goi, nitems, t, v, out, transpose, s);
+}
+
+shot_status shot_heat_apply_noalloc(shot_plan_t P, const int32_t* goi, int32_t nitems, const double* t,
+                                    const void* v, void* out, int32_t transpose, void* stream) {
+  if (!P || !t || !ptr_ok(v) || !ptr_ok(out) || v == out) return SHOT_E_INVALID;
+  for (int i = 0; i < nitems; ++i)
+    if (!(t[i] >= 0) || !std::isfinite(t[i])) return SHOT_E_INVALID;
+  char* base = scratch_of(P->dev);
+  if (!base) return SHOT_E_INVALID;  // no plan was ever made on this device
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(P->dev));
+  return P->prec == SHOT_FP64
+             ? heat_apply_impl<double>(P, goi, nitems, t, v, out, transpose, s, base, SHOT_NOALLOC_SCRATCH_BYTES)
+             : heat_apply_impl<float>(P, goi, nitems, t, v, out, transpose, s, base, SHOT_NOALLOC_SCRATCH_BYTES);
 }
 
 shot_status shot_sinkhorn_solve(shot_plan_t P, const int32_t* goi, int32_t nitems,

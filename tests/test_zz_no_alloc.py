@@ -1,0 +1,77 @@
+"""shot_heat_apply_noalloc (workspace in the library's fixed device array)
+against shot_heat_apply, through the C ABI.
+
+Two calls in a row on one plan, the second with a smaller input, each
+compared with shot_heat_apply on the same input (same kernels, so bit for
+bit) and with the oracle at the heat-apply bound (float64 1e-12, float32
+1e-5 relative L2).  A call whose workspace exceeds the array is refused
+before any launch.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_18389_amd import synth
+
+from helpers import announce, ensure_built, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [("cc", 721, 1440, 720), ("gl", 180, 360, 180)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    ensure_built()
+
+
+def _call(P, fn, goi, t, v, out):
+    tv = np.asarray(t, dtype=np.float64)
+    gi = (ctypes.c_int32 * len(goi))(*goi)
+    return getattr(P.lib, fn)(P.handle, gi, len(goi), tv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(out.data_ptr()), 0,
+                              ctypes.c_void_p(0))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp64", 1e-12)])
+def test_noalloc_heat_apply_matches_heat_apply(prec, tol):
+    import torch
+    from paper_2605_18389_amd import Plan
+    P = Plan(GRIDS, precision=prec, legendre="recurrence")
+    gs = [O.make_grid(*g) for g in GRIDS]
+    rng = np.random.default_rng(31)
+    calls = [([0, 1, 0], [1e-4, 1e-3, 4e-3]), ([1], [2e-3])]   # second call smaller
+    for goi, t in calls:
+        announce(f"noalloc heat apply {prec} items={goi}")
+        fields = [synth.temperature_like(rng, gs[k].x, gs[k].w, gs[k].nlon, K=8) for k in goi]
+        v = to_dev(np.concatenate([f.ravel() for f in fields]), P.dtype)
+        ref = torch.empty_like(v)
+        got = torch.full_like(v, float("nan"))
+        assert _call(P, "shot_heat_apply", goi, t, v, ref) == 0
+        assert _call(P, "shot_heat_apply_noalloc", goi, t, v, got) == 0
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
+        out = to_np(got)
+        off = 0
+        for k, tk, f in zip(goi, t, fields):
+            n = gs[k].n
+            err = rel_l2(out[off:off + n].reshape(f.shape), O.heat_apply(f, gs[k], tk))
+            print(f"  grid {k} t={tk}: rel L2 vs oracle {err:.2e} (bound {tol:.0e})", flush=True)
+            assert err < tol
+            off += n
+
+
+def test_noalloc_refuses_oversized_workspace():
+    """20 float64 items at 721 x 1440 need about 166 MB of spectra: refused before any launch."""
+    import torch
+    from paper_2605_18389_amd import Plan
+    from paper_2605_18389_amd.binding import E_INVALID
+    announce("noalloc oversize")
+    P = Plan(GRIDS[:1], precision="fp64", legendre="recurrence")
+    v = torch.ones(16, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(v)
+    assert _call(P, "shot_heat_apply_noalloc", [0] * 20, [1e-3] * 20, v, out) == E_INVALID
+    assert b"no-allocation scratch" in P.lib.shot_last_error()
