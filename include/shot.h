@@ -25,11 +25,19 @@
  *   items back to back, item i starting at element sum_{i'<i} nlat*nlon of
  *   grid_of_item[i'], each item row-major [nlat][nlon].
  * Precision.  SHOT_FP64 plans take and return double fields and compute in
- *   float64.  SHOT_FP32 and SHOT_BF16_MFMA plans take and return float fields;
- *   FFTs and pointwise updates run in float32, the Legendre stage in float32
- *   (SHOT_FP32) or in bfloat16 operands with float32 accumulation
- *   (SHOT_BF16_MFMA).  Quadrature, Legendre recurrence coefficients and every
- *   final reduction (cost, divergence, norms) are float64 in all plans.
+ *   float64.  SHOT_FP32, SHOT_BF16_MFMA and SHOT_BF16X3_MFMA plans take and
+ *   return float fields; FFTs and pointwise updates run in float32, the
+ *   Legendre stage in float32 (SHOT_FP32), in bfloat16 operands on matrix cores
+ *   with float32 accumulation (SHOT_BF16_MFMA), or in split bfloat16 operands
+ *   (SHOT_BF16X3_MFMA: each operand is the sum of two bfloat16 numbers, hi and
+ *   lo, and a product is formed as hi*hi + hi*lo + lo*hi on matrix cores,
+ *   about 2^-16 relative error per product against 2^-8 for plain bfloat16;
+ *   recurrence Legendre mode only).  With SHOT_LEG_RECURRENCE the bfloat16
+ *   forms generate P_l^m in float64 and round it to the operand form inside
+ *   the kernel; the separate SHT entry points (shot_sht_analysis/synthesis) of
+ *   such plans compute in float32.  Quadrature, Legendre recurrence
+ *   coefficients and every final reduction (cost, divergence, norms) are
+ *   float64 in all plans.
  * Memory.  Pointers documented "device" must be device memory of the GPU
  *   that was current when the plan was made; "host" pointers are ordinary
  *   host memory.  The caller owns every argument buffer; the plan owns its
@@ -65,7 +73,7 @@ typedef enum {
 } shot_status;
 
 enum { SHOT_GRID_GAUSS_LEGENDRE = 0, SHOT_GRID_CLENSHAW_CURTIS = 1, SHOT_GRID_HEALPIX = 2, SHOT_GRID_LOBATTO = 3 };
-enum { SHOT_FP64 = 0, SHOT_FP32 = 1, SHOT_BF16_MFMA = 2 };
+enum { SHOT_FP64 = 0, SHOT_FP32 = 1, SHOT_BF16_MFMA = 2, SHOT_BF16X3_MFMA = 3 };
 enum { SHOT_LEG_AUTO = 0, SHOT_LEG_TABLE = 1, SHOT_LEG_RECURRENCE = 2 };
 
 /* One grid.  kind: SHOT_GRID_GAUSS_LEGENDRE (rows at the roots of P_nlat),
@@ -230,8 +238,10 @@ shot_status shot_gradient_regional_rms(shot_plan_t plan, const int32_t* grid_of_
                                        double* rms_out, void* stream);
 
 /* Launch configuration of grid `grid`'s Legendre kernel: items advanced per
- * workgroup of the VALU kernels (1, 2, 4 or 8; 0 = automatic, capped by LDS)
- * and, as the second value, for SHOT_LEG_RECURRENCE grids the latitude chains
+ * workgroup of the VALU kernels (1, 2, 4 or 8; 0 = automatic, capped by LDS;
+ * for SHOT_LEG_RECURRENCE grids of float plans 8 or 16 select the
+ * recurrence-fed matrix-core kernel with that many items per workgroup, which
+ * bfloat16 plans always use) and, as the second value, for SHOT_LEG_RECURRENCE grids the latitude chains
  * per thread of the latitude-split kernel (1, 2 or 4, at most 256 threads per
  * workgroup; 0 = the row-split kernel), for SHOT_LEG_TABLE grids of float32 and
  * bfloat16 plans the matrix-core kernel's column tiles per workgroup (1, 2 or 4

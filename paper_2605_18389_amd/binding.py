@@ -19,7 +19,7 @@ GRID_GAUSS_LEGENDRE = 0
 GRID_CLENSHAW_CURTIS = 1
 GRID_HEALPIX = 2
 GRID_LOBATTO = 3
-FP64, FP32, BF16_MFMA = 0, 1, 2
+FP64, FP32, BF16_MFMA, BF16X3_MFMA = 0, 1, 2, 3
 LEG_AUTO, LEG_TABLE, LEG_RECURRENCE = 0, 1, 2
 
 OK = 0
@@ -30,7 +30,7 @@ E_UNSUPPORTED = 4
 W_NOT_CONVERGED = 16
 E_BREAKDOWN = 17
 
-_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16_MFMA, "bf16_mfma": BF16_MFMA}
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16_MFMA, "bf16_mfma": BF16_MFMA, "bf16x3": BF16X3_MFMA}
 _LEG = {"auto": LEG_AUTO, "table": LEG_TABLE, "recurrence": LEG_RECURRENCE}
 _KIND = {"gl": GRID_GAUSS_LEGENDRE, "gauss_legendre": GRID_GAUSS_LEGENDRE,
          "cc": GRID_CLENSHAW_CURTIS, "clenshaw_curtis": GRID_CLENSHAW_CURTIS,
@@ -188,7 +188,8 @@ class Plan:
 
     grids: list of (kind, nlat, nlon, L) with kind "gl", "cc" or "lob", or ("hp", nside, L) for a
     HEALPix grid (stored as ("hp", 4 nside - 1, 4 nside, L): rings, longest ring, L).
-    precision: "fp64", "fp32" or "bf16" (bfloat16 Legendre operands, float32 accumulation).
+    precision: "fp64", "fp32", "bf16" (bfloat16 Legendre operands, float32 accumulation) or
+    "bf16x3" (split bfloat16 operands, three products per term; recurrence Legendre only).
     legendre: "auto", "table" (P̄ streamed from HBM) or "recurrence" (generated in float64).
     """
 

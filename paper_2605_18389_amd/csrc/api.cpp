@@ -383,7 +383,7 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
   // Legendre data
   std::vector<double> xs(g.x.begin(), g.x.begin() + g.h);
   int mode = leg_mode;
-  if (mode == SHOT_LEG_AUTO) mode = SHOT_LEG_TABLE;
+  if (mode == SHOT_LEG_AUTO) mode = P->prec == SHOT_BF16X3_MFMA ? SHOT_LEG_RECURRENCE : SHOT_LEG_TABLE;
   if (mode == SHOT_LEG_TABLE) {
     std::vector<double> tab;
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -489,6 +489,9 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
       HIP_TRY(hipMalloc(&g.d_pbuf, pb));
     }
     if ((st = upload((void**)&g.d_xs, xs, s)) != SHOT_OK) return st;
+    // (the matrix-core recurrence kernel reads up to 32 coefficients past an
+    // order's end with wave-uniform indices: pad past the last order)
+    coef.resize(coef.size() + 64, 0.0);
     if ((st = upload((void**)&g.d_rcoef, coef, s)) != SHOT_OK) return st;
     if ((st = upload((void**)&g.d_rgam, gam, s)) != SHOT_OK) return st;
     if ((st = upload((void**)&g.d_rseed, seed, s)) != SHOT_OK) return st;
@@ -512,6 +515,7 @@ struct Layout {
   std::vector<int64_t> user_coff;  // by user item: coefficient offset
   std::vector<Group> groups;
   int64_t spec_total = 0;          // complex elements
+  std::vector<int64_t> sorted_soff; // by sorted position: spectral workspace offset
   int64_t field_total = 0;         // elements
   int hs = 0, Lmax = 0;
 };
@@ -539,10 +543,12 @@ shot_status make_layout(const shot_plan_s* P, const int32_t* grid_of_item, int n
   std::stable_sort(Lo.order.begin(), Lo.order.end(),
                    [&](int a, int b) { return grid_of_item[a] < grid_of_item[b]; });
   Lo.groups.clear();
+  Lo.sorted_soff.assign(nitems, 0);
   for (int s = 0; s < nitems; ++s) {
     const int g = grid_of_item[Lo.order[s]];
     if (Lo.groups.empty() || Lo.groups.back().grid != g) Lo.groups.push_back({g, s, 0});
     Lo.groups.back().count++;
+    Lo.sorted_soff[s] = Lo.spec_total;  // the same running sum as the item descriptors' soff
     Lo.spec_total += 2LL * P->grids[g].d.L * P->grids[g].h;
   }
   return SHOT_OK;
@@ -672,15 +678,17 @@ shot_status upload_items(shot_plan_s* P, const Layout& Lo, const int32_t* grid_o
   return SHOT_OK;
 }
 
-const SplitSched* leg_split(const shot_plan_s* P, const GridRec& g, int nb, int* ib_out);
+const SplitSched* leg_split(const shot_plan_s* P, const GridRec& g, int nb, int leg_mode, int* ib_out);
 
+// leg_mode: mode of the Legendre launch whose spectrum a row launch reads
+// (it decides which kernel ran, and so whether long orders arrive in parts).
 template <typename T>
 RowArgs<T> row_args(const shot_plan_s* P, const GridRec& g, const Layout& Lo, const Group& G, const Work<T>& W,
-                    int nitems) {
+                    int nitems, int leg_mode = 0) {
   RowArgs<T> a;
   std::memset(&a, 0, sizeof(a));
   int cib = 1;
-  if (leg_split(P, g, G.count, &cib) == &g.ss) {  // spectra arrive with long orders in parts
+  if (leg_split(P, g, G.count, leg_mode, &cib) == &g.ss) {  // spectra arrive with long orders in parts
     a.cut = g.d_cut;
     a.pbuf = g.d_pbuf;
     a.npb = g.ss.npb;
@@ -726,9 +734,10 @@ RowArgs<T> row_args(const shot_plan_s* P, const GridRec& g, const Layout& Lo, co
 }
 
 template <typename T>
-LegArgs<T> leg_args(const GridRec& g, const Group& G, const Work<T>& W, int hl_stride) {
+LegArgs<T> leg_args(const GridRec& g, const Group& G, const Work<T>& W, int hl_stride, const Layout& Lo) {
   LegArgs<T> a;
   std::memset(&a, 0, sizeof(a));
+  a.soff0 = Lo.sorted_soff[G.first];
   a.L = g.d.L;
   a.h = g.h;
   a.hpad = g.hpad;
@@ -806,6 +815,24 @@ int mma_tiles(const shot_plan_s* P, const GridRec& g, int count) {
   return nt;
 }
 
+// Recurrence-fed matrix-core kernel for a fused (mode 0) launch of `count`
+// items: column tiles per workgroup (1 or 2, i.e. 8 or 16 items), or 0 for
+// the VALU kernels; *op_out gets the operand form of the plan's precision.
+// bfloat16 and split-bfloat16 plans always take it (their precision is that of
+// the operands); float32 plans when tuned to 8 or 16 items per workgroup.
+int rmma_tiles(const shot_plan_s* P, const GridRec& g, int count, int leg_mode, int* op_out) {
+  if (leg_mode != 0 || g.tab_kind != TAB_RECUR || P->prec == SHOT_FP64 || g.hp || g.h > 512) return 0;
+  const int op = P->prec == SHOT_FP32 ? RM_F32 : (P->prec == SHOT_BF16_MFMA ? RM_BF16 : RM_BF16X3);
+  int nt;
+  if (g.tune_ib >= 8) nt = g.tune_ib / 8;
+  else if (P->prec == SHOT_FP32) return 0;
+  else nt = 1;  // one column tile: two workgroups fit a compute unit's LDS
+  while (nt > 1 && rmma_lds_bytes(g.d.L, g.h, nt, op) > 160 * 1024) nt >>= 1;
+  if (rmma_lds_bytes(g.d.L, g.h, nt, op) > 160 * 1024) return 0;
+  if (op_out) *op_out = op;
+  return nt;
+}
+
 int split_ib(const shot_plan_s* P, const GridRec& g, int count) {
   int ib = (g.tune_ib == 2 || (g.tune_ib == 0 && count >= 2)) ? 2 : 1;
   if (ib == 2 && (g.h > 384 || !pick_sched(P, g, count, 2))) ib = 1;  // 2 items: at most 6 chains per lane
@@ -821,8 +848,8 @@ shot_status run_rows(shot_plan_s* P, const RowArgs<T>& a, int nb, hipStream_t s)
 
 // Row-split work list of a Legendre launch of nb items (nullptr when another
 // kernel runs it) and its items per workgroup.
-const SplitSched* leg_split(const shot_plan_s* P, const GridRec& g, int nb, int* ib_out) {
-  if (mma_tiles(P, g, nb) > 0 || !use_split(P, g)) return nullptr;
+const SplitSched* leg_split(const shot_plan_s* P, const GridRec& g, int nb, int leg_mode, int* ib_out) {
+  if (mma_tiles(P, g, nb) > 0 || rmma_tiles(P, g, nb, leg_mode, nullptr) > 0 || !use_split(P, g)) return nullptr;
   const int ib = split_ib(P, g, nb);
   if (ib_out) *ib_out = ib;
   return pick_sched(P, g, nb, ib);
@@ -832,11 +859,14 @@ template <typename T>
 shot_status run_leg(shot_plan_s* P, const GridRec& g, LegArgs<T> a, hipStream_t s) {
   ProfScope ps(P, s, 0);
   hipError_t e;
-  int ib = 1;
+  int ib = 1, op = 0;
   const int nt = mma_tiles(P, g, a.nb);
+  const int rnt = rmma_tiles(P, g, a.nb, a.mode, &op);
   if (nt > 0) {
     e = launch_legendre_mma<T>(a, g.tab_kind, nt, s);
-  } else if (const SplitSched* S = leg_split(P, g, a.nb, &ib)) {
+  } else if (rnt > 0) {
+    e = launch_legendre_rmma<T>(a, op, rnt, s);
+  } else if (const SplitSched* S = leg_split(P, g, a.nb, a.mode, &ib)) {
     a.parts = S->d_parts;
     a.nparts = S->n;
     a.maxlen = S->maxlen;
@@ -877,7 +907,7 @@ shot_status heat_apply_impl(shot_plan_s* P, const int32_t* goi, int nitems, cons
     a.in = static_cast<const T*>(v);
     a.wts_in = transpose ? 0 : 1;
     ST_TRY(run_rows<T>(P, a, G.count, s));
-    ST_TRY(run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), s));
+    ST_TRY(run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax, Lo), s));
     a.mode = ROW_INV;
     a.out = static_cast<T*>(out);
     a.wts_out = transpose ? 1 : 0;
@@ -897,8 +927,8 @@ shot_status sht_impl(shot_plan_s* P, const int32_t* goi, int nitems, const void*
   ST_TRY(upload_items<T>(P, Lo, goi, {}, {}, tv, {}, {}, W, s));
   for (const Group& G : Lo.groups) {
     const GridRec& g = P->grids[G.grid];
-    RowArgs<T> a = row_args<T>(P, g, Lo, G, W, nitems);
-    LegArgs<T> la = leg_args<T>(g, G, W, Lo.Lmax);
+    RowArgs<T> a = row_args<T>(P, g, Lo, G, W, nitems, analysis ? 1 : 2);
+    LegArgs<T> la = leg_args<T>(g, G, W, Lo.Lmax, Lo);
     if (analysis) {
       a.mode = ROW_FWD;
       a.in = static_cast<const T*>(in);
@@ -984,7 +1014,7 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
     a.out2 = psi;
     return run_rows<T>(P, a, G.count, ls);
   };
-  auto leg = [&](const Group& G, const GridRec& g) { return run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), ls); };
+  auto leg = [&](const Group& G, const GridRec& g) { return run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax, Lo), ls); };
 
   int K = T_iter;
   int final_slot = nslot - 1;
@@ -1176,6 +1206,12 @@ shot_status autotune_impl(shot_plan_s* P, GridRec& g, const Layout& Lo, int nite
   if (g.tab_kind != TAB_RECUR && g.d_tabT)
     for (int nt : {1, 2, 4})
       if (16 * nt <= 2 * std::max(nitems, 8)) cand.push_back({0, nt});
+  if (g.tab_kind == TAB_RECUR && P->prec != SHOT_FP64) {
+    // bfloat16 and split-bfloat16 plans compute on matrix cores only
+    if (P->prec != SHOT_FP32) cand.clear();
+    for (int ib : {8, 16})
+      if (ib <= std::max(nitems, 8)) cand.push_back({ib, 0});
+  }
   const int save_ib = g.tune_ib, save_jpt = g.tune_jpt;
   const bool save_prof = P->prof;
   P->prof = false;
@@ -1188,18 +1224,20 @@ shot_status autotune_impl(shot_plan_s* P, GridRec& g, const Layout& Lo, int nite
   for (auto c : cand) {
     g.tune_ib = c.first;
     g.tune_jpt = c.second;
-    if (g.tab_kind != TAB_RECUR && c.second > 0) {
+    if (g.tab_kind == TAB_RECUR && c.first >= 8) {
+      if (rmma_tiles(P, g, nitems, 0, nullptr) != c.first / 8) continue;  // does not fit LDS
+    } else if (g.tab_kind != TAB_RECUR && c.second > 0) {
       if (mma_tiles(P, g, nitems) != c.second) continue;  // does not fit LDS
     } else if (use_split(P, g) ? split_ib(P, g, nitems) != c.first : pick_ib(P, g, nitems) != c.first) {
       continue;  // does not fit LDS
     }
-    if (g.tab_kind == TAB_RECUR && c.second == 0 && !use_split(P, g)) continue;
+    if (g.tab_kind == TAB_RECUR && c.first < 8 && c.second == 0 && !use_split(P, g)) continue;
     shot_status st = SHOT_OK;
-    for (int w = 0; w < 2 && st == SHOT_OK; ++w) st = run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), s);
+    for (int w = 0; w < 2 && st == SHOT_OK; ++w) st = run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax, Lo), s);
     if (st != SHOT_OK) continue;
     (void)hipEventRecord(e0, s);
     const int reps = 5;
-    for (int r = 0; r < reps && st == SHOT_OK; ++r) st = run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax), s);
+    for (int r = 0; r < reps && st == SHOT_OK; ++r) st = run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax, Lo), s);
     (void)hipEventRecord(e1, s);
     if (hipEventSynchronize(e1) != hipSuccess || st != SHOT_OK) continue;
     float ms = 0.f;
@@ -1338,7 +1376,7 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
     return SHOT_OK;
   };
   auto leg = [&](const Group& G, const GridRec& g, cpx<T>* spec) {
-    LegArgs<T> la = leg_args<T>(g, G, W, Lo.Lmax);
+    LegArgs<T> la = leg_args<T>(g, G, W, Lo.Lmax, Lo);
     la.spec = spec;
     return run_leg<T>(P, g, la, s);
   };
@@ -1712,7 +1750,9 @@ shot_status shot_sht_plan(shot_plan_t* out, const shot_grid_desc* grids, int32_t
   if (!out) return SHOT_E_INVALID;
   *out = nullptr;
   if (!grids || ngrids <= 0) return SHOT_E_INVALID;
-  if (precision < SHOT_FP64 || precision > SHOT_BF16_MFMA) return SHOT_E_INVALID;
+  if (precision < SHOT_FP64 || precision > SHOT_BF16X3_MFMA) return SHOT_E_INVALID;
+  // split bfloat16 operands are formed from the recurrence's values; no table form
+  if (precision == SHOT_BF16X3_MFMA && legendre_mode == SHOT_LEG_TABLE) return SHOT_E_UNSUPPORTED;
   if (legendre_mode < SHOT_LEG_AUTO || legendre_mode > SHOT_LEG_RECURRENCE) return SHOT_E_INVALID;
   for (int i = 0; i < ngrids; ++i) {
     const shot_grid_desc& d = grids[i];
@@ -1943,7 +1983,7 @@ shot_status shot_plan_set_tuning(shot_plan_t P, int32_t grid, int32_t items_per_
   if (!P || grid < 0 || grid >= (int)P->grids.size()) return SHOT_E_INVALID;
   GridRec& g = P->grids[grid];
   if (items_per_block != 0 && items_per_block != 1 && items_per_block != 2 && items_per_block != 4 &&
-      items_per_block != 8)
+      items_per_block != 8 && !(items_per_block == 16 && g.tab_kind == TAB_RECUR))
     return SHOT_E_INVALID;
   if (g.tab_kind == TAB_RECUR) {
     if (chains_per_thread != 0 && !recur_jpt_valid(g.h, chains_per_thread)) return SHOT_E_INVALID;

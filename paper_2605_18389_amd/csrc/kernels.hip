@@ -2307,6 +2307,442 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// Recurrence-fed matrix-core Legendre kernel (float32 fields, batches).
+//
+// P̄_l^m is generated by the float64 three-term recurrence (as in the VALU
+// kernels) and contracted on matrix cores against all the items of a column
+// chunk at once, so one recurrence serves 8 NT items instead of one or two.
+// One workgroup per (order m, chunk of 8 NT items = 16 NT real columns); its
+// NW = ceil(h / 64) waves split the latitudes, each lane running the chain of
+// one latitude j.  Rows are taken in blocks of 32 (16 per parity), rows of
+// one parity forming the M (analysis) or K (synthesis) dimension of a tile:
+//   analysis   D[r][n] = sum_j R_r(x_j) Y[j][n]     K = the wave's 64 latitudes
+//   combine    b[r][n] = gamma_r^2 h_l(item) sum over waves of D (fixed order)
+//   synthesis  G[j][n] = sum_r R_r(x_j) b[r][n]     K = rows of one parity
+// (P̄ = gamma R; the folded spectrum entries E/O are the columns n of one
+// parity).  The analysis A operand needs the recurrence values with the
+// latitude along K, so each block's values pass through a per-wave LDS tile;
+// the synthesis A operand has the rows along K, which a lane already holds,
+// and a 4 x 4 exchange of lane groups (permlane swaps) puts them in operand
+// order.  Operands: float32 (v_mfma_f32_16x16x4_f32), bfloat16
+// (v_mfma_f32_16x16x16_bf16) or split bfloat16 (x = hi + lo, two bf16 with
+// round-to-nearest; products hi*hi + hi*lo + lo*hi, three MFMAs): relative
+// error about 2^-16 per product instead of 2^-8.  Accumulation is float32.
+// ---------------------------------------------------------------------------
+typedef short rm_short4 __attribute__((ext_vector_type(4)));
+
+// bf16 bits of v, round to nearest even (the hardware conversion)
+__device__ __forceinline__ unsigned rm_bf16(float v) {
+  return (unsigned)__builtin_bit_cast(unsigned short, (__bf16)v);
+}
+
+template <int OP>
+struct RmTraits;
+template <>
+struct RmTraits<RM_F32> {
+  static constexpr int KS = 4;       // k per MFMA
+  static constexpr int PLANES = 1;   // LDS planes (hi, lo)
+  static constexpr int ES = 4;       // bytes per element of a plane
+  struct Op { float v; };
+  __device__ static void put(unsigned char* base, size_t plane, size_t idx, float v) {
+    reinterpret_cast<float*>(base)[idx] = v;
+  }
+  // k-run of one lane from a plane row (KS / 4 groups of 4... one value for f32)
+  __device__ static Op get(const unsigned char* base, size_t plane, size_t idx) {
+    return {reinterpret_cast<const float*>(base)[idx]};
+  }
+  __device__ static f32x4_t mma(const Op& a, const Op& b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a.v, b.v, c, 0, 0, 0);
+  }
+  __device__ static Op make(const float (&x)[1]) { return {x[0]}; }
+};
+template <>
+struct RmTraits<RM_BF16> {
+  static constexpr int KS = 16;
+  static constexpr int PLANES = 1;
+  static constexpr int ES = 2;
+  struct Op { uint2 h; };
+  __device__ static void put(unsigned char* base, size_t plane, size_t idx, float v) {
+    reinterpret_cast<unsigned short*>(base)[idx] = (unsigned short)rm_bf16(v);
+  }
+  __device__ static Op get(const unsigned char* base, size_t plane, size_t idx) {
+    return {*reinterpret_cast<const uint2*>(reinterpret_cast<const unsigned short*>(base) + idx)};
+  }
+  __device__ static f32x4_t mma(const Op& a, const Op& b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(rm_short4, a.h),
+                                                     __builtin_bit_cast(rm_short4, b.h), c, 0, 0, 0);
+  }
+  __device__ static Op make(const float (&x)[4]) {
+    return {make_uint2(rm_bf16(x[0]) | (rm_bf16(x[1]) << 16), rm_bf16(x[2]) | (rm_bf16(x[3]) << 16))};
+  }
+};
+template <>
+struct RmTraits<RM_BF16X3> {
+  static constexpr int KS = 16;
+  static constexpr int PLANES = 2;
+  static constexpr int ES = 2;
+  struct Op { uint2 h, l; };
+  __device__ static void put(unsigned char* base, size_t plane, size_t idx, float v) {
+    const unsigned hb = rm_bf16(v);
+    const float lo = v - __uint_as_float(hb << 16);
+    unsigned short* p = reinterpret_cast<unsigned short*>(base);
+    p[idx] = (unsigned short)hb;
+    p[plane + idx] = (unsigned short)rm_bf16(lo);
+  }
+  __device__ static Op get(const unsigned char* base, size_t plane, size_t idx) {
+    const unsigned short* p = reinterpret_cast<const unsigned short*>(base);
+    return {*reinterpret_cast<const uint2*>(p + idx), *reinterpret_cast<const uint2*>(p + plane + idx)};
+  }
+  __device__ static f32x4_t mma(const Op& a, const Op& b, f32x4_t c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(rm_short4, a.l),
+                                                  __builtin_bit_cast(rm_short4, b.h), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(rm_short4, a.h),
+                                                  __builtin_bit_cast(rm_short4, b.l), c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(rm_short4, a.h),
+                                                     __builtin_bit_cast(rm_short4, b.h), c, 0, 0, 0);
+  }
+  __device__ static Op make(const float (&x)[4]) {
+    unsigned hb[4], lb[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      hb[e] = rm_bf16(x[e]);
+      lb[e] = rm_bf16(x[e] - __uint_as_float(hb[e] << 16));
+    }
+    return {make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16)),
+            make_uint2(lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16))};
+  }
+};
+
+// float value of a float64 recurrence term, kept opaque so that a later
+// rounding to bfloat16 stays a float -> bfloat16 conversion (fused with the
+// float64 -> float one, the compiler emits an exact double -> bfloat16
+// conversion costing several instructions per value)
+__device__ __forceinline__ float rm_f32(double x) {
+  float f = (float)x;
+  asm("" : "+v"(f));
+  return f;
+}
+
+// 4 x 4 exchange of lane groups: afterwards register t holds, in lane group g,
+// what lane group t held in register g (lane groups = 16-lane rows).
+__device__ __forceinline__ void lanegroup_transpose4(unsigned& r0, unsigned& r1, unsigned& r2, unsigned& r3) {
+  auto a = __builtin_amdgcn_permlane32_swap(r0, r2, false, false);
+  auto b = __builtin_amdgcn_permlane32_swap(r1, r3, false, false);
+  auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+  auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+  r0 = c[0];
+  r1 = c[1];
+  r2 = d[0];
+  r3 = d[1];
+}
+
+// LDS layout of legendre_rmma_kernel (bytes), shared with the host.
+struct RmLayout {
+  int nb, ncol, pld, bld;
+  size_t o_p, o_d, o_b, o_g, o_h, o_c, total, pplane, bplane;
+};
+__host__ __device__ inline RmLayout rm_layout(int L, int h, int nt, int nw, int es, int planes) {
+  RmLayout q;
+  q.nb = (L + 31) / 32;              // row blocks of the longest order
+  q.ncol = 16 * nt;
+  // row pitches (elements): float rows odd, so the lanes of a k-slice read
+  // distinct banks; bfloat16 rows keep 8-byte operand reads aligned
+  q.pld = es == 4 ? 65 : 68;
+  q.bld = 16 * q.nb + (es == 4 ? 1 : 4);
+  q.pplane = (size_t)nw * 32 * q.pld;
+  q.bplane = (size_t)2 * q.ncol * q.bld;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 15) / 16 * 16; return o; };
+  // the recurrence tiles' region also stages the chunk's folded spectra in and
+  // out: 8 nt items x h latitudes x (E, O) complex
+  const size_t tiles = q.pplane * planes * es, spectra = (size_t)8 * nt * h * 4 * sizeof(float);
+  q.o_p = take(tiles > spectra ? tiles : spectra);
+  q.o_d = take(sizeof(float) * 2 * nw * 2 * q.ncol * 20);
+  q.o_b = take(q.bplane * planes * es);
+  q.o_g = take(sizeof(double) * 32 * q.nb);
+  q.o_h = take(sizeof(float) * 8 * nt * 32 * q.nb);
+  q.o_c = take(sizeof(double) * (32 * q.nb + 1));
+  q.total = off;
+  return q;
+}
+
+template <typename T, int OP, int NT>
+__global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using TR = RmTraits<OP>;
+  using Op = typename TR::Op;
+  constexpr int KS = TR::KS, ES = TR::ES, PL = TR::PLANES;
+  constexpr int NKS = 64 / KS;        // k steps over a wave's 64 latitudes
+  const int L = A.L, h = A.h;
+  const int nw = blockDim.x >> 6;
+  const RmLayout Q = rm_layout(L, h, NT, nw, ES, PL);
+  // workgroups are dispatched in linear order: take orders longest first, all
+  // column chunks of an order together
+  const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+  const int m = lin / gridDim.y;
+  const int nr = L - m;
+  const int nblk = (nr + 31) / 32;
+  const int c0 = (lin - m * gridDim.y) * Q.ncol;
+  const int ncol = 2 * A.nb;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lg = lane >> 4;
+  unsigned char* Pt = smem_raw + Q.o_p + (size_t)wave * 32 * Q.pld * ES;
+  float* Dp = reinterpret_cast<float*>(smem_raw + Q.o_d);
+  unsigned char* Bs = smem_raw + Q.o_b;
+  double* gm = reinterpret_cast<double*>(smem_raw + Q.o_g);
+  float* hls = reinterpret_cast<float*>(smem_raw + Q.o_h);
+  double* cf = reinterpret_cast<double*>(smem_raw + Q.o_c);
+  float* ysl = reinterpret_cast<float*>(smem_raw + Q.o_p);   // [item][j][E re, E im, O re, O im]
+  const long long toff = tri_off(m, L);
+  const int nit = min(8 * NT, A.nb - c0 / 2);                 // items of this chunk
+  // items of one launch group are consecutive in the workspace, each holding
+  // 2 L h complex spectral entries: this chunk's spectra start here
+  const float4* spc = reinterpret_cast<const float4*>(A.spec + A.soff0) + (size_t)(c0 / 2) * L * h + (size_t)m * h;
+  const int j = 64 * wave + lane;
+  const double xj = A.xs[min(j, h - 1)];
+  const double sd = A.rseed[(size_t)m * h + min(j, h - 1)];
+
+  // Staging: the chunk's folded spectra (h x (E, O) complex per item, coalesced
+  // 16-byte loads), the order's recurrence coefficients (zero past its end),
+  // gamma^2 per row and the items' heat multipliers; every load of a thread is
+  // issued before the first is used (one memory round trip)
+  {
+    constexpr int SB = 8;
+    float4 v4[SB];
+    const int ns = nit * h;
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int idx = min(tid + u * (int)blockDim.x, ns - 1), i = idx / h, jj = idx - i * h;
+      v4[u] = spc[(size_t)i * L * h + jj];
+    }
+    double cv[2], gv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = min(tid + u * (int)blockDim.x, nr - 1);
+      cv[u] = A.rcoef[toff + r];
+      gv[u] = A.rgam[toff + r];
+    }
+    constexpr int HB = 16;
+    float hv[HB];
+    const int nh = 8 * NT * 32 * nblk;
+#pragma unroll
+    for (int u = 0; u < HB; ++u) {
+      const int idx = min(tid + u * (int)blockDim.x, nh - 1), i = idx / (32 * nblk), r = idx - i * 32 * nblk;
+      hv[u] = A.hl[(size_t)(A.item0 + c0 / 2 + min(i, nit - 1)) * A.hl_stride + m + min(r, nr - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < SB; ++u)
+      if (tid + u * (int)blockDim.x < ns) reinterpret_cast<float4*>(ysl)[tid + u * blockDim.x] = v4[u];
+    for (int idx = tid + SB * blockDim.x; idx < ns; idx += blockDim.x) {  // larger chunks than one round
+      const int i = idx / h, jj = idx - i * h;
+      reinterpret_cast<float4*>(ysl)[idx] = spc[(size_t)i * L * h + jj];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = tid + u * (int)blockDim.x;
+      if (r <= 32 * nblk) cf[r] = (r < nr && r > 0) ? cv[u] : 0.0;
+      if (r < 32 * nblk) gm[r] = r < nr ? gv[u] * gv[u] : 0.0;
+    }
+    for (int r = tid + 2 * blockDim.x; r <= 32 * nblk; r += blockDim.x) {
+      const int rr = min(r, nr - 1);
+      const double c = A.rcoef[toff + rr], g = A.rgam[toff + rr];
+      cf[r] = (r < nr && r > 0) ? c : 0.0;
+      if (r < 32 * nblk) gm[r] = r < nr ? g * g : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < HB; ++u) {
+      const int idx = tid + u * (int)blockDim.x, i = idx / (32 * nblk), r = idx - i * 32 * nblk;
+      if (idx < nh) hls[idx] = (r < nr && i < nit) ? hv[u] : 0.f;
+    }
+    for (int idx = tid + HB * blockDim.x; idx < nh; idx += blockDim.x) {
+      const int i = idx / (32 * nblk), r = idx - i * 32 * nblk;
+      hls[idx] = (r < nr && i < nit) ? A.hl[(size_t)(A.item0 + c0 / 2 + i) * A.hl_stride + m + r] : 0.f;
+    }
+  }
+  const double seed = j < h ? sd : 0.0;   // lanes past the last latitude run a zero chain
+  __syncthreads();
+  // this wave's latitudes of the items' folded spectra: analysis B operands,
+  // kept in registers (k = latitude 64 wave + KS s + the lane group's k-run)
+  Op yb[NKS][2][NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int il = 8 * t + (li >> 1);
+#pragma unroll
+    for (int s = 0; s < NKS; ++s)
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        float x[KS == 4 ? 1 : 4];
+#pragma unroll
+        for (int e = 0; e < (KS == 4 ? 1 : 4); ++e) {
+          const int jj = 64 * wave + KS * s + (KS == 4 ? lg : 4 * lg + e);
+          x[e] = (il < nit && jj < h) ? ysl[((size_t)il * h + jj) * 4 + 2 * par + (li & 1)] : 0.f;
+        }
+        yb[s][par][t] = TR::make(x);
+      }
+  }
+  __syncthreads();  // the staged spectra share LDS with the recurrence tiles
+
+  // ---- analysis, block by block; partials of the waves combined in LDS
+  double R1 = seed, R2 = 0.0;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int r0 = 32 * blk;
+    double cq[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) cq[q] = cf[r0 + q + 1];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      TR::put(Pt, Q.pplane, (size_t)q * Q.pld + lane, rm_f32(R1));
+      const double rn = fma(cq[q] * xj, R1, R2);
+      R2 = R1;
+      R1 = rn;
+    }
+    f32x4_t acc[2][NT];
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[par][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        // A[i][k] = R_{r0 + 2i + par}(x_{64 wave + KS s + k})
+        const int kk = KS * s + (KS == 4 ? lg : 4 * lg);
+        const Op a = TR::get(Pt, Q.pplane, (size_t)(2 * li + par) * Q.pld + kk);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[par][t] = TR::mma(a, yb[s][par][t], acc[par][t]);
+      }
+    }
+    // wave partials, [wave][parity][column][row of the parity] (rows padded to 20)
+    float* dp = Dp + (size_t)(blk & 1) * nw * 2 * Q.ncol * 20;
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        *reinterpret_cast<f32x4_t*>(dp + (((size_t)wave * 2 + par) * Q.ncol + 16 * t + li) * 20 + 4 * lg) =
+            acc[par][t];
+    __syncthreads();
+    // b = gamma^2 h_l (sum over the waves), in the operand format, rows of one
+    // parity contiguous; rows past the order's end are zero (gamma is zero there)
+    for (int idx = tid; idx < 2 * 16 * Q.ncol; idx += blockDim.x) {
+      const int pn = idx >> 4, rp = idx & 15;
+      const int par = pn / Q.ncol, n = pn - par * Q.ncol;
+      const int r = r0 + 2 * rp + par;
+      float part[8];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) part[w] = dp[(((size_t)min(w, nw - 1) * 2 + par) * Q.ncol + n) * 20 + rp];
+      const double sc = gm[r] * (double)hls[(n >> 1) * 32 * nblk + r];
+      float sum = part[0];
+#pragma unroll
+      for (int w = 1; w < 8; ++w) sum += w < nw ? part[w] : 0.f;
+      TR::put(Bs, Q.bplane, ((size_t)par * Q.ncol + n) * Q.bld + 16 * blk + rp, (float)((double)sum * sc));
+    }
+  }
+  __syncthreads();
+
+  // ---- synthesis: the recurrence again, values moved to operand order by
+  // lane-group exchanges, G accumulated in registers
+  f32x4_t G[2][4][NT];
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) G[par][jt][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  R1 = seed;
+  R2 = 0.0;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int r0 = 32 * blk;
+    double cq[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) cq[q] = cf[r0 + q + 1];
+    float v[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      v[q] = rm_f32(R1);
+      const double rn = fma(cq[q] * xj, R1, R2);
+      R2 = R1;
+      R1 = rn;
+    }
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      if constexpr (OP == RM_F32) {
+        // K step s: rows of this parity 4s .. 4s+3 of the block
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          unsigned a[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[e] = __float_as_uint(v[2 * (4 * s + e) + par]);
+          lanegroup_transpose4(a[0], a[1], a[2], a[3]);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const Op b = TR::get(Bs, Q.bplane, ((size_t)par * Q.ncol + 16 * t + li) * Q.bld + 16 * blk + 4 * s + lg);
+#pragma unroll
+            for (int jt = 0; jt < 4; ++jt) G[par][jt][t] = TR::mma(Op{__uint_as_float(a[jt])}, b, G[par][jt][t]);
+          }
+        }
+      } else {
+        // one K step: the 16 rows of this parity; lane group g holds rows 4g .. 4g+3
+        unsigned hw[2][4], lw[2][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int w2 = 0; w2 < 2; ++w2) {
+            const float x0 = v[2 * (4 * u + 2 * w2) + par], x1 = v[2 * (4 * u + 2 * w2 + 1) + par];
+            const unsigned h0 = rm_bf16(x0), h1 = rm_bf16(x1);
+            hw[w2][u] = h0 | (h1 << 16);
+            if constexpr (OP == RM_BF16X3) {
+              const unsigned l0 = rm_bf16(x0 - __uint_as_float(h0 << 16));
+              const unsigned l1 = rm_bf16(x1 - __uint_as_float(h1 << 16));
+              lw[w2][u] = l0 | (l1 << 16);
+            }
+          }
+#pragma unroll
+        for (int w2 = 0; w2 < 2; ++w2) {
+          lanegroup_transpose4(hw[w2][0], hw[w2][1], hw[w2][2], hw[w2][3]);
+          if constexpr (OP == RM_BF16X3) lanegroup_transpose4(lw[w2][0], lw[w2][1], lw[w2][2], lw[w2][3]);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const Op b = TR::get(Bs, Q.bplane, ((size_t)par * Q.ncol + 16 * t + li) * Q.bld + 16 * blk + 4 * lg);
+#pragma unroll
+          for (int jt = 0; jt < 4; ++jt) {
+            Op a;
+            a.h = make_uint2(hw[0][jt], hw[1][jt]);
+            if constexpr (OP == RM_BF16X3) a.l = make_uint2(lw[0][jt], lw[1][jt]);
+            G[par][jt][t] = TR::mma(a, b, G[par][jt][t]);
+          }
+        }
+      }
+    }
+  }
+  // ---- the order's folded spectrum: G[j][n] (j = 64 wave + 16 jt + 4 lg + e)
+  // gathered in the staging region, then copied out with coalesced stores
+  // (the tiles that region also holds are no longer read)
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int il = 8 * t + (li >> 1);
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int jj = 64 * wave + 16 * jt + 4 * lg + e;
+        if (il < nit && jj < h) {
+          ysl[((size_t)il * h + jj) * 4 + 0 + (li & 1)] = G[0][jt][t][e];
+          ysl[((size_t)il * h + jj) * 4 + 2 + (li & 1)] = G[1][jt][t][e];
+        }
+      }
+  }
+  __syncthreads();
+  float4* dsc = reinterpret_cast<float4*>(A.spec + A.soff0) + (size_t)(c0 / 2) * L * h + (size_t)m * h;
+  for (int idx = tid; idx < nit * h; idx += blockDim.x) {
+    const int i = idx / h, jj = idx - i * h;
+    dsc[(size_t)i * L * h + jj] = reinterpret_cast<const float4*>(ysl)[idx];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Per-item final reductions: cost, e_marg history and final residual, masses.
 // res[item*8 + .] = {cost, err, m(p), m(q), ||p||, 0, 0, 0}.
 // ---------------------------------------------------------------------------
@@ -2697,6 +3133,58 @@ hipError_t launch_legendre_mma(const LegArgs<T>& a, int table_kind, int nt, hipS
 }
 template hipError_t launch_legendre_mma<float>(const LegArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_legendre_mma<double>(const LegArgs<double>&, int, int, hipStream_t);
+
+// Recurrence-fed matrix-core kernel: float32 fields only; waves = ceil(h/64) <= 8.
+template <typename T, int OP, int NT>
+static hipError_t launch_rmma_nt(const LegArgs<T>& a, hipStream_t stream) {
+  if constexpr (sizeof(T) != 4) {
+    return hipErrorInvalidValue;
+  } else {
+    using TR = RmTraits<OP>;
+    const int nw = (a.h + 63) / 64;
+    const RmLayout Q = rm_layout(a.L, a.h, NT, nw, TR::ES, TR::PLANES);
+    if (nw > 8 || Q.total > 160 * 1024) return hipErrorInvalidValue;
+    if (Q.total > 65536) {
+      static size_t attr_bytes = 65536;  // dynamic LDS enabled so far for this instantiation
+      if (Q.total > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&legendre_rmma_kernel<T, OP, NT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)Q.total);
+        if (e != hipSuccess) return e;
+        attr_bytes = Q.total;
+      }
+    }
+    dim3 grid(a.L, (2 * a.nb + Q.ncol - 1) / Q.ncol);
+    SHOT_LAUNCH((legendre_rmma_kernel<T, OP, NT>), grid, dim3(64 * nw), Q.total, stream, a);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, int OP>
+static hipError_t launch_rmma_op(const LegArgs<T>& a, int nt, hipStream_t stream) {
+  switch (nt) {
+    case 1: return launch_rmma_nt<T, OP, 1>(a, stream);
+    case 2: return launch_rmma_nt<T, OP, 2>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t rmma_lds_bytes(int L, int h, int nt, int op) {
+  const int nw = (h + 63) / 64;
+  const int es = op == RM_F32 ? 4 : 2, planes = op == RM_BF16X3 ? 2 : 1;
+  return rm_layout(L, h, nt, nw, es, planes).total;
+}
+
+template <typename T>
+hipError_t launch_legendre_rmma(const LegArgs<T>& a, int op, int nt, hipStream_t stream) {
+  switch (op) {
+    case RM_F32: return launch_rmma_op<T, RM_F32>(a, nt, stream);
+    case RM_BF16: return launch_rmma_op<T, RM_BF16>(a, nt, stream);
+    case RM_BF16X3: return launch_rmma_op<T, RM_BF16X3>(a, nt, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_legendre_rmma<float>(const LegArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_legendre_rmma<double>(const LegArgs<double>&, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_legendre(const LegArgs<T>& a, int table_kind, int ib, hipStream_t stream) {

@@ -160,6 +160,8 @@ struct LegArgs {
   int mode;               // 0 fused (analysis, x h, synthesis), 1 analysis -> coeff, 2 coeff -> synthesis
   int jpt;                // RECURRENCE mode: latitude chains per thread (0 = automatic)
   cpx<T>* coeff;          // packed (m, l) coefficients, item offsets ItemDev::coff (modes 1, 2)
+  long long soff0;        // spectral offset of the launch's first item (items of a launch are
+                          // consecutive, 2 L h complex entries each)
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the launch status.
@@ -199,5 +201,13 @@ hipError_t launch_combine(const CombineDev* d, int npairs, long long maxn, T* ou
 
 // Table element kinds.
 enum { TAB_F64 = 0, TAB_F32 = 1, TAB_BF16 = 2, TAB_RECUR = 3 };
+
+// Operand forms of the recurrence-fed matrix-core Legendre kernel: float32,
+// bfloat16, or split bfloat16 (hi + lo, three products).
+enum { RM_F32 = 0, RM_BF16 = 1, RM_BF16X3 = 2 };
+// nt column tiles of 16 (8 nt items) per workgroup, nt in {1, 2}.
+template <typename T>
+hipError_t launch_legendre_rmma(const LegArgs<T>& a, int op, int nt, hipStream_t stream);
+size_t rmma_lds_bytes(int L, int h, int nt, int op);
 
 }  // namespace shot
