@@ -2439,7 +2439,7 @@ __device__ __forceinline__ void lanegroup_transpose4(unsigned& r0, unsigned& r1,
 // LDS layout of legendre_rmma_kernel (bytes), shared with the host.
 struct RmLayout {
   int nb, ncol, pld, bld;
-  size_t o_p, o_d, o_b, o_g, o_h, o_c, total, pplane, bplane;
+  size_t o_p, o_d, o_b, o_c, o_s, total, pplane, bplane;
 };
 __host__ __device__ inline RmLayout rm_layout(int L, int h, int nt, int nw, int es, int planes) {
   RmLayout q;
@@ -2459,9 +2459,8 @@ __host__ __device__ inline RmLayout rm_layout(int L, int h, int nt, int nw, int 
   q.o_p = take(tiles > spectra ? tiles : spectra);
   q.o_d = take(sizeof(float) * 2 * nw * 2 * q.ncol * 20);
   q.o_b = take(q.bplane * planes * es);
-  q.o_g = take(sizeof(double) * 32 * q.nb);
-  q.o_h = take(sizeof(float) * 8 * nt * 32 * q.nb);
   q.o_c = take(sizeof(double) * (32 * q.nb + 1));
+  q.o_s = take(sizeof(double) * 2 * 32 + sizeof(float) * 2 * 8 * nt * 32);  // per-block gamma, h_l (2 buffers)
   q.total = off;
   return q;
 }
@@ -2490,12 +2489,13 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
   unsigned char* Pt = smem_raw + Q.o_p + (size_t)wave * 32 * Q.pld * ES;
   float* Dp = reinterpret_cast<float*>(smem_raw + Q.o_d);
   unsigned char* Bs = smem_raw + Q.o_b;
-  double* gm = reinterpret_cast<double*>(smem_raw + Q.o_g);
-  float* hls = reinterpret_cast<float*>(smem_raw + Q.o_h);
   double* cf = reinterpret_cast<double*>(smem_raw + Q.o_c);
   float* ysl = reinterpret_cast<float*>(smem_raw + Q.o_p);   // [item][j][E re, E im, O re, O im]
   const long long toff = tri_off(m, L);
   const int nit = min(8 * NT, A.nb - c0 / 2);                 // items of this chunk
+  const int ncomb = 2 * 16 * Q.ncol;                           // combine elements per block
+  double* gsl = reinterpret_cast<double*>(smem_raw + Q.o_s);  // [2][32] gamma of the block's rows
+  float* hsl = reinterpret_cast<float*>(gsl + 64);           // [2][8 NT][32] h_l of the block's rows
   // items of one launch group are consecutive in the workspace, each holding
   // 2 L h complex spectral entries: this chunk's spectra start here
   const float4* spc = reinterpret_cast<const float4*>(A.spec + A.soff0) + (size_t)(c0 / 2) * L * h + (size_t)m * h;
@@ -2516,21 +2516,9 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
       const int idx = min(tid + u * (int)blockDim.x, ns - 1), i = idx / h, jj = idx - i * h;
       v4[u] = spc[(size_t)i * L * h + jj];
     }
-    double cv[2], gv[2];
+    double cv[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int r = min(tid + u * (int)blockDim.x, nr - 1);
-      cv[u] = A.rcoef[toff + r];
-      gv[u] = A.rgam[toff + r];
-    }
-    constexpr int HB = 16;
-    float hv[HB];
-    const int nh = 8 * NT * 32 * nblk;
-#pragma unroll
-    for (int u = 0; u < HB; ++u) {
-      const int idx = min(tid + u * (int)blockDim.x, nh - 1), i = idx / (32 * nblk), r = idx - i * 32 * nblk;
-      hv[u] = A.hl[(size_t)(A.item0 + c0 / 2 + min(i, nit - 1)) * A.hl_stride + m + min(r, nr - 1)];
-    }
+    for (int u = 0; u < 2; ++u) cv[u] = A.rcoef[toff + min(tid + u * (int)blockDim.x, nr - 1)];
 #pragma unroll
     for (int u = 0; u < SB; ++u)
       if (tid + u * (int)blockDim.x < ns) reinterpret_cast<float4*>(ysl)[tid + u * blockDim.x] = v4[u];
@@ -2542,23 +2530,9 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
     for (int u = 0; u < 2; ++u) {
       const int r = tid + u * (int)blockDim.x;
       if (r <= 32 * nblk) cf[r] = (r < nr && r > 0) ? cv[u] : 0.0;
-      if (r < 32 * nblk) gm[r] = r < nr ? gv[u] * gv[u] : 0.0;
     }
-    for (int r = tid + 2 * blockDim.x; r <= 32 * nblk; r += blockDim.x) {
-      const int rr = min(r, nr - 1);
-      const double c = A.rcoef[toff + rr], g = A.rgam[toff + rr];
-      cf[r] = (r < nr && r > 0) ? c : 0.0;
-      if (r < 32 * nblk) gm[r] = r < nr ? g * g : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < HB; ++u) {
-      const int idx = tid + u * (int)blockDim.x, i = idx / (32 * nblk), r = idx - i * 32 * nblk;
-      if (idx < nh) hls[idx] = (r < nr && i < nit) ? hv[u] : 0.f;
-    }
-    for (int idx = tid + HB * blockDim.x; idx < nh; idx += blockDim.x) {
-      const int i = idx / (32 * nblk), r = idx - i * 32 * nblk;
-      hls[idx] = (r < nr && i < nit) ? A.hl[(size_t)(A.item0 + c0 / 2 + i) * A.hl_stride + m + r] : 0.f;
-    }
+    for (int r = tid + 2 * blockDim.x; r <= 32 * nblk; r += blockDim.x)
+      cf[r] = (r < nr && r > 0) ? A.rcoef[toff + min(r, nr - 1)] : 0.0;
   }
   const double seed = j < h ? sd : 0.0;   // lanes past the last latitude run a zero chain
   __syncthreads();
@@ -2587,6 +2561,16 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
   double R1 = seed, R2 = 0.0;
   for (int blk = 0; blk < nblk; ++blk) {
     const int r0 = 32 * blk;
+    // gamma and h_l of this block's rows, loaded now, stored to LDS before the
+    // barrier, used by the combine after it
+    const int gr = min(r0 + (tid & 31), nr - 1);
+    const double gld = A.rgam[toff + gr];
+    float hld[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = min(tid + u * (int)blockDim.x, 8 * NT * 32 - 1), i = min(e >> 5, nit - 1);
+      hld[u] = A.hl[(size_t)(A.item0 + c0 / 2 + i) * A.hl_stride + m + min(r0 + (e & 31), nr - 1)];
+    }
     double cq[32];
 #pragma unroll
     for (int q = 0; q < 32; ++q) cq[q] = cf[r0 + q + 1];
@@ -2613,6 +2597,17 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
         for (int t = 0; t < NT; ++t) acc[par][t] = TR::mma(a, yb[s][par][t], acc[par][t]);
       }
     }
+    if (tid < 32) gsl[(blk & 1) * 32 + tid] = r0 + tid < nr ? gld : 0.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + u * (int)blockDim.x;
+      if (e < 8 * NT * 32) hsl[(blk & 1) * 8 * NT * 32 + e] = (r0 + (e & 31) < nr && (e >> 5) < nit) ? hld[u] : 0.f;
+    }
+    for (int e = tid + 2 * blockDim.x; e < 8 * NT * 32; e += blockDim.x) {  // one-wave workgroups of 16 items
+      const int i = e >> 5, r = r0 + (e & 31);
+      hsl[(blk & 1) * 8 * NT * 32 + e] =
+          (r < nr && i < nit) ? A.hl[(size_t)(A.item0 + c0 / 2 + i) * A.hl_stride + m + r] : 0.f;
+    }
     // wave partials, [wave][parity][column][row of the parity] (rows padded to 20)
     float* dp = Dp + (size_t)(blk & 1) * nw * 2 * Q.ncol * 20;
 #pragma unroll
@@ -2624,14 +2619,14 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
     __syncthreads();
     // b = gamma^2 h_l (sum over the waves), in the operand format, rows of one
     // parity contiguous; rows past the order's end are zero (gamma is zero there)
-    for (int idx = tid; idx < 2 * 16 * Q.ncol; idx += blockDim.x) {
+    for (int idx = tid; idx < ncomb; idx += blockDim.x) {
       const int pn = idx >> 4, rp = idx & 15;
       const int par = pn / Q.ncol, n = pn - par * Q.ncol;
-      const int r = r0 + 2 * rp + par;
       float part[8];
 #pragma unroll
       for (int w = 0; w < 8; ++w) part[w] = dp[(((size_t)min(w, nw - 1) * 2 + par) * Q.ncol + n) * 20 + rp];
-      const double sc = gm[r] * (double)hls[(n >> 1) * 32 * nblk + r];
+      const double g = gsl[(blk & 1) * 32 + 2 * rp + par];
+      const double sc = g * g * (double)hsl[(blk & 1) * 8 * NT * 32 + (n >> 1) * 32 + 2 * rp + par];
       float sum = part[0];
 #pragma unroll
       for (int w = 1; w < 8; ++w) sum += w < nw ? part[w] : 0.f;
