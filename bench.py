@@ -91,21 +91,59 @@ def time_solves(plan, p, q, steps, warmup, torch, profile=False):
     return dt, info[0], leg, rows
 
 
-C5_GRID = ("gl", 360, 720, 360)
-C4_GRIDS = [("gl", 90, 180, 90), ("gl", 180, 360, 180), ("gl", 360, 720, 360)]
-C4_COUNTS = [96, 96, 64]
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def oracle_ref(case):
+    """Stored oracle results of a workload (tests/golden/oracle_<case>.json, written by
+    tests/golden/make_oracle_refs.py from the oracle alone), or None."""
+    try:
+        with open(os.path.join(GOLDEN, f"oracle_{case}.json")) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b) if b not in (0, None) and math.isfinite(b) else None
+
+
+def pair_errors(S, info, ref_pairs, index_of=lambda k, pr: k, kr_min=1e-4):
+    """S and status against stored oracle pairs: how many pairs agree on which solves broke
+    down, and the largest S error over the pairs finite on both sides, and over those whose
+    three oracle solves also keep a kernel ratio min(K.)/max(K.) above kr_min (ten times the
+    float32 grading margin: the pairs whose S float32 can resolve)."""
+    status_agree, errs, errs_wc = 0, [], []
+    for k, pr in enumerate(ref_pairs):
+        i = index_of(k, pr)
+        gpu_b = [int(x["breakdown_iter"] > 0) for x in info[3 * i:3 * i + 3]]
+        orc_b = [int(x["breakdown"] > 0) for x in pr["solves"]]
+        status_agree += gpu_b == orc_b
+        if not any(orc_b) and not any(gpu_b) and math.isfinite(S[i]):
+            errs.append(rel(S[i], pr["S"]))
+            if min(x["kratio"] for x in pr["solves"]) > kr_min:
+                errs_wc.append(rel(S[i], pr["S"]))
+    return {"pairs_compared": len(ref_pairs), "status_agree": status_agree,
+            "finite_both": len(errs), "max_S_rel_err": max(errs) if errs else None,
+            "well_conditioned": len(errs_wc), "kratio_min": kr_min,
+            "max_S_rel_err_well_conditioned": max(errs_wc) if errs_wc else None}
+
+
+BATCH16_GRID = ("gl", 360, 720, 360)
+UNEVEN_GRIDS = [("gl", 90, 180, 90), ("gl", 180, 360, 180), ("gl", 360, 720, 360)]
+UNEVEN_COUNTS = [96, 96, 64]
 
 
 def bench_grad_batch(torch, precision, legendre, reps=1):
     """16 pairs on 360x720 Gauss-Legendre, t = 1e-3, balanced, T = 300: S and dS/dp per pair
     (forward, then the hand-written adjoint with checkpoint recompute)."""
     from paper_2605_18389_amd import Plan, synth
-    plan = Plan([C5_GRID], precision=precision, legendre=legendre)
+    plan = Plan([BATCH16_GRID], precision=precision, legendre=legendre)
     plan.autotune(0, 48)
     x, w = plan.grid_nodes(0)
     ps, qs = [], []
     for i in range(16):
-        p, q = synth.temperature_pair(synth.pair_seed(4, i), x, w, C5_GRID[2], K=8)
+        p, q = synth.temperature_pair(synth.pair_seed(4, i), x, w, BATCH16_GRID[2], K=8)
         ps.append(p)
         qs.append(q)
     p = torch.as_tensor(np.stack(ps), dtype=plan.dtype, device="cuda").contiguous()
@@ -118,8 +156,13 @@ def bench_grad_batch(torch, precision, legendre, reps=1):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     bad = sum(1 for i in range(16) if any(x["status"] == 17 for x in info[3 * i:3 * i + 3]))
-    return {"divergence_grad_per_s": 16 / dt, "ms_per_batch": dt * 1e3, "pairs": 16,
-            "pairs_with_breakdown": bad, "tuning": plan.get_tuning(0)}
+    out = {"divergence_grad_per_s": 16 / dt, "ms_per_batch": dt * 1e3, "pairs": 16,
+           "pairs_with_breakdown": bad, "tuning": plan.get_tuning(0)}
+    ref = oracle_ref("gl360_batch16_t1e-3")
+    if ref and len(ref["pairs"]) == 16:
+        out["vs_oracle"] = pair_errors(S, info, ref["pairs"])
+        out["oracle_pairs_with_breakdown"] = sum(1 for pr in ref["pairs"] if any(x["breakdown"] for x in pr["solves"]))
+    return out
 
 
 def bench_uneven_batch(torch, precision, legendre, reps=1):
@@ -127,15 +170,15 @@ def bench_uneven_batch(torch, precision, legendre, reps=1):
     log-uniform in [1e-4, 1e-2], half balanced and half unbalanced (tau in {0.1, 1, 10},
     masses 1 vs 1.05), T = 300, one divergence call (768 solves advanced together)."""
     from paper_2605_18389_amd import Plan, synth
-    plan = Plan(C4_GRIDS, precision=precision, legendre=legendre)
-    goi = sum(([k] * c for k, c in enumerate(C4_COUNTS)), [])
-    for k, c in enumerate(C4_COUNTS):
+    plan = Plan(UNEVEN_GRIDS, precision=precision, legendre=legendre)
+    goi = sum(([k] * c for k, c in enumerate(UNEVEN_COUNTS)), [])
+    for k, c in enumerate(UNEVEN_COUNTS):
         plan.autotune(k, 3 * c)
     prm = synth.batch_pair_params(synth.pair_seed(3, 0), len(goi))
     ps, qs = [], []
     for i, k in enumerate(goi):
         x, w = plan.grid_nodes(k)
-        p, q = synth.temperature_pair(synth.pair_seed(3, i), x, w, C4_GRIDS[k][2], K=8, q_mass=prm[i][2])
+        p, q = synth.temperature_pair(synth.pair_seed(3, i), x, w, UNEVEN_GRIDS[k][2], K=8, q_mass=prm[i][2])
         ps.append(p.ravel())
         qs.append(q.ravel())
     p = torch.as_tensor(np.concatenate(ps), dtype=plan.dtype, device="cuda")
@@ -150,8 +193,55 @@ def bench_uneven_batch(torch, precision, legendre, reps=1):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     bad = sum(1 for i in range(len(goi)) if any(x["status"] == 17 for x in info[3 * i:3 * i + 3]))
-    return {"divergences_per_s": len(goi) / dt, "ms_per_batch": dt * 1e3, "pairs": len(goi),
-            "pairs_with_breakdown": bad}
+    out = {"divergences_per_s": len(goi) / dt, "ms_per_batch": dt * 1e3, "pairs": len(goi),
+           "pairs_with_breakdown": bad, "tuning": [plan.get_tuning(k) for k in range(3)]}
+    ref = oracle_ref("uneven256_subset")
+    if ref:
+        out["vs_oracle_subset"] = pair_errors(S, info, ref["pairs"], lambda k, pr: pr["index"])
+    return out
+
+
+def bench_companion(torch, case, precision, steps=3):
+    """A stored oracle workload at full size: divergence (three solves advanced together)
+    per second, S against the oracle, statuses; unbalanced pairs also report the fixed-point
+    residual max |phi_T - phi_(T-C)| (C = 10) of the cross solve."""
+    from paper_2605_18389_amd import Plan, synth
+    ref = oracle_ref(case)
+    if ref is None:
+        return {"error": f"no stored oracle results for {case}"}
+    grid = tuple(ref["grid"])
+    plan = Plan([grid], precision=precision, legendre="recurrence")
+    x, w = plan.grid_nodes(0)
+    out = {}
+    for k, pr in enumerate(ref["pairs"]):
+        tau = math.inf if pr.get("tau") is None else pr["tau"]
+        if case == "cc721_uniform_eps0.1":
+            p, q = synth.uniform_pair_at(pr["seed"], plan.area(0))
+        else:
+            p, q = synth.temperature_pair(pr["seed"], x, w, grid[2], K=32 if grid[1] == 721 else 8,
+                                          q_mass=pr.get("q_mass", 1.0))
+        pd = torch.as_tensor(p, dtype=plan.dtype, device="cuda").contiguous()
+        qd = torch.as_tensor(q, dtype=plan.dtype, device="cuda").contiguous()
+        T = ref["T"]
+        plan.divergence(pd, qd, ref["eps"], tau, T=T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            S, info = plan.divergence(pd, qd, ref["eps"], tau, T=T)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        r = {"divergences_per_s": 1 / dt, "solve_iterations_per_s": 3 * T / dt, "T": T,
+             "S": S[0], "S_oracle": pr["S"], "S_rel_err": rel(S[0], pr["S"]),
+             "status": [x["status"] for x in info], "oracle_breakdown": [x["breakdown"] for x in pr["solves"]],
+             "cost_rel_err": [rel(x["cost"], y["cost"]) for x, y in zip(info, pr["solves"])]}
+        if not math.isinf(tau):
+            C = 10
+            phiT, _, _ = plan.sinkhorn(pd, qd, ref["eps"], tau, T=T, C=C)
+            phiC, _, _ = plan.sinkhorn(pd, qd, ref["eps"], tau, T=T - C, C=C)
+            r["fixed_point_residual"] = float((phiT - phiC).abs().max())
+            r["fixed_point_residual_note"] = "max |phi_T - phi_(T-10)| = eps max |log(u_T / u_(T-10))|"
+        out["balanced" if math.isinf(tau) else f"tau{tau:g}"] = r
+    return out
 
 
 def bench_healpix(torch, nside, precision, T=200):
@@ -207,11 +297,13 @@ def bench_climate_attribution(torch, precision, npairs=8, T=300):
                                         if any(x["status"] == 17 for x in info[3 * i:3 * i + 3]))}
 
 
-def cpu_baseline(budget_s, gpu_heat=None):
+def cpu_baseline(budget_s, gpu_heat=None, one_thread_budget_s=0.0):
     """FP64 oracle on host cores: iterations/s of Alg. 1 on the same workload.
 
     With gpu_heat ({name: K p computed by a GPU plan}) also returns each
-    plan's relative L2 error against the oracle's heat apply of the same p."""
+    plan's relative L2 error against the oracle's heat apply of the same p.
+    With one_thread_budget_s > 0 the oracle is also timed with BLAS limited to
+    one thread."""
     import oracle as O
     from paper_2605_18389_amd import synth
     try:
@@ -234,9 +326,25 @@ def cpu_baseline(budget_s, gpu_heat=None):
     t0 = time.perf_counter()
     O.sinkhorn(p, q, g, 4 * T_HEAT, T=n)
     dt = time.perf_counter() - t0
-    return ({"value": n / dt, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
-             "sample": f"{n} Alg. 1 iterations (2 heat applies each) of the 721x1440 pair, "
-                       f"float64 NumPy, Legendre table built beforehand"}, errors)
+    res = {"value": n / dt, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{n} Alg. 1 iterations (2 heat applies each) of the 721x1440 pair, "
+                     f"float64 NumPy, Legendre table built beforehand"}
+    if one_thread_budget_s > 0:
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                t0 = time.perf_counter()
+                O.sinkhorn(p, q, g, 4 * T_HEAT, T=1)
+                one = time.perf_counter() - t0
+                n1 = max(1, int(one_thread_budget_s / max(one, 1e-3)))
+                t0 = time.perf_counter()
+                O.sinkhorn(p, q, g, 4 * T_HEAT, T=n1)
+                d1 = time.perf_counter() - t0
+            res["one_thread"] = {"value": n1 / d1, "unit": "iterations/s", "cores": 1,
+                                 "sample": f"{n1} iterations, BLAS limited to one thread"}
+        except Exception as e:
+            res["one_thread"] = {"error": str(e)}
+    return res, errors
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_18389_amd", "csrc", "kernels.hip")
@@ -338,7 +446,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x3", "fp64"])
     ap.add_argument("--legendre", default="recurrence", choices=["recurrence", "table"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -348,6 +456,9 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="reduce the two counter runs to profiles/traffic.json")
     ap.add_argument("--pmc-command", default="", help="command line recorded in profiles/traffic.json")
+    ap.add_argument("--only", choices=["grad16", "uneven256"],
+                    help="run one batched workload at --precision / --legendre and print its entry "
+                         "(the command the batched kernel profiles are taken over)")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_command)
@@ -361,6 +472,11 @@ def main():
 
     if args.traffic_probe:
         traffic_probe()
+        return
+    if args.only:
+        import torch
+        fn = bench_grad_batch if args.only == "grad16" else bench_uneven_batch
+        print(json.dumps({args.only: fn(torch, args.precision, args.legendre)}), flush=True)
         return
 
     import torch
@@ -398,7 +514,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "sinkhorn_cc721x1440_L720_t1e-4_balanced_T1000",
                    "grid": "Clenshaw-Curtis 721x1440", "L": 720, "iterations_per_step": ITERS,
@@ -412,7 +528,8 @@ def main():
     if not args.no_secondary:
         sec = {}
         other = "table" if args.legendre == "recurrence" else "recurrence"
-        for prec, legm in ((args.precision, other), ("bf16", "table")):
+        for prec, legm in ((args.precision, other), ("bf16", "table"), ("fp64", "recurrence"),
+                           ("bf16x3", "recurrence")):
             if (prec, legm) == (args.precision, args.legendre):
                 continue
             try:
@@ -421,8 +538,10 @@ def main():
                 pp, qq, _, _ = make_inputs(pl, torch)
                 d2, _, _, _ = time_solves(pl, pp, qq, 2, 1, torch)
                 _, _, lg, _ = time_solves(pl, pp, qq, 1, 0, torch, profile=True)
+                _, _, inf2 = pl.sinkhorn(pp, qq, 4 * T_HEAT, T=ITERS, potentials=False)
                 sec[f"{prec}_{legm}"] = {"iterations_per_s": 2 * ITERS / d2,
-                                         "legendre_avg_launch_ms": lg[1] / max(lg[0], 1)}
+                                         "legendre_avg_launch_ms": lg[1] / max(lg[0], 1),
+                                         "status": inf2[0]["status"], "breakdown_iter": inf2[0]["breakdown_iter"]}
                 del pl
             except Exception as e:  # report, do not hide
                 sec[f"{prec}_{legm}"] = {"error": str(e)}
@@ -440,6 +559,17 @@ def main():
                                                  "ms_per_divergence": d3 * 1e3}
         except Exception as e:
             sec["divergence_fp32_recurrence"] = {"error": str(e)}
+        comp = {}
+        for case, precs in (("cc721_uniform_eps0.1", ("fp32", "fp64")), ("cc721_temperature_t1e-2", ("fp32", "fp64", "bf16x3")),
+                            ("gl180_temperature_t1e-2", ("fp32", "fp64", "bf16x3"))):
+            for prec in precs:
+                try:
+                    log(f"[bench] companion {case} {prec}")
+                    comp[f"{case}_{prec}"] = bench_companion(torch, case, prec)
+                except Exception as e:
+                    comp[f"{case}_{prec}"] = {"error": str(e)}
+                torch.cuda.empty_cache()
+        out["companions"] = comp
         for prec in ("fp32", "fp64"):
             try:
                 log(f"[bench] climate attribution {prec}")
@@ -457,8 +587,9 @@ def main():
                 torch.cuda.empty_cache()
         out["secondary"] = sec
         bat = {}
-        for prec, legm in (("fp32", "recurrence"), ("fp32", "table"), ("bf16", "table")):
-            key = f"{prec}_{'mfma' if legm == 'table' else 'recurrence'}"
+        for prec, legm in (("fp32", "recurrence"), ("bf16x3", "recurrence"), ("bf16", "recurrence"),
+                           ("bf16", "table")):
+            key = f"{prec}_{'table_mfma' if legm == 'table' else 'recurrence'}"
             try:
                 log(f"[bench] batched gradient {key}")
                 bat[f"grad_16x360x720_{key}"] = bench_grad_batch(torch, prec, legm)
@@ -472,7 +603,8 @@ def main():
         log("[bench] heat applies for the error report")
         gpu_heat = {}
         _, _, p_np, _ = make_inputs(plan, torch)
-        for prec, legm in (("fp32", "recurrence"), ("bf16", "table"), ("fp64", "recurrence")):
+        for prec, legm in (("fp32", "recurrence"), ("bf16", "table"), ("fp64", "recurrence"),
+                           ("bf16x3", "recurrence"), ("bf16", "recurrence")):
             try:
                 pl = plan if (prec, legm) == (args.precision, args.legendre) else \
                     Plan([GRID], precision=prec, legendre=legm)
@@ -483,7 +615,7 @@ def main():
                 log(f"[bench] heat apply {prec} {legm} failed: {e}")
             torch.cuda.empty_cache()
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"], errs = cpu_baseline(args.cpu_budget, gpu_heat)
+        out["cpu_baseline"], errs = cpu_baseline(args.cpu_budget, gpu_heat, one_thread_budget_s=8.0)
         out["heat_apply_rel_l2_vs_oracle"] = errs
     print(json.dumps(out), flush=True)
 

@@ -78,9 +78,10 @@ def uniform_field(rng, x, w, nlon, total=1.0):
     return _normalise(f, w, nlon, total)
 
 
-def pair_seed(config_index, pair_index):
-    """Seed of pair i of workload c: 1000 c + i."""
-    return 1000 * config_index + pair_index
+def pair_seed(workload_id, pair_index):
+    """Seed of pair i of the workload numbered w: 1000 w + i (each workload draws its
+    pairs from its own block of seeds)."""
+    return 1000 * workload_id + pair_index
 
 
 def vmf_pair(seed, x, w, nlon, K=4):

@@ -7,26 +7,28 @@ the HIP library.  The GPU tests and the benchmark read these files; the cases
 are the benchmarked workloads at their full sizes, which the oracle needs
 minutes to hours for (so they cannot run inside a test):
 
-* c2_t1e-2        180x360 Gauss-Legendre (L = 180), the 1-degree temperature-like
+* gl180_temperature_t1e-2   180x360 Gauss-Legendre (L = 180), the 1-degree temperature-like
                   pair at t = 1e-2, T = 500, balanced and unbalanced (tau = 1,
                   masses 1 vs 1.05): a heat time at which the cross solves stay
                   clear of the positivity breakdown (App. C.4).
-* c3_uniform      721x1440 Clenshaw-Curtis (L = 720), the paper's runtime
+* cc721_uniform_eps0.1      721x1440 Clenshaw-Curtis (L = 720), the paper's runtime
                   workload (a pair of i.i.d. uniform fields normalised by the
                   area weights, eps = 0.1, balanced), T = 100.
-* c3_temperature  721x1440, the 32-anomaly temperature-like pair at t = 1e-2,
+* cc721_temperature_t1e-2   721x1440, the 32-anomaly temperature-like pair at t = 1e-2,
                   T = 100, balanced: a heat time at which the solves stay well
                   clear of the breakdown (at t = 4e-3 the cross solve's kernel
                   ratio falls to 7e-5).
-* c4_subset       pairs of the uneven 256-pair batch (90x180, 180x360, 360x720
+* uneven256_subset          pairs of the uneven 256-pair batch (90x180, 180x360, 360x720
                   Gauss-Legendre): per grid and per kind (balanced, tau = 0.1,
                   1, 10) the first pair drawn and the one with the largest heat
                   time, at their drawn parameters, T = 300.
-* c5              the 16 pairs at 360x720, t = 1e-3, balanced, T = 300: every
+* gl360_batch16_t1e-3       the 16 pairs at 360x720, t = 1e-3, balanced, T = 300: every
                   pair's divergence and solves; on the two pairs with the
                   largest kernel ratio also central differences of S along
                   mass-preserving directions (h = 1e-4) and the envelope gradient
                   (Sec. 4.2.2) at sampled points.
+* gl360_pairs01_t1e-2       pairs 0 and 1 of that batch at t = 1e-2 (cross solves clear of
+                  the breakdown at T = 300), with the same gradient references.
 
 Per solve the file keeps the Alg. 1 return value, e_marg, the breakdown
 iteration, the kernel ratio and its per-iteration history (the grading rules
@@ -92,7 +94,7 @@ def write(case, data):
     log(f"wrote {path}")
 
 
-def case_c2():
+def case_gl180_temperature():
     grid = ("gl", 180, 360, 180)
     g = O.make_grid(*grid)
     idx = synth.sample_indices(77, g.n, NSAMPLE)
@@ -104,11 +106,11 @@ def case_c2():
         rec, _ = divergence_record(p, q, g, 4 * t, tau, T, idx)
         rec.update({"tau": None if math.isinf(tau) else tau, "q_mass": qm, "seed": synth.pair_seed(1, 0)})
         out["pairs"].append(rec)
-        log(f"c2 tau={tau}: S={rec['S']:.12e} ({time.time() - t0:.0f} s)")
-    write("c2_t1e-2", out)
+        log(f"gl180 tau={tau}: S={rec['S']:.12e} ({time.time() - t0:.0f} s)")
+    write("gl180_temperature_t1e-2", out)
 
 
-def case_c3_uniform():
+def case_cc721_uniform():
     grid = ("cc", 721, 1440, 720)
     g = O.make_grid(*grid)
     idx = synth.sample_indices(78, g.n, NSAMPLE)
@@ -117,11 +119,11 @@ def case_c3_uniform():
     t0 = time.time()
     rec, _ = divergence_record(p, q, g, eps, math.inf, T, idx)
     rec.update({"tau": None, "seed": seed})
-    log(f"c3 uniform: S={rec['S']:.12e} e_marg={[s['err'] for s in rec['solves']]} ({time.time() - t0:.0f} s)")
-    write("c3_uniform", {"grid": grid, "eps": eps, "T": T, "sample_idx": idx.tolist(), "pairs": [rec]})
+    log(f"cc721 uniform: S={rec['S']:.12e} e_marg={[s['err'] for s in rec['solves']]} ({time.time() - t0:.0f} s)")
+    write("cc721_uniform_eps0.1", {"grid": grid, "eps": eps, "T": T, "sample_idx": idx.tolist(), "pairs": [rec]})
 
 
-def case_c3_temperature():
+def case_cc721_temperature():
     grid = ("cc", 721, 1440, 720)
     g = O.make_grid(*grid)
     idx = synth.sample_indices(79, g.n, NSAMPLE)
@@ -130,20 +132,20 @@ def case_c3_temperature():
     t0 = time.time()
     rec, _ = divergence_record(p, q, g, 4 * t, math.inf, T, idx)
     rec.update({"tau": None, "seed": seed})
-    log(f"c3 temperature: S={rec['S']:.12e} ({time.time() - t0:.0f} s)")
-    write("c3_temperature", {"grid": grid, "t": t, "eps": 4 * t, "T": T, "sample_idx": idx.tolist(),
+    log(f"cc721 temperature: S={rec['S']:.12e} ({time.time() - t0:.0f} s)")
+    write("cc721_temperature_t1e-2", {"grid": grid, "t": t, "eps": 4 * t, "T": T, "sample_idx": idx.tolist(),
                              "pairs": [rec]})
 
 
-C4_GRIDS = [("gl", 90, 180, 90), ("gl", 180, 360, 180), ("gl", 360, 720, 360)]
-C4_COUNTS = [96, 96, 64]
+UNEVEN_GRIDS = [("gl", 90, 180, 90), ("gl", 180, 360, 180), ("gl", 360, 720, 360)]
+UNEVEN_COUNTS = [96, 96, 64]
 
 
-def c4_subset_indices():
+def uneven256_subset_indices():
     """Per grid of the batch and per kind (balanced, tau = 0.1, 1, 10): the first
     pair drawn and the pair with the largest heat time (the best resolved)."""
-    prm = synth.batch_pair_params(synth.pair_seed(3, 0), sum(C4_COUNTS))
-    goi = sum(([k] * c for k, c in enumerate(C4_COUNTS)), [])
+    prm = synth.batch_pair_params(synth.pair_seed(3, 0), sum(UNEVEN_COUNTS))
+    goi = sum(([k] * c for k, c in enumerate(UNEVEN_COUNTS)), [])
     pick = []
     for k in range(3):
         for want in (math.inf, 0.1, 1.0, 10.0):
@@ -154,11 +156,11 @@ def c4_subset_indices():
     return sorted(pick), prm, goi
 
 
-def case_c4():
-    pick, prm, goi = c4_subset_indices()
-    grids = [O.make_grid(*gr) for gr in C4_GRIDS]
+def case_uneven256_subset():
+    pick, prm, goi = uneven256_subset_indices()
+    grids = [O.make_grid(*gr) for gr in UNEVEN_GRIDS]
     T = 300
-    out = {"grids": C4_GRIDS, "counts": C4_COUNTS, "T": T, "pairs": []}
+    out = {"grids": UNEVEN_GRIDS, "counts": UNEVEN_COUNTS, "T": T, "pairs": []}
     for i in pick:
         g = grids[goi[i]]
         t, tau, qm = prm[i]
@@ -169,13 +171,13 @@ def case_c4():
         rec.update({"index": i, "grid": goi[i], "t": t, "eps": 4 * t, "tau": None if math.isinf(tau) else tau,
                     "q_mass": qm, "sample_idx": idx.tolist()})
         out["pairs"].append(rec)
-        log(f"c4 pair {i} grid {goi[i]} t={t:.3e} tau={tau}: S={rec['S']:.6e} "
+        log(f"uneven256 pair {i} grid {goi[i]} t={t:.3e} tau={tau}: S={rec['S']:.6e} "
             f"breakdown={[s['breakdown'] for s in rec['solves']]} kratio={[s['kratio'] for s in rec['solves']]} "
             f"({time.time() - t0:.0f} s)")
-    write("c4_subset", out)
+    write("uneven256_subset", out)
 
 
-def case_c5():
+def case_gl360_batch16():
     grid = ("gl", 360, 720, 360)
     g = O.make_grid(*grid)
     a = g.area
@@ -195,9 +197,9 @@ def case_c5():
         rec["index"] = i
         out["pairs"].append(rec)
         sols.append(solves)
-        log(f"c5 pair {i}: S={rec['S']:.9e} kratio={[s['kratio'] for s in rec['solves']]} "
+        log(f"gl360 batch pair {i}: S={rec['S']:.9e} kratio={[s['kratio'] for s in rec['solves']]} "
             f"breakdown={[s['breakdown'] for s in rec['solves']]} ({time.time() - t0:.0f} s)")
-        write("c5", out)   # checkpoint: a long run keeps what it has
+        write("gl360_batch16_t1e-3", out)   # checkpoint: a long run keeps what it has
     # the two pairs whose (p,q) and (p,p) solves (those that depend on p) have the largest kernel ratio
     cond = [min(r["solves"][0]["kratio"], r["solves"][1]["kratio"]) if all(s["breakdown"] == 0 for s in r["solves"])
             else -math.inf for r in out["pairs"]]
@@ -216,13 +218,45 @@ def case_c5():
         fd[str(i)] = {"h": h, "direction_seed": synth.pair_seed(5, i), "ndir": ndir,
                       "fd": [float(v) for v in vals],
                       "envelope_centred_sample": [float(x) for x in (c.ravel()[idx] - mean)]}
-        log(f"c5 FD pair {i}: {fd[str(i)]['fd']} ({time.time() - t0:.0f} s)")
+        log(f"gl360 batch FD pair {i}: {fd[str(i)]['fd']} ({time.time() - t0:.0f} s)")
         out["fd"] = fd
-        write("c5", out)
+        write("gl360_batch16_t1e-3", out)
 
 
-CASES = {"c2": case_c2, "c3_uniform": case_c3_uniform, "c3_temperature": case_c3_temperature,
-         "c4": case_c4, "c5": case_c5}
+def case_gl360_pairs01():
+    """Pairs 0 and 1 of the 360x720 batch at t = 1e-2 (the cross solves stay clear
+    of the breakdown at T = 300): divergence, solves, central differences along
+    mass-preserving directions and the envelope gradient at sampled points."""
+    grid = ("gl", 360, 720, 360)
+    g = O.make_grid(*grid)
+    a = g.area
+    idx = synth.sample_indices(82, g.n, NSAMPLE)
+    t, T, h, ndir = 1e-2, 300, 1e-4, 4
+    eps = 4 * t
+    mass = O.sinkhorn.__globals__["mass"]
+    out = {"grid": grid, "t": t, "eps": eps, "T": T, "sample_idx": idx.tolist(), "pairs": [], "fd": {}}
+    for i in (0, 1):
+        p, q = synth.temperature_pair(synth.pair_seed(4, i), g.x, g.w, g.nlon, K=8)
+        t0 = time.time()
+        rec, (rpq, rpp, _) = divergence_record(p, q, g, eps, math.inf, T, idx)
+        rec["index"] = i
+        out["pairs"].append(rec)
+        env = O.envelope_gradient(rpq, rpp, g, eps, mass(p, g), mass(q, g))
+        c = env / a
+        mean = float((a * c).sum() / a.sum())
+        D = synth.mass_preserving_directions(synth.pair_seed(5, i), p, a, ndir)
+        vals = O.fd_directional(p, q, D, g, eps, T, h=h)
+        out["fd"][str(i)] = {"h": h, "direction_seed": synth.pair_seed(5, i), "ndir": ndir,
+                             "fd": [float(v) for v in vals],
+                             "envelope_centred_sample": [float(x) for x in (c.ravel()[idx] - mean)]}
+        log(f"gl360 t=1e-2 pair {i}: S={rec['S']:.9e} kratio={[s['kratio'] for s in rec['solves']]} "
+            f"fd={out['fd'][str(i)]['fd']} ({time.time() - t0:.0f} s)")
+        write("gl360_pairs01_t1e-2", out)
+
+
+CASES = {"gl180_temperature_t1e-2": case_gl180_temperature, "cc721_uniform_eps0.1": case_cc721_uniform,
+         "cc721_temperature_t1e-2": case_cc721_temperature, "uneven256_subset": case_uneven256_subset,
+         "gl360_batch16_t1e-3": case_gl360_batch16, "gl360_pairs01_t1e-2": case_gl360_pairs01}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(CASES)

@@ -73,84 +73,84 @@ def grade_potentials(name, phi, psi, r, idx, eps, prec):
         assert d.max() <= tol
 
 
-C2_LEG = [("fp32", "recurrence"), ("fp32", "table"), ("fp64", "recurrence")]
+GL180_FORMS = [("fp32", "recurrence"), ("fp32", "table"), ("fp64", "recurrence")]
 
 
-@pytest.mark.parametrize("prec,legendre", C2_LEG)
+@pytest.mark.parametrize("prec,legendre", GL180_FORMS)
 @pytest.mark.parametrize("k", [0, 1], ids=["balanced", "unbalanced"])
-def test_c2_resolved_divergence(k, prec, legendre):
+def test_gl180_resolved_divergence(k, prec, legendre):
     """180x360 temperature-like pair at t = 1e-2, T = 500: balanced, and unbalanced
     with tau = 1 and masses 1 vs 1.05.  All three solves stay clear of the
     breakdown, so S is graded at the stated bound; the potentials of the cross
     solve are compared at the sample points."""
-    ref = _ref("c2_t1e-2")
+    ref = _ref("gl180_temperature_t1e-2")
     pr = ref["pairs"][k]
     tau = math.inf if pr["tau"] is None else pr["tau"]
-    announce(f"C2 t=1e-2 tau={tau} {prec} {legendre}")
+    announce(f"gl180 t=1e-2 tau={tau} {prec} {legendre}")
     grid = tuple(ref["grid"])
     g = O.make_grid(*grid)
     p, q = synth.temperature_pair(pr["seed"], g.x, g.w, g.nlon, K=8, q_mass=pr["q_mass"])
     P = _plan([grid], prec, legendre)
     pd, qd = to_dev(p, P.dtype), to_dev(q, P.dtype)
     S, info = P.divergence(pd, qd, ref["eps"], tau, T=ref["T"])
-    graded, _ = grade_pair(f"C2 {prec} {legendre} tau={tau}", S[0], info, pr, prec)
+    graded, _ = grade_pair(f"gl180 {prec} {legendre} tau={tau}", S[0], info, pr, prec)
     assert all(graded)
     phi, psi, inf = P.sinkhorn(pd, qd, ref["eps"], tau, T=ref["T"])
-    grade_potentials("C2 pq", phi, psi, pr["solves"][0], np.asarray(ref["sample_idx"]), ref["eps"], prec)
+    grade_potentials("gl180 pq", phi, psi, pr["solves"][0], np.asarray(ref["sample_idx"]), ref["eps"], prec)
 
 
-C3 = ("cc", 721, 1440, 720)
+CC721 = ("cc", 721, 1440, 720)
 
 
 @pytest.mark.parametrize("prec,legendre", [("fp32", "recurrence"), ("fp64", "recurrence"),
                                            ("bf16x3", "recurrence")])
-def test_c3_resolved_divergence(prec, legendre):
+def test_cc721_resolved_divergence(prec, legendre):
     """0.25-degree grid (721 x 1440, L = 720), the 32-anomaly pair at t = 1e-2, T = 100:
     a heat time at which all three solves stay clear of the breakdown (kernel ratios
     5e-3 and above).  The three solves advance together, as the benchmark runs them."""
-    ref = _ref("c3_temperature")
+    ref = _ref("cc721_temperature_t1e-2")
     pr = ref["pairs"][0]
-    announce(f"C3 t=1e-2 {prec} {legendre}")
-    g = O.make_grid(*C3)
+    announce(f"CC721 t=1e-2 {prec} {legendre}")
+    g = O.make_grid(*CC721)
     p, q = synth.temperature_pair(pr["seed"], g.x, g.w, g.nlon, K=32)
-    P = _plan([C3], prec, legendre)
+    P = _plan([CC721], prec, legendre)
     pd, qd = to_dev(p, P.dtype), to_dev(q, P.dtype)
     S, info = P.divergence(pd, qd, ref["eps"], T=ref["T"])
-    graded, _ = grade_pair(f"C3 {prec}", S[0], info, pr, prec)
+    graded, _ = grade_pair(f"CC721 {prec}", S[0], info, pr, prec)
     assert all(graded)
     phi, psi, _ = P.sinkhorn(pd, qd, ref["eps"], T=ref["T"])
-    grade_potentials("C3 pq", phi, psi, pr["solves"][0], np.asarray(ref["sample_idx"]), ref["eps"], prec)
+    grade_potentials("CC721 pq", phi, psi, pr["solves"][0], np.asarray(ref["sample_idx"]), ref["eps"], prec)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c3_runtime_workload_divergence(prec):
+def test_cc721_runtime_workload_divergence(prec):
     """The paper's runtime workload on the 0.25-degree grid: two i.i.d. uniform fields
     normalised by the area weights, eps = 0.1, balanced, T = 100.  S (4.8e-6) is about
     45 000 times smaller than each cost, so float32 fields cannot carry it to 1e-4
     relative (that needs 2e-9 per cost); float32 is held to the rounding of the costs
     instead, |dS| <= 10 u (|R_pq| + (|R_pp| + |R_qq|)/2), and float64 to 1e-10."""
-    ref = _ref("c3_uniform")
+    ref = _ref("cc721_uniform_eps0.1")
     pr = ref["pairs"][0]
-    announce(f"C3 uniform eps=0.1 {prec}")
-    g = O.make_grid(*C3)
+    announce(f"CC721 uniform eps=0.1 {prec}")
+    g = O.make_grid(*CC721)
     p, q = synth.uniform_pair_at(pr["seed"], g.area)
-    P = _plan([C3], prec, "recurrence")
+    P = _plan([CC721], prec, "recurrence")
     S, info = P.divergence(to_dev(p, P.dtype), to_dev(q, P.dtype), ref["eps"], T=ref["T"])
     bound = None
     if prec == "fp32":
         from parity import U
         R = [abs(s["cost"]) for s in pr["solves"]]
         bound = 10 * U["fp32"] * (R[0] + 0.5 * (R[1] + R[2])) / abs(pr["S"])
-    graded, err = grade_pair(f"C3 uniform {prec}", S[0], info, pr, prec, S_bound=bound)
+    graded, err = grade_pair(f"CC721 uniform {prec}", S[0], info, pr, prec, S_bound=bound)
     assert all(graded) and err is not None
 
 
-C4_GRIDS = [("gl", 90, 180, 90), ("gl", 180, 360, 180), ("gl", 360, 720, 360)]
-C4_COUNTS = [96, 96, 64]
+UNEVEN_GRIDS = [("gl", 90, 180, 90), ("gl", 180, 360, 180), ("gl", 360, 720, 360)]
+UNEVEN_COUNTS = [96, 96, 64]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_c4_uneven_batch_subset(prec):
+def test_uneven256_batch_subset(prec):
     """The whole uneven batch (256 pairs on three grids, 768 solves advanced together,
     one divergence call, Legendre shapes from the autotuner, T = 300) in the launch
     configuration the benchmark times; 23 of its pairs -- per grid and per kind
@@ -158,14 +158,14 @@ def test_c4_uneven_batch_subset(prec):
     compared with the oracle: status of every solve, costs and S of pairs outside the
     margin (tests/parity.py s_bound: for float32 the stated bound when every solve
     is at least 10x above the margin, else the summed cost tolerances)."""
-    ref = _ref("c4_subset")
-    announce(f"C4 uneven batch {prec}")
-    P = _plan(C4_GRIDS, prec, "recurrence")
-    goi = sum(([k] * c for k, c in enumerate(C4_COUNTS)), [])
-    for k, c in enumerate(C4_COUNTS):
+    ref = _ref("uneven256_subset")
+    announce(f"uneven256 uneven batch {prec}")
+    P = _plan(UNEVEN_GRIDS, prec, "recurrence")
+    goi = sum(([k] * c for k, c in enumerate(UNEVEN_COUNTS)), [])
+    for k, c in enumerate(UNEVEN_COUNTS):
         P.autotune(k, 3 * c)
     prm = synth.batch_pair_params(synth.pair_seed(3, 0), len(goi))
-    gs = [O.make_grid(*gr) for gr in C4_GRIDS]
+    gs = [O.make_grid(*gr) for gr in UNEVEN_GRIDS]
     ps, qs = [], []
     for i, k in enumerate(goi):
         p, q = synth.temperature_pair(synth.pair_seed(3, i), gs[k].x, gs[k].w, gs[k].nlon, K=8, q_mass=prm[i][2])
@@ -180,27 +180,27 @@ def test_c4_uneven_batch_subset(prec):
         i = pr["index"]
         assert goi[i] == pr["grid"] and abs(prm[i][0] - pr["t"]) < 1e-15
         inf = info[3 * i:3 * i + 3]
-        graded, err = grade_pair(f"C4 pair {i} grid {pr['grid']} t={pr['t']:.2e} tau={pr['tau']}", S[i], inf, pr,
+        graded, err = grade_pair(f"uneven256 pair {i} grid {pr['grid']} t={pr['t']:.2e} tau={pr['tau']}", S[i], inf, pr,
                                  prec)
         if all(graded):
             n_graded += 1
             n_stated += well_conditioned(pr["solves"], prec)
-    print(f"  C4 {prec}: {n_graded} of {len(ref['pairs'])} pairs value-graded, {n_stated} at the stated S bound",
+    print(f"  uneven256 {prec}: {n_graded} of {len(ref['pairs'])} pairs value-graded, {n_stated} at the stated S bound",
           flush=True)
     assert n_graded >= 10
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
-def test_c2_matrix_core_forms(prec):
+def test_gl180_matrix_core_forms(prec):
     """The 180x360 pair at t = 1e-2 on the bfloat16 forms of the recurrence path: status
     against the oracle on every solve; values where the margin allows."""
-    ref = _ref("c2_t1e-2")
+    ref = _ref("gl180_temperature_t1e-2")
     for pr in ref["pairs"]:
         tau = math.inf if pr["tau"] is None else pr["tau"]
-        announce(f"C2 {prec} tau={tau}")
+        announce(f"gl180 {prec} tau={tau}")
         grid = tuple(ref["grid"])
         g = O.make_grid(*grid)
         p, q = synth.temperature_pair(pr["seed"], g.x, g.w, g.nlon, K=8, q_mass=pr["q_mass"])
         P = _plan([grid], prec, "recurrence")
         S, info = P.divergence(to_dev(p, P.dtype), to_dev(q, P.dtype), ref["eps"], tau, T=ref["T"])
-        grade_pair(f"C2 {prec} tau={tau}", S[0], info, pr, prec)
+        grade_pair(f"gl180 {prec} tau={tau}", S[0], info, pr, prec)

@@ -32,11 +32,11 @@ def _plan(grids, precision, legendre="table"):
     return Plan(grids, precision=precision, legendre=legendre)
 
 
-C1 = ("gl", 32, 64, 32)
+GL32 = ("gl", 32, 64, 32)
 
 
-def _c1_pair(seed):
-    g = O.make_grid(*C1)
+def _gl32_pair(seed):
+    g = O.make_grid(*GL32)
     p, q = synth.vmf_pair(synth.pair_seed(0, seed), g.x, g.w, g.nlon, K=4)
     return g, p, q
 
@@ -44,18 +44,18 @@ def _c1_pair(seed):
 @pytest.mark.parametrize("legendre", ["table", "recurrence"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("t", [1e-2, 4e-2])
-def test_c1_divergence_fp64(t, seed, legendre):
+def test_gl32_divergence_fp64(t, seed, legendre):
     """32x64 vMF pair, 200 iterations: literal t = 1e-2 and the resolved t = 4e-2."""
-    announce(f"C1 t={t} seed={seed} {legendre}")
-    g, p, q = _c1_pair(seed)
+    announce(f"GL32 t={t} seed={seed} {legendre}")
+    g, p, q = _gl32_pair(seed)
     eps = 4 * t
-    P = _plan([C1], "fp64", legendre)
+    P = _plan([GL32], "fp64", legendre)
     pd, qd = to_dev(p, P.dtype), to_dev(q, P.dtype)
     S, info = P.divergence(pd, qd, eps, T=200)
     Sref, solves = O.divergence(p, q, g, eps, T=200, return_solves=True)
     graded = [check_status(inf, r, "fp64") for inf, r in zip(info, solves)]
     for name, inf, r, gr in zip(("pq", "pp", "qq"), info, solves, graded):
-        report(f"C1 t={t} seed={seed} {legendre} {name}", graded=gr, kratio=r["kratio"],
+        report(f"GL32 t={t} seed={seed} {legendre} {name}", graded=gr, kratio=r["kratio"],
                oracle_breakdown=r["breakdown"], gpu_breakdown=inf["breakdown_iter"],
                cost=inf["cost"], cost_ref=r["cost"], err=inf["err"], err_ref=r["err"])
         if gr:
@@ -65,7 +65,7 @@ def test_c1_divergence_fp64(t, seed, legendre):
             assert abs(inf["err"] - r["err"]) <= 1e-3 * r["err"] + 10 * tol
     if all(graded):
         tol = max(tolerance(r, "fp64") for r in solves)
-        report(f"C1 t={t} seed={seed} {legendre} S", S=S[0], S_ref=Sref, tol=tol)
+        report(f"GL32 t={t} seed={seed} {legendre} S", S=S[0], S_ref=Sref, tol=tol)
         assert abs(S[0] - Sref) <= tol * abs(Sref)
         phi, psi, inf = P.sinkhorn(pd, qd, eps, T=200)
         assert inf[0]["iters"] == 200
@@ -75,21 +75,21 @@ def test_c1_divergence_fp64(t, seed, legendre):
 
 def test_self_divergence_is_exactly_zero():
     announce("S(a,a) == 0")
-    g, p, _ = _c1_pair(0)
+    g, p, _ = _gl32_pair(0)
     for prec in ("fp64", "fp32"):
-        P = _plan([C1], prec)
+        P = _plan([GL32], prec)
         pd = to_dev(p, P.dtype)
         S, _ = P.divergence(pd, pd.clone(), 0.16, T=50)
         assert S[0] == 0.0
 
 
 @pytest.mark.parametrize("tau", [math.inf, 1.0])
-def test_c1b_unbalanced_and_balanced_potentials_fp64(tau):
-    announce(f"C1b potentials tau={tau}")
-    g = O.make_grid(*C1)
+def test_gl32_resolved_unbalanced_and_balanced_potentials_fp64(tau):
+    announce(f"gl32 resolved potentials tau={tau}")
+    g = O.make_grid(*GL32)
     p, q = synth.temperature_pair(7, g.x, g.w, g.nlon, K=8, q_mass=1.0 if math.isinf(tau) else 1.05)
     eps = 0.16
-    P = _plan([C1], "fp64", "recurrence")
+    P = _plan([GL32], "fp64", "recurrence")
     phi, psi, info = P.sinkhorn(to_dev(p, P.dtype), to_dev(q, P.dtype), eps, tau, T=120)
     r = O.sinkhorn(p, q, g, eps, tau, T=120)
     assert rel_l2(to_np(phi).reshape(p.shape), r["phi"]) < 1e-10
@@ -110,26 +110,26 @@ def test_early_exit_matches_oracle():
     assert rel_l2(to_np(phi).reshape(p.shape), r["phi"]) < 1e-10
 
 
-C2 = ("gl", 180, 360, 180)
+GL180 = ("gl", 180, 360, 180)
 
 
 @pytest.mark.parametrize("legendre", ["table", "recurrence"])
 @pytest.mark.parametrize("tau", [math.inf, 1.0])
-def test_c2_divergence_fp32(tau, legendre):
+def test_gl180_divergence_fp32(tau, legendre):
     """1-degree pair, t = 1e-3, 500 iterations, float32, balanced and unbalanced (rho = 1, masses 1 vs 1.05)."""
-    announce(f"C2 fp32 tau={tau} {legendre}")
-    g = O.make_grid(*C2)
+    announce(f"GL180 fp32 tau={tau} {legendre}")
+    g = O.make_grid(*GL180)
     p, q = synth.temperature_pair(synth.pair_seed(1, 0), g.x, g.w, g.nlon, K=8,
                                   q_mass=1.0 if math.isinf(tau) else 1.05)
     eps = 4e-3  # t = 1e-3
     T = 500
-    P = _plan([C2], "fp32", legendre)
+    P = _plan([GL180], "fp32", legendre)
     pd, qd = to_dev(p, P.dtype), to_dev(q, P.dtype)
     S, info = P.divergence(pd, qd, eps, tau, T=T)
     Sref, solves = O.divergence(p, q, g, eps, tau, T=T, return_solves=True)
     graded = [check_status(inf, r, "fp32") for inf, r in zip(info, solves)]
     for name, inf, r, gr in zip(("pq", "pp", "qq"), info, solves, graded):
-        report(f"C2 tau={tau} {legendre} {name}", graded=gr, kratio=r["kratio"],
+        report(f"GL180 tau={tau} {legendre} {name}", graded=gr, kratio=r["kratio"],
                oracle_breakdown=r["breakdown"], gpu_breakdown=inf["breakdown_iter"],
                cost=inf["cost"], cost_ref=r["cost"], err=inf["err"], err_ref=r["err"])
         if gr:
@@ -146,9 +146,9 @@ def test_c2_divergence_fp32(tau, legendre):
 
 def test_repeat_runs_are_bitwise_identical():
     announce("determinism")
-    g = O.make_grid(*C2)
+    g = O.make_grid(*GL180)
     p, q = synth.temperature_pair(3, g.x, g.w, g.nlon)
-    P = _plan([C2], "fp32", "recurrence")
+    P = _plan([GL180], "fp32", "recurrence")
     pd, qd = to_dev(p, P.dtype), to_dev(q, P.dtype)
     a = P.sinkhorn(pd, qd, 4e-3, T=30)
     b = P.sinkhorn(pd, qd, 4e-3, T=30)
