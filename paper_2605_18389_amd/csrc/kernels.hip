@@ -514,6 +514,15 @@ __device__ __forceinline__ bool bad_kernel_value(T x) {
   return !(x > (T)0) || !isfinite(x);
 }
 
+// Term u^(-eps/tau) of the unbalanced gauge sums (Alg. 1), taken in the field
+// precision: a float32 scaling gives a float32 power (about one ulp, as the
+// scaling itself carries); a float64 power of it cost more than the rest of
+// an unbalanced row launch.  The sums themselves stay float64.
+template <typename T>
+__device__ __forceinline__ double gauge_term(T u, double eot) {
+  return (double)pow(u, (T)(-eot));
+}
+
 template <typename T>
 __device__ __forceinline__ T* ubuf_of(const RowArgs<T>& A, int k) { return (k & 1) ? A.ubuf1 : A.ubuf0; }
 template <typename T>
@@ -906,7 +915,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
         if (!I.balanced) u = pow(u, (T)I.lam);
         un[fi] = u;
         nv[rr] = u;
-        acc0 += I.balanced ? (double)u : (double)aj * (double)pv * pow((double)u, -I.eot);
+        acc0 += I.balanced ? (double)u : (double)aj * (double)pv * gauge_term(u, I.eot);
       }
       if (mode == ROW_SINK_U) X[pr * N + c] = {nv[0], eq ? (T)0 : nv[1]};
     }
@@ -926,7 +935,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
         T v = qv / kraw;
         if (!I.balanced) {
           v = pow(v, (T)I.lam);
-          acc1 += (double)aj * (double)qv * pow((double)v, -I.eot);
+          acc1 += (double)aj * (double)qv * gauge_term(v, I.eot);
         }
         vn[fidx - I.foff] = v;
         nv[rr] = v;
@@ -1349,7 +1358,7 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
       if (!(kv >= FLT_MIN)) x = f / kv;
       if (!I.balanced) {
         x = pow(x, (T)I.lam);
-        acc += (double)aj * (double)f * pow((double)x, -I.eot);
+        acc += (double)aj * (double)f * gauge_term(x, I.eot);
       } else if (umode) {
         acc += (double)x;
       }
@@ -2900,10 +2909,13 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop) {
     g_ev_start = g_ev_stop = nullptr;                                                              \
   } while (0)
 // Row pairs per workgroup: the most (1, 2 or 4) whose two FFT buffers fit in
-// LDS while the launch keeps at least ~2048 workgroups.
+// LDS, with at most 1440 points of rows per group (192 items of 720-point
+// rows: 250 us with 4 pairs per group, 226 us with 2), while the launch keeps
+// at least ~2048 workgroups.
 int row_pairs_per_group(int h, int nlon, int nb, size_t cs) {
   int rpw = 4;
-  while (rpw > 1 && ((size_t)2 * rpw * nlon * cs > 60 * 1024 || (long long)((h + rpw - 1) / rpw) * nb < 2048))
+  while (rpw > 1 && ((size_t)2 * rpw * nlon * cs > 60 * 1024 || rpw * nlon > 1440 ||
+                     (long long)((h + rpw - 1) / rpw) * nb < 2048))
     rpw >>= 1;
   return rpw;
 }
