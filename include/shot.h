@@ -209,9 +209,13 @@ shot_status shot_sinkhorn_divergence(shot_plan_t plan, const int32_t* grid_of_pa
  * with tol = 0; the pairs of one call are all balanced (tau = +INFINITY) or all
  * unbalanced (SHOT_E_UNSUPPORTED otherwise).
  * mode 0: exact reverse-mode derivative of the T-iteration computation
- *         (hand-written adjoint of Alg. 1, both branches, and of HeatConv); the
- *         forward iterates are recomputed from checkpoints of v taken every
- *         `checkpoint_every` iterations (0 = ceil(sqrt(T))) instead of being stored.
+ *         (hand-written adjoint of Alg. 1, both branches, and of HeatConv).  The
+ *         reverse sweep reads the forward iterates of `checkpoint_every`
+ *         iterations at a time, recomputed from checkpoints of v.  With 0 the
+ *         library keeps the whole history in one segment (one forward pass, no
+ *         recomputation) when 2 T fields per (p,q) and (p,p) solve take at most
+ *         half the free device memory and 64 GiB, else checkpoints every
+ *         ceil(sqrt(T)) iterations.  The workspace stays with the plan.
  * mode 1: envelope gradient from the potentials (balanced pairs only),
  *         a (.) (phi_pq - (phi_pp + psi_pp)/2) + eps (m(p)-m(q)) a.
  * dS_dp: device, layout of p.  Other arguments as shot_sinkhorn_divergence. */

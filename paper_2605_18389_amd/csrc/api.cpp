@@ -1321,7 +1321,17 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
     if (std::isinf(S.prm[i].tau) == unbal || S.prm[i].tol != 0 || S.prm[i].max_iter != Tit)
       return SHOT_E_UNSUPPORTED;
   }
-  if (CK <= 0) CK = (int)std::ceil(std::sqrt((double)Tit));
+  if (CK <= 0) {
+    // keep the whole forward history (u-hat, v-hat of every iteration) when it
+    // takes at most half the free device memory (and 64 GiB): the reverse sweep
+    // then needs one forward pass instead of a checkpointed pass plus a
+    // recomputation; otherwise checkpoints every ceil(sqrt(T)) iterations
+    size_t fr = 0, tot = 0;
+    const double hist = 2.0 * sizeof(T) * (double)Lo.field_total * Tit;
+    const bool fits = hipMemGetInfo(&fr, &tot) == hipSuccess &&
+                      hist <= std::min(0.5 * (double)fr, 64.0 * 1024 * 1024 * 1024);
+    CK = fits ? Tit : (int)std::ceil(std::sqrt((double)Tit));
+  }
   CK = std::min(CK, Tit);
   const int nck = (Tit - 1) / CK;  // checkpoints at k = CK, 2CK, ... < T
   Work<T> W;
@@ -1381,12 +1391,14 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
     return run_leg<T>(P, g, la, s);
   };
   // ---- forward sweep with checkpoints of (v-hat_k, s_k) at k = CK, 2CK, ...
-  ST_TRY(each([&](const Group& G, const GridRec& g) {
-    RowArgs<T> a = base_args(G, g);
-    a.mode = ROW_INIT;
-    return run_rows<T>(P, a, G.count, s);
-  }));
-  for (int k = 1; k <= Tit; ++k) {
+  // (none when one segment holds every iteration: the sweep is skipped)
+  if (nck > 0)
+    ST_TRY(each([&](const Group& G, const GridRec& g) {
+      RowArgs<T> a = base_args(G, g);
+      a.mode = ROW_INIT;
+      return run_rows<T>(P, a, G.count, s);
+    }));
+  for (int k = 1; nck > 0 && k <= Tit; ++k) {
     ST_TRY(each([&](const Group& G, const GridRec& g) {
       shot_status st = leg(G, g, W.spec);
       if (st != SHOT_OK) return st;

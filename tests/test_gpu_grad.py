@@ -85,6 +85,25 @@ def test_unbalanced_gradient_matches_oracle_fd(prec, tol, ck, tau):
     assert np.abs(an - fd).max() <= tol * scale, (an, fd)
 
 
+@pytest.mark.parametrize("prec,tau", [("fp32", math.inf), ("fp64", math.inf), ("fp32", 1.0)])
+def test_whole_history_and_checkpointed_adjoints_agree(prec, tau):
+    """The reverse sweep with the whole forward history kept (checkpoint_every 0
+    or T: one forward pass) reads the same iterates that the checkpointed form
+    recomputes from its checkpoints, so S and the gradient agree bit for bit."""
+    grid = ("gl", 32, 64, 32)
+    announce(f"adjoint history vs checkpoints {prec} tau={tau}")
+    g = O.make_grid(*grid)
+    p, q = synth.temperature_pair(24, g.x, g.w, g.nlon, K=4, q_mass=1.0 if math.isinf(tau) else 1.05)
+    eps, T = 0.1, 40
+    P = _plan([grid], prec)
+    pd, qd = to_dev(p, P.dtype), to_dev(q, P.dtype)
+    out = {ck: P.divergence_grad(pd, qd, eps, T=T, checkpoint_every=ck, tau=tau) for ck in (0, T, 7)}
+    for ck in (T, 7):
+        assert out[ck][0][0] == out[0][0][0], (ck, out[ck][0], out[0][0])
+        assert np.array_equal(to_np(out[ck][1]), to_np(out[0][1])), ck
+    assert np.isfinite(to_np(out[0][1])).all()
+
+
 def test_unbalanced_gradient_through_autograd():
     import torch
     from paper_2605_18389_amd.autograd import sinkhorn_divergence
