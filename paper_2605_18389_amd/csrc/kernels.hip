@@ -2455,9 +2455,11 @@ __host__ __device__ inline RmLayout rm_layout(int L, int h, int nt, int nw, int 
   q.nb = (L + 31) / 32;              // row blocks of the longest order
   q.ncol = 16 * nt;
   // row pitches (elements): float rows odd, so the lanes of a k-slice read
-  // distinct banks; bfloat16 rows keep 8-byte operand reads aligned
+  // distinct banks; bfloat16 rows keep 8-byte operand reads aligned.  b holds
+  // one block's 16 rows per parity: a pitch of 18 floats puts the 32 lanes of
+  // a half-wave's k-slice on distinct banks
   q.pld = es == 4 ? 65 : 68;
-  q.bld = 16 * q.nb + (es == 4 ? 1 : 4);
+  q.bld = es == 4 ? 18 : 20;
   q.pplane = (size_t)nw * 32 * q.pld;
   q.bplane = (size_t)2 * q.ncol * q.bld;
   size_t off = 0;
@@ -2466,21 +2468,25 @@ __host__ __device__ inline RmLayout rm_layout(int L, int h, int nt, int nw, int 
   // out: 8 nt items x h latitudes x (E, O) complex
   const size_t tiles = q.pplane * planes * es, spectra = (size_t)8 * nt * h * 4 * sizeof(float);
   q.o_p = take(tiles > spectra ? tiles : spectra);
-  q.o_d = take(sizeof(float) * 2 * nw * 2 * q.ncol * 20);
+  q.o_d = take(sizeof(float) * nw * 2 * q.ncol * 20);
   q.o_b = take(q.bplane * planes * es);
   q.o_c = take(sizeof(double) * (32 * q.nb + 1));
-  q.o_s = take(sizeof(double) * 2 * 32 + sizeof(float) * 2 * 8 * nt * 32);  // per-block gamma, h_l (2 buffers)
+  q.o_s = take(sizeof(double) * 32 + sizeof(float) * 8 * nt * 32);  // the block's gamma and h_l
   q.total = off;
   return q;
 }
 
+// Split bfloat16 with 8 items per group is held to three waves per SIMD (at
+// most 168 registers); the other forms reach it or exceed it by design.
 template <typename T, int OP, int NT>
-__global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((OP == RM_BF16X3 && NT == 1) ? 3 : 1)))
+legendre_rmma_kernel(LegArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using TR = RmTraits<OP>;
   using Op = typename TR::Op;
   constexpr int KS = TR::KS, ES = TR::ES, PL = TR::PLANES;
   constexpr int NKS = 64 / KS;        // k steps over a wave's 64 latitudes
+  constexpr int RQ = OP == RM_BF16X3 ? 8 : 16;  // recurrence coefficients held in registers at once
   const int L = A.L, h = A.h;
   const int nw = blockDim.x >> 6;
   const RmLayout Q = rm_layout(L, h, NT, nw, ES, PL);
@@ -2503,8 +2509,8 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
   const long long toff = tri_off(m, L);
   const int nit = min(8 * NT, A.nb - c0 / 2);                 // items of this chunk
   const int ncomb = 2 * 16 * Q.ncol;                           // combine elements per block
-  double* gsl = reinterpret_cast<double*>(smem_raw + Q.o_s);  // [2][32] gamma of the block's rows
-  float* hsl = reinterpret_cast<float*>(gsl + 64);           // [2][8 NT][32] h_l of the block's rows
+  double* gsl = reinterpret_cast<double*>(smem_raw + Q.o_s);  // [32] gamma of the block's rows
+  float* hsl = reinterpret_cast<float*>(gsl + 32);           // [8 NT][32] h_l of the block's rows
   // items of one launch group are consecutive in the workspace, each holding
   // 2 L h complex spectral entries: this chunk's spectra start here
   const float4* spc = reinterpret_cast<const float4*>(A.spec + A.soff0) + (size_t)(c0 / 2) * L * h + (size_t)m * h;
@@ -2566,7 +2572,17 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
   }
   __syncthreads();  // the staged spectra share LDS with the recurrence tiles
 
-  // ---- analysis, block by block; partials of the waves combined in LDS
+  // ---- one pass over the order's rows, 32 at a time: the block's analysis
+  // f = sum_j P y (partials of the waves combined in LDS), b = gamma^2 h_l f,
+  // then the block's synthesis term G += sum_l P b from the same recurrence
+  // values (kept in registers; lane-group exchanges put them in operand order)
+  f32x4_t G[2][4][NT];
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) G[par][jt][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   double R1 = seed, R2 = 0.0;
   for (int blk = 0; blk < nblk; ++blk) {
     const int r0 = 32 * blk;
@@ -2580,15 +2596,20 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
       const int e = min(tid + u * (int)blockDim.x, 8 * NT * 32 - 1), i = min(e >> 5, nit - 1);
       hld[u] = A.hl[(size_t)(A.item0 + c0 / 2 + i) * A.hl_stride + m + min(r0 + (e & 31), nr - 1)];
     }
-    double cq[32];
+    float v[32];
 #pragma unroll
-    for (int q = 0; q < 32; ++q) cq[q] = cf[r0 + q + 1];
+    for (int hq = 0; hq < 32; hq += RQ) {  // coefficients in batches of RQ (registers)
+      double cq[RQ];
 #pragma unroll
-    for (int q = 0; q < 32; ++q) {
-      TR::put(Pt, Q.pplane, (size_t)q * Q.pld + lane, rm_f32(R1));
-      const double rn = fma(cq[q] * xj, R1, R2);
-      R2 = R1;
-      R1 = rn;
+      for (int q = 0; q < RQ; ++q) cq[q] = cf[r0 + hq + q + 1];
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) {
+        v[hq + q] = rm_f32(R1);
+        TR::put(Pt, Q.pplane, (size_t)(hq + q) * Q.pld + lane, v[hq + q]);
+        const double rn = fma(cq[q] * xj, R1, R2);
+        R2 = R1;
+        R1 = rn;
+      }
     }
     f32x4_t acc[2][NT];
 #pragma unroll
@@ -2606,24 +2627,22 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
         for (int t = 0; t < NT; ++t) acc[par][t] = TR::mma(a, yb[s][par][t], acc[par][t]);
       }
     }
-    if (tid < 32) gsl[(blk & 1) * 32 + tid] = r0 + tid < nr ? gld : 0.0;
+    if (tid < 32) gsl[tid] = r0 + tid < nr ? gld : 0.0;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int e = tid + u * (int)blockDim.x;
-      if (e < 8 * NT * 32) hsl[(blk & 1) * 8 * NT * 32 + e] = (r0 + (e & 31) < nr && (e >> 5) < nit) ? hld[u] : 0.f;
+      if (e < 8 * NT * 32) hsl[e] = (r0 + (e & 31) < nr && (e >> 5) < nit) ? hld[u] : 0.f;
     }
     for (int e = tid + 2 * blockDim.x; e < 8 * NT * 32; e += blockDim.x) {  // one-wave workgroups of 16 items
       const int i = e >> 5, r = r0 + (e & 31);
-      hsl[(blk & 1) * 8 * NT * 32 + e] =
-          (r < nr && i < nit) ? A.hl[(size_t)(A.item0 + c0 / 2 + i) * A.hl_stride + m + r] : 0.f;
+      hsl[e] = (r < nr && i < nit) ? A.hl[(size_t)(A.item0 + c0 / 2 + i) * A.hl_stride + m + r] : 0.f;
     }
     // wave partials, [wave][parity][column][row of the parity] (rows padded to 20)
-    float* dp = Dp + (size_t)(blk & 1) * nw * 2 * Q.ncol * 20;
 #pragma unroll
     for (int par = 0; par < 2; ++par)
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        *reinterpret_cast<f32x4_t*>(dp + (((size_t)wave * 2 + par) * Q.ncol + 16 * t + li) * 20 + 4 * lg) =
+        *reinterpret_cast<f32x4_t*>(Dp + (((size_t)wave * 2 + par) * Q.ncol + 16 * t + li) * 20 + 4 * lg) =
             acc[par][t];
     __syncthreads();
     // b = gamma^2 h_l (sum over the waves), in the operand format, rows of one
@@ -2631,43 +2650,14 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
     for (int idx = tid; idx < ncomb; idx += blockDim.x) {
       const int pn = idx >> 4, rp = idx & 15;
       const int par = pn / Q.ncol, n = pn - par * Q.ncol;
-      float part[8];
-#pragma unroll
-      for (int w = 0; w < 8; ++w) part[w] = dp[(((size_t)min(w, nw - 1) * 2 + par) * Q.ncol + n) * 20 + rp];
-      const double g = gsl[(blk & 1) * 32 + 2 * rp + par];
-      const double sc = g * g * (double)hsl[(blk & 1) * 8 * NT * 32 + (n >> 1) * 32 + 2 * rp + par];
-      float sum = part[0];
-#pragma unroll
-      for (int w = 1; w < 8; ++w) sum += w < nw ? part[w] : 0.f;
-      TR::put(Bs, Q.bplane, ((size_t)par * Q.ncol + n) * Q.bld + 16 * blk + rp, (float)((double)sum * sc));
+      float sum = 0.f;
+      for (int w = 0; w < nw; ++w) sum += Dp[(((size_t)w * 2 + par) * Q.ncol + n) * 20 + rp];
+      const double g = gsl[2 * rp + par];
+      const double sc = g * g * (double)hsl[(n >> 1) * 32 + 2 * rp + par];
+      TR::put(Bs, Q.bplane, ((size_t)par * Q.ncol + n) * Q.bld + rp, (float)((double)sum * sc));
     }
-  }
-  __syncthreads();
-
-  // ---- synthesis: the recurrence again, values moved to operand order by
-  // lane-group exchanges, G accumulated in registers
-  f32x4_t G[2][4][NT];
-#pragma unroll
-  for (int par = 0; par < 2; ++par)
-#pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
-#pragma unroll
-      for (int t = 0; t < NT; ++t) G[par][jt][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  R1 = seed;
-  R2 = 0.0;
-  for (int blk = 0; blk < nblk; ++blk) {
-    const int r0 = 32 * blk;
-    double cq[32];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) cq[q] = cf[r0 + q + 1];
-    float v[32];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) {
-      v[q] = rm_f32(R1);
-      const double rn = fma(cq[q] * xj, R1, R2);
-      R2 = R1;
-      R1 = rn;
-    }
+    __syncthreads();
+    // the block's synthesis term
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
       if constexpr (OP == RM_F32) {
@@ -2680,7 +2670,7 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
           lanegroup_transpose4(a[0], a[1], a[2], a[3]);
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
-            const Op b = TR::get(Bs, Q.bplane, ((size_t)par * Q.ncol + 16 * t + li) * Q.bld + 16 * blk + 4 * s + lg);
+            const Op b = TR::get(Bs, Q.bplane, ((size_t)par * Q.ncol + 16 * t + li) * Q.bld + 4 * s + lg);
 #pragma unroll
             for (int jt = 0; jt < 4; ++jt) G[par][jt][t] = TR::mma(Op{__uint_as_float(a[jt])}, b, G[par][jt][t]);
           }
@@ -2708,7 +2698,7 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          const Op b = TR::get(Bs, Q.bplane, ((size_t)par * Q.ncol + 16 * t + li) * Q.bld + 16 * blk + 4 * lg);
+          const Op b = TR::get(Bs, Q.bplane, ((size_t)par * Q.ncol + 16 * t + li) * Q.bld + 4 * lg);
 #pragma unroll
           for (int jt = 0; jt < 4; ++jt) {
             Op a;
@@ -2722,8 +2712,8 @@ __global__ void __launch_bounds__(512) legendre_rmma_kernel(LegArgs<T> A) {
   }
   // ---- the order's folded spectrum: G[j][n] (j = 64 wave + 16 jt + 4 lg + e)
   // gathered in the staging region, then copied out with coalesced stores
-  // (the tiles that region also holds are no longer read)
-  __syncthreads();
+  // (the tiles that region also holds are not read after the last block's
+  // second barrier)
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int il = 8 * t + (li >> 1);
