@@ -15,7 +15,10 @@ output whose true value is below that cannot be told from zero.  Hence:
   breakdown at iteration 93, GPU at 84 where the oracle's ratio was 5.3e-4);
   an item graded by value must not break down on the GPU;
 * tolerance: graded values agree to max(base, 10 u / kratio) relative, the
-  error of the smallest heat-kernel output carried into u = p / K v.
+  error of the smallest heat-kernel output carried into u = p / K v; the
+  GPU's running kernel ratio itself, usually smallest at the first
+  iterations, to max(that, 10 E_APPLY / kratio), E_APPLY being one heat
+  apply's error relative to max|K v|.
 
 Matrix-core forms, bounds fixed from the operand precision before any run:
 * split bfloat16 (hi + lo, three products): about 2^-16 relative per product,
@@ -30,6 +33,10 @@ import json
 import os
 
 U = {"fp64": 1.1e-16, "fp32": 6.0e-8, "bf16x3": 1.5e-5, "bf16": 3.9e-3}
+# error of one heat apply relative to max|K v|: float32 plans may contract on
+# matrix cores, accumulating in float32 over up to L terms (about sqrt(L) u,
+# 1.6e-6 at L = 720); the other forms as u
+E_APPLY = {"fp64": 1e-15, "fp32": 2e-6, "bf16x3": 1.5e-4, "bf16": 3.9e-2}
 MARGIN = {"fp64": 1e-13, "fp32": 1e-5, "bf16x3": 2e-3, "bf16": 0.5}
 BASE = {"fp64": 1e-10, "fp32": 1e-4, "bf16x3": 1e-3, "bf16": 5e-2}
 
@@ -49,9 +56,12 @@ def check_status(gpu, oref, prec):
     graded = kb == 0 and float(oref["kratio"]) > margin
     if graded:
         assert kg == 0, "item above the margin broke down on the GPU"
-        # the GPU's own running kernel ratio is a graded value like the costs
+        # the GPU's own running kernel ratio: its minimum is usually reached at
+        # the first iterations, where min(K.) carries the heat apply's own
+        # error, E_APPLY of max|K.|, undamped by the iteration
         kr = float(oref["kratio"])
-        assert abs(gpu["kratio"] - kr) <= tolerance(oref, prec) * kr, (gpu["kratio"], kr)
+        kr_tol = max(tolerance(oref, prec), 10.0 * E_APPLY[prec] / kr)
+        assert abs(gpu["kratio"] - kr) <= kr_tol * kr, (gpu["kratio"], kr, kr_tol)
     return graded
 
 
