@@ -2605,11 +2605,40 @@ legendre_rmma_kernel(LegArgs<T> A) {
 #pragma unroll
       for (int q = 0; q < RQ; ++q) {
         v[hq + q] = rm_f32(R1);
-        TR::put(Pt, Q.pplane, (size_t)(hq + q) * Q.pld + lane, v[hq + q]);
+        if constexpr (OP == RM_F32) TR::put(Pt, Q.pplane, (size_t)(hq + q) * Q.pld + lane, v[hq + q]);
         const double rn = fma(cq[q] * xj, R1, R2);
         R2 = R1;
         R1 = rn;
       }
+    }
+    // bfloat16 forms: the block's values rounded once, packed two rows of a
+    // parity per word (rows 2(4u+2w)+par and the next of that parity), used by
+    // the synthesis operands and written to the tile as 16-bit halves; tile
+    // rows are stored by parity (row 2k+par at 16 par + k), so that the 16
+    // lanes of an 8-byte operand read fall on distinct banks
+    unsigned hwp[2][2][4], lwp[2][2][4];
+    if constexpr (OP != RM_F32) {
+      unsigned short* th = reinterpret_cast<unsigned short*>(Pt);
+#pragma unroll
+      for (int par = 0; par < 2; ++par)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int w2 = 0; w2 < 2; ++w2) {
+            const float x0 = v[2 * (4 * u + 2 * w2) + par], x1 = v[2 * (4 * u + 2 * w2 + 1) + par];
+            const unsigned h0 = rm_bf16(x0), h1 = rm_bf16(x1);
+            hwp[par][w2][u] = h0 | (h1 << 16);
+            const size_t ra = (size_t)(16 * par + 4 * u + 2 * w2) * Q.pld + lane;
+            th[ra] = (unsigned short)h0;
+            th[ra + Q.pld] = (unsigned short)h1;
+            if constexpr (OP == RM_BF16X3) {
+              const unsigned l0 = rm_bf16(x0 - __uint_as_float(h0 << 16));
+              const unsigned l1 = rm_bf16(x1 - __uint_as_float(h1 << 16));
+              lwp[par][w2][u] = l0 | (l1 << 16);
+              th[Q.pplane + ra] = (unsigned short)l0;
+              th[Q.pplane + ra + Q.pld] = (unsigned short)l1;
+            }
+          }
     }
     f32x4_t acc[2][NT];
 #pragma unroll
@@ -2622,7 +2651,8 @@ legendre_rmma_kernel(LegArgs<T> A) {
       for (int par = 0; par < 2; ++par) {
         // A[i][k] = R_{r0 + 2i + par}(x_{64 wave + KS s + k})
         const int kk = KS * s + (KS == 4 ? lg : 4 * lg);
-        const Op a = TR::get(Pt, Q.pplane, (size_t)(2 * li + par) * Q.pld + kk);
+        const int trow = OP == RM_F32 ? 2 * li + par : 16 * par + li;
+        const Op a = TR::get(Pt, Q.pplane, (size_t)trow * Q.pld + kk);
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[par][t] = TR::mma(a, yb[s][par][t], acc[par][t]);
       }
@@ -2682,14 +2712,8 @@ legendre_rmma_kernel(LegArgs<T> A) {
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int w2 = 0; w2 < 2; ++w2) {
-            const float x0 = v[2 * (4 * u + 2 * w2) + par], x1 = v[2 * (4 * u + 2 * w2 + 1) + par];
-            const unsigned h0 = rm_bf16(x0), h1 = rm_bf16(x1);
-            hw[w2][u] = h0 | (h1 << 16);
-            if constexpr (OP == RM_BF16X3) {
-              const unsigned l0 = rm_bf16(x0 - __uint_as_float(h0 << 16));
-              const unsigned l1 = rm_bf16(x1 - __uint_as_float(h1 << 16));
-              lw[w2][u] = l0 | (l1 << 16);
-            }
+            hw[w2][u] = hwp[par][w2][u];
+            if constexpr (OP == RM_BF16X3) lw[w2][u] = lwp[par][w2][u];
           }
 #pragma unroll
         for (int w2 = 0; w2 < 2; ++w2) {
