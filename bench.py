@@ -134,6 +134,41 @@ UNEVEN_GRIDS = [("gl", 90, 180, 90), ("gl", 180, 360, 180), ("gl", 360, 720, 360
 UNEVEN_COUNTS = [96, 96, 64]
 
 
+MFMA_PEAK = {"fp32": 157.3, "bf16x3": 2500.0 / 3, "bf16": 2500.0}   # TFLOP/s of the contraction
+
+
+def batched_roofline(torch, precision, grid, nitems, tuning):
+    """Roofline of the matrix-core recurrence Legendre kernel at a batch's launch shape:
+    one heat apply of `nitems` items with the batch's tuning, HIP events on the launch
+    stream around each of 5 launches.  Work per launch: the contraction 2 E 4 flop per
+    item (complex x real, analysis + synthesis; split bfloat16 takes three products,
+    so its peak is a third of the bfloat16 one), the folded spectra in and out."""
+    from paper_2605_18389_amd import Plan
+    P = Plan([grid], precision=precision, legendre="recurrence")
+    P.set_tuning(0, *tuning)
+    _, nlat, nlon, L = grid
+    v = torch.rand(nitems, nlat, nlon, dtype=torch.float32, device="cuda") + 0.5
+    P.heat_apply(v, [1e-3] * nitems)
+    P.profile(True)
+    for _ in range(5):
+        P.heat_apply(v, [1e-3] * nitems)
+    n, ms = P.profile_read(0)
+    P.profile(False)
+    avg_ms = ms / max(n, 1)
+    h = (nlat + 1) // 2
+    E = L * (L + 1) // 2 * h
+    flops = 2 * E * 4 * nitems
+    bytes_ = nitems * 2 * L * h * 2 * 8
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    traffic = measured_traffic("legendre_rmma_kernel") if (precision, nitems) == ("fp32", 48) else None
+    return {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK[precision], "unit": "TFLOP/s",
+            "frac": achieved / MFMA_PEAK[precision], "traffic": traffic,
+            "kernel": "legendre_rmma_kernel (recurrence-fed matrix-core Legendre)",
+            "launch": {"grid": list(grid), "items": nitems, "tuning": list(tuning)},
+            "avg_launch_ms": avg_ms, "work_per_launch": {"flop": flops, "bytes": bytes_},
+            "hbm_GBps": bytes_ / (avg_ms * 1e-3) / 1e9}
+
+
 def bench_grad_batch(torch, precision, legendre, reps=1):
     """16 pairs on 360x720 Gauss-Legendre, t = 1e-3, balanced, T = 300: S and dS/dp per pair
     (forward, then the hand-written adjoint with checkpoint recompute)."""
@@ -158,6 +193,8 @@ def bench_grad_batch(torch, precision, legendre, reps=1):
     bad = sum(1 for i in range(16) if any(x["status"] == 17 for x in info[3 * i:3 * i + 3]))
     out = {"divergence_grad_per_s": 16 / dt, "ms_per_batch": dt * 1e3, "pairs": 16,
            "pairs_with_breakdown": bad, "tuning": plan.get_tuning(0)}
+    if legendre == "recurrence" and plan.get_tuning(0)[0] >= 8:
+        out["roofline"] = batched_roofline(torch, precision, BATCH16_GRID, 48, plan.get_tuning(0))
     ref = oracle_ref("gl360_batch16_t1e-3")
     if ref and len(ref["pairs"]) == 16:
         out["vs_oracle"] = pair_errors(S, info, ref["pairs"])
@@ -195,6 +232,8 @@ def bench_uneven_batch(torch, precision, legendre, reps=1):
     bad = sum(1 for i in range(len(goi)) if any(x["status"] == 17 for x in info[3 * i:3 * i + 3]))
     out = {"divergences_per_s": len(goi) / dt, "ms_per_batch": dt * 1e3, "pairs": len(goi),
            "pairs_with_breakdown": bad, "tuning": [plan.get_tuning(k) for k in range(3)]}
+    if legendre == "recurrence" and plan.get_tuning(2)[0] >= 8:
+        out["roofline"] = batched_roofline(torch, precision, UNEVEN_GRIDS[2], 3 * UNEVEN_COUNTS[2], plan.get_tuning(2))
     ref = oracle_ref("uneven256_subset")
     if ref:
         out["vs_oracle_subset"] = pair_errors(S, info, ref["pairs"], lambda k, pr: pr["index"])
@@ -378,6 +417,13 @@ def traffic_probe():
     for _ in range(2):
         plan.sinkhorn(p, q, 4 * T_HEAT, T=10, potentials=True)
     torch.cuda.synchronize()
+    # the matrix-core recurrence kernel at the 16-pair batch's forward shape
+    bp = Plan([BATCH16_GRID], precision="fp32", legendre="recurrence")
+    bp.set_tuning(0, 8, 0)
+    v = torch.rand(48, BATCH16_GRID[1], BATCH16_GRID[2], dtype=torch.float32, device="cuda") + 0.5
+    for _ in range(3):
+        bp.heat_apply(v, [1e-3] * 48)
+    torch.cuda.synchronize()
     print("traffic probe done", flush=True)
 
 
@@ -510,6 +556,15 @@ def main():
                            f"`value` is from HIP-graph replay",
                  "work_per_launch": {"flop": flops, "bytes": bytes_},
                  "row_fft_avg_launch_ms": rows[1] / max(rows[0], 1)})
+    if args.legendre == "recurrence":
+        # the other counting: 4 flop per entry and pass for the recurrence at the
+        # float64 peak plus the contraction at the packed-float32 peak
+        _, nlat_, _, L_ = GRID
+        E = L_ * (L_ + 1) // 2 * ((nlat_ + 1) // 2)
+        ideal_us = (2 * E * 4 / 78.6e12 + 2 * E * 4 / 157.3e12) * 1e6
+        roof["alt_counting"] = {"recurrence_fp64_flop": 2 * E * 4, "contraction_fp32_flop": 2 * E * 4,
+                                "ideal_us": ideal_us, "frac": ideal_us / (avg_leg_ms * 1e3),
+                                "note": "the kernel contracts in float64 (same issue rate as unpacked float32)"}
     out = {
         "metric": METRIC, "value": value, "unit": "iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,

@@ -523,6 +523,25 @@ __device__ __forceinline__ double gauge_term(T u, double eot) {
   return (double)pow(u, (T)(-eot));
 }
 
+// The unbalanced update x -> x^lam (lam = tau/(tau+eps)) and the new value's
+// gauge-sum term x^(-lam eps/tau), both from one base-2 logarithm in float32:
+// exp2(lam log2 x) is within about |log2 x| ulp of the correctly rounded power
+// (about 1e-6 relative for scalings within 2^+-16), and the term's exponent is
+// damped by eps/tau.  Zero, infinite and negative x give what the powers give.
+// float64 fields keep the library powers.
+template <typename T>
+__device__ __forceinline__ T unbalanced_update(T x, double lam, double eot, double& term) {
+  if constexpr (sizeof(T) == 4) {
+    const float y = (float)lam * log2f(x);
+    term = (double)exp2f(-(float)eot * y);
+    return exp2f(y);
+  } else {
+    const T xn = pow(x, (T)lam);
+    term = gauge_term(xn, eot);
+    return xn;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T* ubuf_of(const RowArgs<T>& A, int k) { return (k & 1) ? A.ubuf1 : A.ubuf0; }
 template <typename T>
@@ -912,10 +931,11 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
         bad |= bad_kernel_value(kv);
         track_minmax(kmin, kmax, kraw);
         T u = pv / kv;
-        if (!I.balanced) u = pow(u, (T)I.lam);
+        double gt = 0.0;
+        if (!I.balanced) u = unbalanced_update(u, I.lam, I.eot, gt);
         un[fi] = u;
         nv[rr] = u;
-        acc0 += I.balanced ? (double)u : (double)aj * (double)pv * gauge_term(u, I.eot);
+        acc0 += I.balanced ? (double)u : (double)aj * (double)pv * gt;
       }
       if (mode == ROW_SINK_U) X[pr * N + c] = {nv[0], eq ? (T)0 : nv[1]};
     }
@@ -934,8 +954,9 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
         const T qv = pre ? pick2(pfv, e, rr) : Q[fidx];
         T v = qv / kraw;
         if (!I.balanced) {
-          v = pow(v, (T)I.lam);
-          acc1 += (double)aj * (double)qv * gauge_term(v, I.eot);
+          double gt;
+          v = unbalanced_update(v, I.lam, I.eot, gt);
+          acc1 += (double)aj * (double)qv * gt;
         }
         vn[fidx - I.foff] = v;
         nv[rr] = v;
@@ -1357,8 +1378,9 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
       // finite: take the IEEE divide there (a branch no lane takes is skipped)
       if (!(kv >= FLT_MIN)) x = f / kv;
       if (!I.balanced) {
-        x = pow(x, (T)I.lam);
-        acc += (double)aj * (double)f * gauge_term(x, I.eot);
+        double gt;
+        x = unbalanced_update(x, I.lam, I.eot, gt);
+        acc += (double)aj * (double)f * gt;
       } else if (umode) {
         acc += (double)x;
       }
