@@ -523,6 +523,7 @@ struct Layout {
 shot_status make_layout(const shot_plan_s* P, const int32_t* grid_of_item, int nitems, Layout& Lo) {
   if (nitems <= 0 || !grid_of_item) return SHOT_E_INVALID;
   const int ng = (int)P->grids.size();
+  Lo = Layout{};  // a layout may be rebuilt in place: every running total starts again
   Lo.user_foff.assign(nitems, 0);
   Lo.user_coff.assign(nitems, 0);
   int64_t fo = 0, co = 0;
@@ -968,7 +969,16 @@ shot_status check_params(const shot_params& pr) {
 template <typename T>
 shot_status finish_solve(shot_plan_s* P, const Layout& Lo, Work<T>& W, int nitems, int K, int C,
                          int final_slot, double tol, T* phi, T* psi, shot_solve_info* info,
-                         double* mass_out, hipStream_t s);
+                         double* mass_out, hipStream_t s, T* u_last = nullptr, T* v_last = nullptr);
+
+// Whether the reverse sweep over these fields keeps the whole forward history:
+// 2 T fields per item within half the free device memory and 64 GiB.
+template <typename T>
+bool whole_history_fits(long long field_total, int T_iter) {
+  size_t fr = 0, tot = 0;
+  const double hist = 2.0 * sizeof(T) * (double)field_total * T_iter;
+  return hipMemGetInfo(&fr, &tot) == hipSuccess && hist <= std::min(0.5 * (double)fr, 64.0 * 1024 * 1024 * 1024);
+}
 
 template <typename T>
 shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_solve_info* info,
@@ -1124,16 +1134,19 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
 }
 
 // Potentials, cost and reports after the iteration loop (iteration K reached).
+// u_last / v_last: where the last scalings are, when not in the work buffers.
 template <typename T>
 shot_status finish_solve(shot_plan_s* P, const Layout& Lo, Work<T>& W, int nitems, int K, int C,
                          int final_slot, double tol, T* phi, T* psi, shot_solve_info* info,
-                         double* mass_out, hipStream_t s) {
+                         double* mass_out, hipStream_t s, T* u_last, T* v_last) {
   for (const Group& G : Lo.groups) {
     RowArgs<T> a = row_args<T>(P, P->grids[G.grid], Lo, G, W, nitems);
     a.mode = ROW_FINAL;
     a.k = K;
     a.out = phi;
     a.out2 = psi;
+    if (u_last) a.ubuf0 = a.ubuf1 = u_last;
+    if (v_last) a.vbuf0 = a.vbuf1 = v_last;
     ST_TRY(run_rows<T>(P, a, G.count, s));
   }
   const int nchk_done = K / C;
@@ -1311,7 +1324,7 @@ char* scratch_of(int dev) {
 // ---------------------------------------------------------------------------
 template <typename T>
 shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_out, T** qbar_out,
-                         Layout& Lo, hipStream_t s) {
+                         Layout& Lo, hipStream_t s, shot_solve_info* fwd_info = nullptr, double* fwd_mass = nullptr) {
   const int nitems = (int)S.grid.size();
   ST_TRY(make_layout(P, S.grid.data(), nitems, Lo));
   const int Tit = S.prm[0].max_iter;
@@ -1321,21 +1334,21 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
     if (std::isinf(S.prm[i].tau) == unbal || S.prm[i].tol != 0 || S.prm[i].max_iter != Tit)
       return SHOT_E_UNSUPPORTED;
   }
-  if (CK <= 0) {
-    // keep the whole forward history (u-hat, v-hat of every iteration) when it
-    // takes at most half the free device memory (and 64 GiB): the reverse sweep
-    // then needs one forward pass instead of a checkpointed pass plus a
-    // recomputation; otherwise checkpoints every ceil(sqrt(T)) iterations
-    size_t fr = 0, tot = 0;
-    const double hist = 2.0 * sizeof(T) * (double)Lo.field_total * Tit;
-    const bool fits = hipMemGetInfo(&fr, &tot) == hipSuccess &&
-                      hist <= std::min(0.5 * (double)fr, 64.0 * 1024 * 1024 * 1024);
-    CK = fits ? Tit : (int)std::ceil(std::sqrt((double)Tit));
-  }
+  // keep the whole forward history (u-hat, v-hat of every iteration) when it
+  // fits: the reverse sweep then needs one forward pass instead of a
+  // checkpointed pass plus a recomputation; otherwise checkpoints every
+  // ceil(sqrt(T)) iterations.  With fwd_info the forward pass (which must then
+  // hold the whole history) also reports each solve as solve_impl does.
+  if (fwd_info) CK = Tit;
+  else if (CK <= 0) CK = whole_history_fits<T>(Lo.field_total, Tit) ? Tit : (int)std::ceil(std::sqrt((double)Tit));
   CK = std::min(CK, Tit);
   const int nck = (Tit - 1) / CK;  // checkpoints at k = CK, 2CK, ... < T
+  const int C = S.prm[0].check_every;
+  for (int i = 0; fwd_info && i < nitems; ++i)
+    if (S.prm[i].check_every != C) return SHOT_E_UNSUPPORTED;
+  const int nslot = fwd_info ? Tit / C + 1 : 1;  // e_marg history, as solve_impl keeps it
   Work<T> W;
-  ST_TRY(carve<T>(P, Lo, nitems, true, 1, W));
+  ST_TRY(carve<T>(P, Lo, nitems, true, nslot, W));
   std::vector<double> eps(nitems), tau(nitems), tv(nitems);
   for (int i = 0; i < nitems; ++i) {
     eps[i] = S.prm[i].eps;
@@ -1451,6 +1464,7 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
         a.k = k;
         a.ubuf0 = a.ubuf1 = hu + F * slot;
         if (k == k0 + 1 && k0 > 0) a.gk = ckg + (size_t)(seg - 1) * nitems;
+        if (fwd_info && k - 1 >= 1 && (k - 1) % C == 0) a.chk_slot = (k - 1) / C - 1;
         return run_rows<T>(P, a, G.count, s);
       }));
       if (!unbal)  // s_k = sum u-hat_k
@@ -1472,6 +1486,26 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
           RowArgs<T> a = base_args(G, P->grids[G.grid]);
           HIP_TRY(launch_gauge3<T>(a, G.count, k, gh + (size_t)slot * nitems * 3, s));
         }
+    }
+    if (fwd_info) {
+      // the forward pass is complete (one segment): e_marg of the returned
+      // scalings, potentials' cost and the reports, as at the end of solve_impl
+      const int final_slot = (Tit % C == 0) ? Tit / C - 1 : nslot - 1;
+      T* u_last = hu + F * (size_t)(Tit - 1);
+      T* v_last = hv + F * (size_t)(Tit - 1);
+      ST_TRY(each([&](const Group& G, const GridRec& g) {
+        shot_status st = leg(G, g, W.spec);
+        if (st != SHOT_OK) return st;
+        RowArgs<T> a = base_args(G, g);
+        a.mode = ROW_CHECK;
+        a.k = Tit + 1;
+        a.chk_slot = final_slot;
+        a.ubuf0 = a.ubuf1 = u_last;
+        a.vbuf0 = a.vbuf1 = v_last;
+        return run_rows<T>(P, a, G.count, s);
+      }));
+      ST_TRY(finish_solve<T>(P, Lo, W, nitems, Tit, C, final_slot, 0.0, nullptr, nullptr, fwd_info, fwd_mass, s,
+                             u_last, v_last));
     }
     // walk the segment backwards
     if (unbal) {
@@ -1592,6 +1626,64 @@ shot_status divergence_grad_impl(shot_plan_s* P, const int32_t* gop, int npairs,
   }
   const T* pb = static_cast<const T*>(p);
   const T* qb = static_cast<const T*>(q);
+  if (mode == 0 && CK <= 0) {
+    // the reverse sweep's forward pass over the (p,q) and (p,p) solves keeps the
+    // whole history and reports them; only the (q,q) solves run separately
+    SolveSpec S2, S1;
+    for (int i = 0; i < npairs; ++i) {
+      const T* pi = pb + Lp.user_foff[i];
+      const T* qi = qb + Lp.user_foff[i];
+      const void* ps[3] = {pi, pi, qi};
+      const void* qs[3] = {qi, pi, qi};
+      for (int r = 0; r < 3; ++r) {
+        SolveSpec& D = r < 2 ? S2 : S1;
+        D.grid.push_back(gop[i]);
+        D.prm.push_back(params[i]);
+        D.p.push_back(ps[r]);
+        D.q.push_back(qs[r]);
+      }
+    }
+    Layout L2;
+    ST_TRY(make_layout(P, S2.grid.data(), 2 * npairs, L2));
+    if (whole_history_fits<T>(L2.field_total, params[0].max_iter)) {
+      std::vector<shot_solve_info> inf2(2 * (size_t)npairs), inf1(npairs), inf(3 * (size_t)npairs);
+      std::vector<double> mass2(4 * (size_t)npairs), mass1(2 * (size_t)npairs), mass(6 * (size_t)npairs);
+      T* gA = nullptr;
+      T* gB = nullptr;
+      ST_TRY(adjoint_impl<T>(P, S2, 0, &gA, &gB, L2, s, inf2.data(), mass2.data()));
+      ST_TRY(solve_impl<T>(P, S1, nullptr, nullptr, inf1.data(), mass1.data(), s));
+      for (int i = 0; i < npairs; ++i) {
+        for (int r = 0; r < 3; ++r) {
+          inf[3 * i + r] = r < 2 ? inf2[2 * i + r] : inf1[i];
+          mass[6 * i + 2 * r] = r < 2 ? mass2[4 * i + 2 * r] : mass1[2 * i];
+          mass[6 * i + 2 * r + 1] = r < 2 ? mass2[4 * i + 2 * r + 1] : mass1[2 * i + 1];
+        }
+      }
+      combine_divergence(params, npairs, inf.data(), mass.data(), S_out);
+      if (info) std::copy(inf.begin(), inf.end(), info);
+      std::vector<CombineDev> dv(npairs);
+      for (int i = 0; i < npairs; ++i) {
+        const GridRec& g = P->grids[gop[i]];
+        CombineDev& d = dv[i];
+        d.off_out = Lp.user_foff[i];
+        d.off1 = L2.user_foff[2 * i];      // p-bar of (p,q)
+        d.off2 = L2.user_foff[2 * i + 1];  // p-bar of (p,p)
+        d.off3 = L2.user_foff[2 * i + 1];  // q-bar of (p,p)
+        d.x1 = gA;
+        d.x2 = gA;
+        d.x3 = gB;
+        d.mul_area = 0;
+        d.coef = params[i].eps * (mass[6 * i] - mass[6 * i + 1]);
+        d.nlat = g.d.nlat;
+        d.nlon = g.d.nlon;
+        d.n = g.n();
+        d.equal_area = g.hp ? 1 : 0;
+        d.h = g.h;
+        d.aw = g.d_aw;
+      }
+      return combine_pairs<T>(P, dv, dS, s);
+    }
+  }
   // forward divergence: three solves per pair (potentials kept for the envelope form)
   SolveSpec S3;
   for (int i = 0; i < npairs; ++i) {

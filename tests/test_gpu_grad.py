@@ -104,6 +104,37 @@ def test_whole_history_and_checkpointed_adjoints_agree(prec, tau):
     assert np.isfinite(to_np(out[0][1])).all()
 
 
+@pytest.mark.parametrize("prec,tau,ipb", [("fp32", math.inf, 0), ("fp32", 1.0, 0), ("fp32", math.inf, 8),
+                                            ("fp64", math.inf, 0), ("fp64", 0.5, 0)])
+def test_gradient_call_reports_the_divergence_solves(prec, tau, ipb):
+    """divergence_grad takes S and the solve reports of the (p,q) and (p,p) solves
+    from the reverse sweep's forward pass (whole history kept) and runs only the
+    (q,q) solves separately; S, costs, statuses and kernel ratios equal those of
+    shot_sinkhorn_divergence bit for bit, and the gradient equals the checkpointed
+    path's (where the three solves run first)."""
+    grid = ("gl", 32, 64, 32)
+    announce(f"gradient call solve reports {prec} tau={tau} ipb={ipb}")
+    g = O.make_grid(*grid)
+    P = _plan([grid], prec)
+    if ipb:
+        P.set_tuning(0, ipb, 0)
+    ps, qs = [], []
+    for i in range(3):
+        p, q = synth.temperature_pair(30 + i, g.x, g.w, g.nlon, K=4, q_mass=1.0 if math.isinf(tau) else 1.05)
+        ps.append(p)
+        qs.append(q)
+    pd, qd = to_dev(np.stack(ps), P.dtype), to_dev(np.stack(qs), P.dtype)
+    eps, T = 0.1, 40
+    S_d, info_d = P.divergence(pd, qd, eps, tau, T=T)
+    S_g, G_g, info_g = P.divergence_grad(pd, qd, eps, T=T, tau=tau)
+    _, G_c, _ = P.divergence_grad(pd, qd, eps, T=T, tau=tau, checkpoint_every=7)
+    assert np.array_equal(S_g, S_d), (S_g, S_d)
+    for a, b in zip(info_g, info_d):
+        for k in ("cost", "err", "status", "breakdown_iter", "kratio", "iters"):
+            assert a[k] == b[k], (k, a[k], b[k])
+    assert np.array_equal(to_np(G_g), to_np(G_c))
+
+
 def test_unbalanced_gradient_through_autograd():
     import torch
     from paper_2605_18389_amd.autograd import sinkhorn_divergence
