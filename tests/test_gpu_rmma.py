@@ -97,3 +97,28 @@ def test_rmma_tuning_and_autotune():
     with pytest.raises(ShotError):
         from paper_2605_18389_amd import Plan
         Plan([("gl", 90, 180, 90)], precision="bf16x3", legendre="table")
+
+
+@pytest.mark.parametrize("prec,ipb", [("fp32", 8), ("bf16x3", 0), ("bf16", 0)])
+def test_rmma_rough_input_and_item_independence(prec, ipb):
+    """White noise (energy at every degree the grid holds, unlike the smooth
+    temperature-like fields): the heat apply against the oracle at the same
+    bounds, and each item of a batch equal bit for bit to the same item alone
+    (items never share arithmetic)."""
+    grid = ("gl", 180, 360, 180)
+    announce(f"rmma rough input {prec} ipb={ipb}")
+    P = _plan([grid], prec)
+    if ipb:
+        P.set_tuning(0, ipb, 0)
+    g = O.make_grid(*grid)
+    rng = np.random.default_rng(17)
+    v = rng.random((5, g.nlat, g.nlon))
+    t = [1e-3, 1e-4, 4e-2, 1e-3, 2e-3]
+    out = to_np(P.heat_apply(to_dev(v, P.dtype), t)).reshape(v.shape)
+    for i in (0, 2):
+        err = rel_l2(out[i], O.heat_apply(v[i], g, t[i]))
+        print(f"  item {i} t={t[i]}: rel L2 {err:.2e} (bound {BOUND[prec]:.0e})", flush=True)
+        assert err < BOUND[prec]
+    for i in range(5):
+        alone = to_np(P.heat_apply(to_dev(v[i:i + 1], P.dtype), [t[i]])).reshape(v.shape[1:])
+        assert np.array_equal(alone, out[i]), i
