@@ -104,6 +104,10 @@ struct shot_plan_s {
   // fixed-T solve loops are captured once into a HIP graph and replayed
   bool graphs = true;
   hipStream_t cap = nullptr;
+  // side streams of a captured solve: one branch per grid group after the
+  // first, forked from and joined back into the capture stream
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> bev;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<long long> gkey;
@@ -1051,6 +1055,49 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
       return st != SHOT_OK ? st : rows(G, g, ROW_CHECK, K + 1, final_slot);
     });
   };
+  // Under capture, the grid groups of a call touch disjoint items: each group's
+  // whole loop is recorded on its own branch (the first on the capture stream,
+  // the others on side streams forked from it and joined back), so that the
+  // replayed graph can run the groups side by side.
+  auto fixed_loop_branches = [&]() -> shot_status {
+    const int ng = (int)Lo.groups.size();
+    if (ng == 1) return fixed_loop();
+    while ((int)P->branch.size() < ng - 1) {
+      hipStream_t b = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+      P->branch.push_back(b);
+    }
+    while ((int)P->bev.size() < ng) {
+      hipEvent_t e = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      P->bev.push_back(e);
+    }
+    hipStream_t cs = ls;
+    HIP_TRY(hipEventRecord(P->bev[0], cs));
+    for (int gi = 0; gi < ng; ++gi) {
+      const Group& G = Lo.groups[gi];
+      const GridRec& g = P->grids[G.grid];
+      ls = gi == 0 ? cs : P->branch[gi - 1];
+      if (gi > 0) HIP_TRY(hipStreamWaitEvent(ls, P->bev[0], 0));
+      ST_TRY(rows(G, g, ROW_INIT, 0, -1));
+      for (int k = 1; k <= T_iter; ++k) {
+        const bool chk_prev = (k - 1 >= 1) && ((k - 1) % C == 0);
+        const int slot = chk_prev ? (k - 1) / C - 1 : -1;
+        ST_TRY(leg(G, g));
+        ST_TRY(rows(G, g, ROW_SINK_U, k, slot));
+        ST_TRY(leg(G, g));
+        ST_TRY(rows(G, g, ROW_SINK_V, k, -1));
+      }
+      ST_TRY(leg(G, g));
+      ST_TRY(rows(G, g, ROW_CHECK, K + 1, final_slot));
+    }
+    for (int gi = 1; gi < ng; ++gi) {
+      HIP_TRY(hipEventRecord(P->bev[gi], P->branch[gi - 1]));
+      HIP_TRY(hipStreamWaitEvent(cs, P->bev[gi], 0));
+    }
+    ls = cs;
+    return SHOT_OK;
+  };
   // (event timing needs eager launches: events recorded inside a graph cannot be timed)
   if (tol == 0 && P->graphs && !P->prof) {
     std::vector<long long> key = {(long long)(uintptr_t)P->ws.p, (long long)P->ws.bytes, nitems, T_iter, C,
@@ -1067,7 +1114,7 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
       if (!P->cap) HIP_TRY(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
       HIP_TRY(hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed));
       ls = P->cap;
-      shot_status st = fixed_loop();
+      shot_status st = fixed_loop_branches();
       ls = s;
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(P->cap, &graph);
@@ -1909,6 +1956,8 @@ shot_status shot_plan_destroy(shot_plan_t P) {
   for (auto& g : P->grids) free_grid(g);
   drop_graph(P);
   if (P->cap) (void)hipStreamDestroy(P->cap);
+  for (auto b : P->branch) (void)hipStreamDestroy(b);
+  for (auto e : P->bev) (void)hipEventDestroy(e);
   if (P->ws.p) (void)hipFree(P->ws.p);
   if (P->ws2.p) (void)hipFree(P->ws2.p);
   for (auto e : P->evpool) (void)hipEventDestroy(e);
