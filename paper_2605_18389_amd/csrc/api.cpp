@@ -1371,7 +1371,8 @@ char* scratch_of(int dev) {
 // ---------------------------------------------------------------------------
 template <typename T>
 shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_out, T** qbar_out,
-                         Layout& Lo, hipStream_t s, shot_solve_info* fwd_info = nullptr, double* fwd_mass = nullptr) {
+                         Layout& Lo, hipStream_t s, shot_solve_info* fwd_info = nullptr, double* fwd_mass = nullptr,
+                         int nrev = -1) {
   const int nitems = (int)S.grid.size();
   ST_TRY(make_layout(P, S.grid.data(), nitems, Lo));
   const int Tit = S.prm[0].max_iter;
@@ -1438,8 +1439,27 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
     a.vbar = vbar;
     return a;
   };
+  // items of each group that the reverse sweep runs: all, or (nrev >= 0) the
+  // call's first nrev items, which open every group (the others, after them,
+  // run forward only: their solves are reported, not differentiated)
+  std::vector<int> rev_count(Lo.groups.size());
+  for (size_t gi = 0; gi < Lo.groups.size(); ++gi) {
+    const Group& G = Lo.groups[gi];
+    int n = 0;
+    for (int q = G.first; q < G.first + G.count; ++q) n += (nrev < 0 || Lo.order[q] < nrev) ? 1 : 0;
+    for (int q = G.first; q < G.first + n; ++q)
+      if (!(nrev < 0 || Lo.order[q] < nrev)) return SHOT_E_UNSUPPORTED;
+    rev_count[gi] = n;
+  }
+  if (nrev >= 0 && !fwd_info) return SHOT_E_UNSUPPORTED;  // forward-only items need the one-pass form
+  bool reverse_phase = false;
   auto each = [&](auto&& fn) -> shot_status {
-    for (const Group& G : Lo.groups) {
+    for (size_t gi = 0; gi < Lo.groups.size(); ++gi) {
+      Group G = Lo.groups[gi];
+      if (reverse_phase) {
+        G.count = rev_count[gi];
+        if (G.count == 0) continue;
+      }
       shot_status st = fn(G, P->grids[G.grid]);
       if (st != SHOT_OK) return st;
     }
@@ -1555,6 +1575,7 @@ shot_status adjoint_impl(shot_plan_s* P, const SolveSpec& S, int CK, T** pbar_ou
                              u_last, v_last));
     }
     // walk the segment backwards
+    reverse_phase = true;
     if (unbal) {
       for (int k = k1; k > k0; --k) {
         const int slot = k - k0 - 1;
@@ -1674,36 +1695,43 @@ shot_status divergence_grad_impl(shot_plan_s* P, const int32_t* gop, int npairs,
   const T* pb = static_cast<const T*>(p);
   const T* qb = static_cast<const T*>(q);
   if (mode == 0 && CK <= 0) {
-    // the reverse sweep's forward pass over the (p,q) and (p,p) solves keeps the
-    // whole history and reports them; only the (q,q) solves run separately
-    SolveSpec S2, S1;
+    // one forward pass over all three solves of every pair keeps the whole
+    // history and reports them; the reverse sweep then runs the (p,q) and (p,p)
+    // solves, which come first (the (q,q) solves follow, forward only)
+    SolveSpec S2;
     for (int i = 0; i < npairs; ++i) {
       const T* pi = pb + Lp.user_foff[i];
       const T* qi = qb + Lp.user_foff[i];
-      const void* ps[3] = {pi, pi, qi};
-      const void* qs[3] = {qi, pi, qi};
-      for (int r = 0; r < 3; ++r) {
-        SolveSpec& D = r < 2 ? S2 : S1;
-        D.grid.push_back(gop[i]);
-        D.prm.push_back(params[i]);
-        D.p.push_back(ps[r]);
-        D.q.push_back(qs[r]);
+      const void* ps[2] = {pi, pi};
+      const void* qs[2] = {qi, pi};
+      for (int r = 0; r < 2; ++r) {
+        S2.grid.push_back(gop[i]);
+        S2.prm.push_back(params[i]);
+        S2.p.push_back(ps[r]);
+        S2.q.push_back(qs[r]);
       }
     }
+    for (int i = 0; i < npairs; ++i) {
+      const T* qi = qb + Lp.user_foff[i];
+      S2.grid.push_back(gop[i]);
+      S2.prm.push_back(params[i]);
+      S2.p.push_back(qi);
+      S2.q.push_back(qi);
+    }
     Layout L2;
-    ST_TRY(make_layout(P, S2.grid.data(), 2 * npairs, L2));
+    ST_TRY(make_layout(P, S2.grid.data(), 3 * npairs, L2));
     if (whole_history_fits<T>(L2.field_total, params[0].max_iter)) {
-      std::vector<shot_solve_info> inf2(2 * (size_t)npairs), inf1(npairs), inf(3 * (size_t)npairs);
-      std::vector<double> mass2(4 * (size_t)npairs), mass1(2 * (size_t)npairs), mass(6 * (size_t)npairs);
+      std::vector<shot_solve_info> inf2(3 * (size_t)npairs), inf(3 * (size_t)npairs);
+      std::vector<double> mass2(6 * (size_t)npairs), mass(6 * (size_t)npairs);
       T* gA = nullptr;
       T* gB = nullptr;
-      ST_TRY(adjoint_impl<T>(P, S2, 0, &gA, &gB, L2, s, inf2.data(), mass2.data()));
-      ST_TRY(solve_impl<T>(P, S1, nullptr, nullptr, inf1.data(), mass1.data(), s));
+      ST_TRY(adjoint_impl<T>(P, S2, 0, &gA, &gB, L2, s, inf2.data(), mass2.data(), 2 * npairs));
       for (int i = 0; i < npairs; ++i) {
         for (int r = 0; r < 3; ++r) {
-          inf[3 * i + r] = r < 2 ? inf2[2 * i + r] : inf1[i];
-          mass[6 * i + 2 * r] = r < 2 ? mass2[4 * i + 2 * r] : mass1[2 * i];
-          mass[6 * i + 2 * r + 1] = r < 2 ? mass2[4 * i + 2 * r + 1] : mass1[2 * i + 1];
+          const int u = r < 2 ? 2 * i + r : 2 * npairs + i;
+          inf[3 * i + r] = inf2[u];
+          mass[6 * i + 2 * r] = mass2[2 * u];
+          mass[6 * i + 2 * r + 1] = mass2[2 * u + 1];
         }
       }
       combine_divergence(params, npairs, inf.data(), mass.data(), S_out);
