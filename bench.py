@@ -2,10 +2,19 @@
 
 One step = one full Alg. 1 solve (T = 1000 iterations, balanced, t = 1e-4) of a
 seeded temperature-like pair (32 anomalies) already resident in HBM, through
-the libshot C ABI.  Prints ONE JSON line (see --help).  Also reported in the
-same line: the dominant kernel's roofline (timed live with HIP events on the
-launch stream), the FP64 oracle timed on the host cores on a bounded sample,
-and secondary measurements (the BF16 form, the other Legendre mode).
+the libshot C ABI.  Prints ONE JSON line (see --help) with, beside `value`:
+* roofline: the dominant (Legendre) kernel, timed live with HIP events on its
+  launch stream, with the calibrated HBM traffic of profiles/traffic.json;
+* cpu_baseline: the FP64 oracle on the host cores (and on one thread), on a
+  bounded sample of the same workload;
+* secondary: the other Legendre forms (fp32 table, bfloat16 table, fp64,
+  split bfloat16) at the same shape, the headline divergence, HEALPix and the
+  climate attribution;
+* companions: full-size workloads whose runs stay finite, each with its S and
+  cost errors against stored oracle results (tests/golden/);
+* batched: the 16-pair 360x720 divergence + gradient and the 256-pair uneven
+  batch per form, with status agreement and S errors against the stored
+  oracle pairs and the matrix-core kernel's roofline at the batch's shape.
 
 Single GPU only: --gpus N with N > 1 exits with a message.
 """
