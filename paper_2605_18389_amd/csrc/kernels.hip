@@ -2386,6 +2386,12 @@ struct RmTraits<RM_F32> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a.v, b.v, c, 0, 0, 0);
   }
   __device__ static Op make(const float (&x)[1]) { return {x[0]}; }
+  // four consecutive elements, idx a multiple of 2
+  __device__ static void put4(unsigned char* base, size_t plane, size_t idx, const float (&v)[4]) {
+    float2* p = reinterpret_cast<float2*>(reinterpret_cast<float*>(base) + idx);
+    p[0] = make_float2(v[0], v[1]);
+    p[1] = make_float2(v[2], v[3]);
+  }
 };
 template <>
 struct RmTraits<RM_BF16> {
@@ -2405,6 +2411,10 @@ struct RmTraits<RM_BF16> {
   }
   __device__ static Op make(const float (&x)[4]) {
     return {make_uint2(rm_bf16(x[0]) | (rm_bf16(x[1]) << 16), rm_bf16(x[2]) | (rm_bf16(x[3]) << 16))};
+  }
+  // four consecutive elements, idx a multiple of 4
+  __device__ static void put4(unsigned char* base, size_t plane, size_t idx, const float (&v)[4]) {
+    *reinterpret_cast<uint2*>(reinterpret_cast<unsigned short*>(base) + idx) = make(v).h;
   }
 };
 template <>
@@ -2441,6 +2451,13 @@ struct RmTraits<RM_BF16X3> {
     }
     return {make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16)),
             make_uint2(lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16))};
+  }
+  // four consecutive elements, idx a multiple of 4
+  __device__ static void put4(unsigned char* base, size_t plane, size_t idx, const float (&v)[4]) {
+    const Op o = make(v);
+    unsigned short* p = reinterpret_cast<unsigned short*>(base);
+    *reinterpret_cast<uint2*>(p + idx) = o.h;
+    *reinterpret_cast<uint2*>(p + plane + idx) = o.l;
   }
 };
 
@@ -2493,7 +2510,7 @@ __host__ __device__ inline RmLayout rm_layout(int L, int h, int nt, int nw, int 
   q.o_d = take(sizeof(float) * nw * 2 * q.ncol * 20);
   q.o_b = take(q.bplane * planes * es);
   q.o_c = take(sizeof(double) * (32 * q.nb + 1));
-  q.o_s = take(sizeof(double) * 32 + sizeof(float) * 8 * nt * 32);  // the block's gamma and h_l
+  q.o_s = take(sizeof(double) * 2 * 8 * nt * 16);  // the block's gamma^2 h_l per parity, item, row
   q.total = off;
   return q;
 }
@@ -2531,8 +2548,7 @@ legendre_rmma_kernel(LegArgs<T> A) {
   const long long toff = tri_off(m, L);
   const int nit = min(8 * NT, A.nb - c0 / 2);                 // items of this chunk
   const int ncomb = 2 * 16 * Q.ncol;                           // combine elements per block
-  double* gsl = reinterpret_cast<double*>(smem_raw + Q.o_s);  // [32] gamma of the block's rows
-  float* hsl = reinterpret_cast<float*>(gsl + 32);           // [8 NT][32] h_l of the block's rows
+  double* scd = reinterpret_cast<double*>(smem_raw + Q.o_s);  // [parity][8 NT items][16 rows] gamma^2 h_l
   // items of one launch group are consecutive in the workspace, each holding
   // 2 L h complex spectral entries: this chunk's spectra start here
   const float4* spc = reinterpret_cast<const float4*>(A.spec + A.soff0) + (size_t)(c0 / 2) * L * h + (size_t)m * h;
@@ -2679,15 +2695,23 @@ legendre_rmma_kernel(LegArgs<T> A) {
         for (int t = 0; t < NT; ++t) acc[par][t] = TR::mma(a, yb[s][par][t], acc[par][t]);
       }
     }
-    if (tid < 32) gsl[tid] = r0 + tid < nr ? gld : 0.0;
+    // the combine's scale gamma^2 h_l per (parity, item, row of the parity);
+    // zero past the order's end and past the chunk's items (blockDim is a
+    // multiple of 32, so e & 31 is this thread's gamma row)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int e = tid + u * (int)blockDim.x;
-      if (e < 8 * NT * 32) hsl[e] = (r0 + (e & 31) < nr && (e >> 5) < nit) ? hld[u] : 0.f;
+      const int e = tid + u * (int)blockDim.x, i = e >> 5, rr = e & 31;
+      if (e < 8 * NT * 32) {
+        const double g = r0 + rr < nr && i < nit ? gld : 0.0;
+        scd[((rr & 1) * 8 * NT + i) * 16 + (rr >> 1)] = g * g * (double)hld[u];
+      }
     }
     for (int e = tid + 2 * blockDim.x; e < 8 * NT * 32; e += blockDim.x) {  // one-wave workgroups of 16 items
-      const int i = e >> 5, r = r0 + (e & 31);
-      hsl[e] = (r < nr && i < nit) ? A.hl[(size_t)(A.item0 + c0 / 2 + i) * A.hl_stride + m + r] : 0.f;
+      const int i = e >> 5, rr = e & 31, r = r0 + rr;
+      const bool ok = r < nr && i < nit;
+      const double g = ok ? A.rgam[toff + r] : 0.0;
+      const float hv = ok ? (float)A.hl[(size_t)(A.item0 + c0 / 2 + i) * A.hl_stride + m + r] : 0.f;
+      scd[((rr & 1) * 8 * NT + i) * 16 + (rr >> 1)] = g * g * (double)hv;
     }
     // wave partials, [wave][parity][column][row of the parity] (rows padded to 20)
 #pragma unroll
@@ -2698,15 +2722,20 @@ legendre_rmma_kernel(LegArgs<T> A) {
             acc[par][t];
     __syncthreads();
     // b = gamma^2 h_l (sum over the waves), in the operand format, rows of one
-    // parity contiguous; rows past the order's end are zero (gamma is zero there)
-    for (int idx = tid; idx < ncomb; idx += blockDim.x) {
-      const int pn = idx >> 4, rp = idx & 15;
-      const int par = pn / Q.ncol, n = pn - par * Q.ncol;
-      float sum = 0.f;
-      for (int w = 0; w < nw; ++w) sum += Dp[(((size_t)w * 2 + par) * Q.ncol + n) * 20 + rp];
-      const double g = gsl[2 * rp + par];
-      const double sc = g * g * (double)hsl[(n >> 1) * 32 + 2 * rp + par];
-      TR::put(Bs, Q.bplane, ((size_t)par * Q.ncol + n) * Q.bld + rp, (float)((double)sum * sc));
+    // parity contiguous, four rows per thread; rows past the order's end are
+    // zero (their scale is zero)
+    for (int idx = tid; idx < ncomb / 4; idx += blockDim.x) {
+      constexpr int NC = 16 * NT;
+      const int pn = idx >> 2, q4 = idx & 3;
+      const int par = pn >= NC ? 1 : 0, n = pn - par * NC;
+      const f32x4_t* dp = reinterpret_cast<const f32x4_t*>(Dp) + (par * NC + n) * 5 + q4;
+      f32x4_t sum = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      for (int w = 0; w < nw; ++w) sum += dp[w * 2 * NC * 5];
+      const double* sc = scd + (par * 8 * NT + (n >> 1)) * 16 + 4 * q4;
+      float o[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o[e] = (float)((double)sum[e] * sc[e]);
+      TR::put4(Bs, Q.bplane, (size_t)(par * NC + n) * Q.bld + 4 * q4, o);
     }
     __syncthreads();
     // the block's synthesis term
