@@ -48,8 +48,6 @@ struct GridRec {
   std::vector<int> fac;
   int tab_kind = TAB_F32;
   void* d_tab = nullptr;
-  void* d_tabT = nullptr;            // transposed per-(m, parity) blocks for the MFMA kernel
-  long long* d_toffT = nullptr;      // [2L] offsets of those blocks
   int* d_morder = nullptr;           // [L] order run by MFMA workgroup column b (rows balanced over units)
   double* d_xs = nullptr;
   double* d_rcoef = nullptr;
@@ -77,6 +75,11 @@ struct GridRec {
                      // tiles (1, 2, 4), 0 = automatic, -1 = VALU kernel only
   int64_t n() const { return hp ? 12LL * nside * nside : (int64_t)d.nlat * d.nlon; }
 };
+
+// float32 or bfloat16 table plans run the matrix-core table kernel
+static bool mma_table(const GridRec& g) {
+  return g.d_tab != nullptr && (g.tab_kind == TAB_F32 || g.tab_kind == TAB_BF16);
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -212,15 +215,14 @@ uint16_t to_bf16(double v) {
 }
 
 void free_grid(GridRec& g) {
-  for (void* p : {g.d_tab, g.d_tabT, (void*)g.d_toffT, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam,
+  for (void* p : {g.d_tab, (void*)g.d_xs, (void*)g.d_rcoef, (void*)g.d_rgam,
                   (void*)g.d_rseed, (void*)g.sw.d_parts, (void*)g.sw.d_ck, (void*)g.ss.d_parts,
                   (void*)g.ss.d_ck, (void*)g.d_morder, (void*)g.d_ring, (void*)g.d_rpair, g.d_ring_tw, g.d_ring_ph, g.d_ring_blu, (void*)g.d_cut, g.d_pbuf, g.d_aw, g.d_tw})
     if (p) (void)hipFree(p);
-  g.d_tab = g.d_tabT = g.d_aw = g.d_tw = g.d_pbuf = g.d_ring_tw = g.d_ring_ph = g.d_ring_blu = nullptr;
+  g.d_tab = g.d_aw = g.d_tw = g.d_pbuf = g.d_ring_tw = g.d_ring_ph = g.d_ring_blu = nullptr;
   g.d_morder = nullptr;
   g.d_ring = nullptr;
   g.d_rpair = nullptr;
-  g.d_toffT = nullptr;
   g.d_xs = g.d_rcoef = g.d_rgam = g.d_rseed = nullptr;
   g.sw = SplitSched{};
   g.ss = SplitSched{};
@@ -392,30 +394,6 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
     std::vector<double> tab;
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     legendre_rows(d.L, xs, g.hpad, tab, (int)hw);
-    // transposed per-(m, parity) blocks [round_up(h,16)][mma_rpad(rows)] for the MFMA kernel
-    std::vector<long long> toffT;
-    std::vector<double> tabT;
-    if (P->prec != SHOT_FP64) {
-      const int hT = (g.h + 15) / 16 * 16;
-      toffT.resize(2 * (size_t)d.L);
-      long long off = 0;
-      for (int m = 0; m < d.L; ++m)
-        for (int par = 0; par < 2; ++par) {
-          toffT[2 * m + par] = off;
-          off += (long long)hT * mma_rpad((d.L - m + 1 - par) / 2);
-        }
-      tabT.assign((size_t)off, 0.0);
-      for (int m = 0; m < d.L; ++m)
-        for (int par = 0; par < 2; ++par) {
-          const int npar = (d.L - m + 1 - par) / 2, rpad = mma_rpad(npar);
-          double* blk = tabT.data() + toffT[2 * m + par];
-          for (int rp = 0; rp < npar; ++rp) {
-            const double* row = tab.data() + (tri_offset(m, d.L) + 2 * rp + par) * g.hpad;
-            for (int j = 0; j < g.h; ++j) blk[(size_t)j * rpad + rp] = row[j];
-          }
-        }
-      if ((st = upload((void**)&g.d_toffT, toffT, s)) != SHOT_OK) return st;
-    }
     if (P->prec == SHOT_FP64) {
       g.tab_kind = TAB_F64;
       st = upload(&g.d_tab, tab, s);
@@ -423,23 +401,14 @@ shot_status build_grid(shot_plan_s* P, GridRec& g, int leg_mode, hipStream_t s) 
       g.tab_kind = TAB_F32;
       std::vector<float> t32(tab.begin(), tab.end());
       st = upload(&g.d_tab, t32, s);
-      if (st == SHOT_OK) {
-        std::vector<float> tT(tabT.begin(), tabT.end());
-        st = upload(&g.d_tabT, tT, s);
-      }
     } else {
       g.tab_kind = TAB_BF16;
       std::vector<uint16_t> t16(tab.size());
       for (size_t i = 0; i < tab.size(); ++i) t16[i] = to_bf16(tab[i]);
       st = upload(&g.d_tab, t16, s);
-      if (st == SHOT_OK) {
-        std::vector<uint16_t> tT(tabT.size());
-        for (size_t i = 0; i < tabT.size(); ++i) tT[i] = to_bf16(tabT[i]);
-        st = upload(&g.d_tabT, tT, s);
-      }
     }
     if (st != SHOT_OK) return st;
-    if (g.d_tabT) {
+    if (mma_table(g)) {
       // the MFMA kernel runs one order per workgroup column: deal the orders
       // so that the rows meeting on one compute unit add up evenly
       std::vector<int> rows(d.L);
@@ -747,9 +716,7 @@ LegArgs<T> leg_args(const GridRec& g, const Group& G, const Work<T>& W, int hl_s
   a.h = g.h;
   a.hpad = g.hpad;
   a.tab = g.d_tab;
-  a.tabT = g.d_tabT;
   a.morder = g.d_morder;
-  a.toffT = g.d_toffT;
   a.xs = g.d_xs;
   a.rcoef = g.d_rcoef;
   a.rgam = g.d_rgam;
@@ -805,7 +772,7 @@ bool use_split(const shot_plan_s* P, const GridRec& g) {
 // the VALU kernels.  Automatic: matrix cores from 4 items on, the widest tile
 // count (<= the batch) whose LDS staging fits.
 int mma_tiles(const shot_plan_s* P, const GridRec& g, int count) {
-  if (!g.d_tabT || (g.tab_kind != TAB_F32 && g.tab_kind != TAB_BF16) || g.tune_jpt < 0) return 0;
+  if (!mma_table(g) || g.tune_jpt < 0) return 0;
   int nt = g.tune_jpt;
   // Matrix cores for any item count: they stream the table faster than the
   // VALU table kernel even for a single item (one item at L = 720: bf16
@@ -1263,7 +1230,7 @@ shot_status autotune_impl(shot_plan_s* P, GridRec& g, const Layout& Lo, int nite
       cand.push_back({ib, -1});  // VALU table kernel
     }
   }
-  if (g.tab_kind != TAB_RECUR && g.d_tabT)
+  if (mma_table(g))
     for (int nt : {1, 2, 4})
       if (16 * nt <= 2 * std::max(nitems, 8)) cand.push_back({0, nt});
   if (g.tab_kind == TAB_RECUR && P->prec != SHOT_FP64) {
@@ -2169,7 +2136,7 @@ shot_status shot_plan_set_tuning(shot_plan_t P, int32_t grid, int32_t items_per_
   if (g.tab_kind == TAB_RECUR) {
     if (chains_per_thread != 0 && !recur_jpt_valid(g.h, chains_per_thread)) return SHOT_E_INVALID;
   } else if (chains_per_thread != 0) {
-    const bool mma = g.d_tabT != nullptr;
+    const bool mma = mma_table(g);
     if (!(chains_per_thread == -1 || (mma && (chains_per_thread == 1 || chains_per_thread == 2 ||
                                                 chains_per_thread == 4))))
       return SHOT_E_INVALID;

@@ -2196,8 +2196,23 @@ struct MmaTraits<float> {
   __device__ static void load_a(float* dst, const float* src, bool ok) { *dst = ok ? *src : 0.0f; }
 };
 
-template <typename T, typename TT, int NT, bool NARROW>
-__global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
+// Per-wave synthesis tile of legendre_mma_kernel: 32 table rows x 16 qt
+// latitudes, row pitch in elements.  bfloat16 rows of an odd word count = 1
+// mod 4 put the four lane groups' rows (8 apart) on distinct banks; float rows
+// keep 16-byte alignment.  Eight-wave workgroups take 32-latitude tasks.
+// waves per workgroup: eight for a single item (a launch of one workgroup per
+// order is otherwise too few waves to keep the table stream in flight)
+__host__ __device__ constexpr int mma_waves(bool narrow) { return narrow ? 8 : 4; }
+__host__ __device__ constexpr int mma_tile_q(int nw) { return nw == 8 ? 2 : 4; }
+__host__ __device__ constexpr int mma_tile_ld(int es, int qt) { return es == 2 ? 16 * qt + 2 : 16 * qt + 4; }
+// byte offset of the four tiles: after Y and b, rounded up to 16 bytes
+__host__ __device__ inline size_t mma_tile_off(int L, int hpad, int ns, int es, int pad) {
+  const size_t yb = (size_t)es * 2 * ns * ((size_t)hpad + pad) + (size_t)es * 2 * ns * (mma_rpad((L + 1) / 2) + pad);
+  return (yb + 15) / 16 * 16;
+}
+
+template <typename T, typename TT, int NT, bool NARROW, int NW>
+__global__ void __launch_bounds__(64 * NW) legendre_mma_kernel(LegArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using MT = MmaTraits<TT>;
   constexpr int NB = 16 * NT, KS = MT::KS, KV = MT::KV;
@@ -2222,7 +2237,7 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
 
   // stage Y (zero beyond h and beyond the last column) and clear b: one
   // (parity, column) row per wave at a time, latitudes across the lanes
-  for (int pn = wave; pn < 2 * NS; pn += 4) {
+  for (int pn = wave; pn < 2 * NS; pn += NW) {
     const int par = pn / NS, n = pn - par * NS;
     const int col = c0 + n;  // (the zero row of a NARROW tile: col = 2 >= ncol)
     const bool cok = A.mode != 2 && col < ncol;
@@ -2237,14 +2252,14 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
       dst[j] = MT::cvt(v);
     }
   }
-  for (int idx = tid; idx < 2 * NS * bs_ld; idx += 256) bs[idx] = MT::cvt(0.f);
+  for (int idx = tid; idx < 2 * NS * bs_ld; idx += 64 * NW) bs[idx] = MT::cvt(0.f);
   __syncthreads();
 
   if (A.mode != 2) {
     for (int par = 0; par < 2; ++par) {
       const int npar = (nr + 1 - par) / 2;
       const int Rt = (npar + 15) / 16;
-      for (int t = wave; t < Rt; t += 4) {
+      for (int t = wave; t < Rt; t += NW) {
         f32x4_t acc[NT];
 #pragma unroll
         for (int c = 0; c < NT; ++c) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -2290,7 +2305,7 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
     }
     if (A.mode == 1) return;
   } else {
-    for (int idx = tid; idx < NB * nr; idx += 256) {
+    for (int idx = tid; idx < NB * nr; idx += 64 * NW) {
       const int n = idx / nr, r = idx % nr, col = c0 + n;
       if (col >= ncol) continue;
       const cpx<T> c = A.coeff[A.items[A.item0 + (col >> 1)].coff + toff + r];
@@ -2299,29 +2314,66 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
   }
   __syncthreads();
 
-  const TT* tabT = static_cast<const TT*>(A.tabT);
-  const int Jt = (h + 15) / 16;
-  for (int task = wave; task < 2 * Jt; task += 4) {
-    const int par = task / Jt, jt = task % Jt;
+  // Synthesis G[j][n] = sum_r P[r][j] b[r][n] per parity, from the same
+  // row-major table as the analysis (no second copy: one stream of the table
+  // per launch).  The A operand needs the rows along K, so each wave stages
+  // 32 rows x 64 latitudes of one parity in its own LDS tile (coalesced
+  // 16-byte loads) and reads the operands across the rows.  Tasks: (parity,
+  // 16 QT latitudes), QT 16-latitude tiles per task.
+  constexpr int QT = mma_tile_q(NW);
+  constexpr int TW = mma_tile_ld(sizeof(TT), QT);
+  constexpr int EPL = 16 / sizeof(TT);  // elements per 16-byte load
+  constexpr int LPR = 16 * QT / EPL;    // lanes per tile row
+  constexpr int RPL = 64 / LPR;         // tile rows per load round
+  TT* tw = reinterpret_cast<TT*>(smem_raw + mma_tile_off(L, kpad, NS, sizeof(TT), MT::PAD)) + (size_t)wave * 32 * TW;
+  const int Jq = (h + 16 * QT - 1) / (16 * QT);
+  for (int task = wave; task < 2 * Jq; task += NW) {
+    const int par = task / Jq, jq = task - par * Jq;
     const int npar = (nr + 1 - par) / 2;
-    const int rpad = mma_rpad(npar);
-    const TT* trow = tabT + A.toffT[2 * m + par] + (size_t)(jt * 16 + li) * rpad + lg * KV;
-    f32x4_t acc[NT];
+    f32x4_t acc[QT][NT];
 #pragma unroll
-    for (int c = 0; c < NT; ++c) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    for (int kg = 0; kg < rpad; kg += KG * KS) {
-      TT a[KG][KV];
+    for (int q = 0; q < QT; ++q)
 #pragma unroll
-      for (int s = 0; s < KG; ++s) MT::load_a(a[s], trow + kg + s * KS, kg + s * KS < rpad);
+      for (int c = 0; c < NT; ++c) acc[q][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const int jl = 16 * QT * jq + (lane % LPR) * EPL;  // first latitude of this lane's loads
+    // the next chunk's rows are loaded while this one is contracted
+    uint4 v[32 / RPL];
+    auto load_chunk = [&](int k0) {
 #pragma unroll
-      for (int s = 0; s < KG; ++s) {
-        if (kg + s * KS >= rpad) break;
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-          const TT* bp = bs + ((size_t)par * NS + srow(c * 16 + li)) * bs_ld + kg + s * KS + lg * KV;
-          acc[c] = MT::mma(a[s], bp, acc[c]);
-        }
+      for (int u = 0; u < 32 / RPL; ++u) {
+        const int rp = k0 + u * RPL + lane / LPR;
+        v[u] = rp < npar && jl < kpad
+                   ? *reinterpret_cast<const uint4*>(tab + (size_t)(2 * rp + par) * kpad + jl)
+                   : make_uint4(0, 0, 0, 0);
       }
+    };
+    load_chunk(0);
+    for (int k0 = 0; k0 < npar; k0 += 32) {
+      __builtin_amdgcn_wave_barrier();  // the previous chunk's operand reads come first
+#pragma unroll
+      for (int u = 0; u < 32 / RPL; ++u) {
+        unsigned* d = reinterpret_cast<unsigned*>(tw + (size_t)(u * RPL + lane / LPR) * TW + (lane % LPR) * EPL);
+        d[0] = v[u].x;
+        d[1] = v[u].y;
+        d[2] = v[u].z;
+        d[3] = v[u].w;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (k0 + 32 < npar) load_chunk(k0 + 32);
+#pragma unroll
+      for (int s = 0; s < 32 / KS; ++s)
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+          // A[j][k] = P[row k0 + KS s + KV lg + e][latitude 16 (QT jq + q) + li]
+          TT a[KV];
+#pragma unroll
+          for (int e = 0; e < KV; ++e) a[e] = tw[(size_t)(KS * s + KV * lg + e) * TW + 16 * q + li];
+#pragma unroll
+          for (int c = 0; c < NT; ++c) {
+            const TT* bp = bs + ((size_t)par * NS + srow(c * 16 + li)) * bs_ld + k0 + KS * s + lg * KV;
+            acc[q][c] = MT::mma(a, bp, acc[q][c]);
+          }
+        }
     }
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
@@ -2329,10 +2381,12 @@ __global__ void __launch_bounds__(256) legendre_mma_kernel(LegArgs<T> A) {
       if (col >= ncol) continue;
       cpx<T>* dst = A.spec + A.items[A.item0 + (col >> 1)].soff + (size_t)m * h * 2 + par;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int j = jt * 16 + lg * 4 + i;
-        if (j < h) reinterpret_cast<T*>(&dst[2 * j])[col & 1] = (T)acc[c][i];
-      }
+      for (int q = 0; q < QT; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = 16 * (QT * jq + q) + lg * 4 + i;
+          if (j < h) reinterpret_cast<T*>(&dst[2 * j])[col & 1] = (T)acc[q][c][i];
+        }
     }
   }
 }
@@ -3157,14 +3211,15 @@ template hipError_t launch_legendre_split<float>(const LegArgs<float>&, int, hip
 template hipError_t launch_legendre_split<double>(const LegArgs<double>&, int, hipStream_t);
 
 size_t mma_lds_bytes(int L, int hpad, int nt, int table_kind, bool narrow) {
-  const size_t es = table_kind == TAB_BF16 ? 2 : 4;
-  const size_t pad = table_kind == TAB_BF16 ? 8 : 1;
-  const size_t NB = narrow ? 3 : 16 * nt, RP = mma_rpad((L + 1) / 2);
-  return es * 2 * NB * ((size_t)hpad + pad) + es * 2 * NB * (RP + pad);
+  const int es = table_kind == TAB_BF16 ? 2 : 4;
+  const int pad = table_kind == TAB_BF16 ? 8 : 1;
+  const int NB = narrow ? 3 : 16 * nt, nw = mma_waves(narrow);
+  return mma_tile_off(L, hpad, NB, es, pad) + (size_t)nw * 32 * mma_tile_ld(es, mma_tile_q(nw)) * es;
 }
 
 template <typename T, typename TT, int NT, bool NARROW>
 static hipError_t launch_mma_nt(const LegArgs<T>& a, hipStream_t stream) {
+  constexpr int NW = mma_waves(NARROW);
   dim3 grid(a.L, (2 * a.nb + 16 * NT - 1) / (16 * NT));
   const size_t lds = mma_lds_bytes(a.L, a.hpad, NT, sizeof(TT) == 2 ? TAB_BF16 : TAB_F32, NARROW);
   // The balanced order assumes the launch's workgroups sit three to a compute
@@ -3176,13 +3231,13 @@ static hipError_t launch_mma_nt(const LegArgs<T>& a, hipStream_t stream) {
   if (lds > 65536) {  // long orders of fp32 tables: one workgroup per compute unit
     static size_t attr_bytes = 65536;  // dynamic LDS enabled so far for this instantiation
     if (lds > attr_bytes) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&legendre_mma_kernel<T, TT, NT, NARROW>),
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&legendre_mma_kernel<T, TT, NT, NARROW, NW>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       attr_bytes = lds;
     }
   }
-  SHOT_LAUNCH((legendre_mma_kernel<T, TT, NT, NARROW>), grid, dim3(256), lds, stream, b);
+  SHOT_LAUNCH((legendre_mma_kernel<T, TT, NT, NARROW, NW>), grid, dim3(64 * NW), lds, stream, b);
   return hipGetLastError();
 }
 
@@ -3198,7 +3253,7 @@ static hipError_t launch_mma_tt(const LegArgs<T>& a, int nt, hipStream_t stream)
 
 template <typename T>
 hipError_t launch_legendre_mma(const LegArgs<T>& a, int table_kind, int nt, hipStream_t stream) {
-  if (!a.tabT || a.hpad % 32) return hipErrorInvalidValue;
+  if (a.hpad % 32) return hipErrorInvalidValue;
   if (table_kind == TAB_BF16) return launch_mma_tt<T, unsigned short>(a, nt, stream);
   if (table_kind == TAB_F32) return launch_mma_tt<T, float>(a, nt, stream);
   return hipErrorInvalidValue;

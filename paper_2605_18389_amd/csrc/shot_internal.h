@@ -139,9 +139,7 @@ template <typename T>
 struct LegArgs {
   int L, h, hpad;
   const void* tab;        // TABLE mode: [L(L+1)/2][hpad] P̄ rows
-  const void* tabT;       // TABLE mode, MFMA kernel: per (m, parity) block [round_up(h,16)][rpad] of P̄ transposed
   const int* morder;      // MFMA kernel: order run by workgroup column b (nullptr: b itself)
-  const long long* toffT; // [2L] element offsets of those blocks
   const double* xs;       // RECURRENCE mode: h nodes
   const double* rcoef;    // [L(L+1)/2]
   const double* rgam;     // [L(L+1)/2]
