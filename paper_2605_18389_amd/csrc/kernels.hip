@@ -2392,6 +2392,160 @@ __global__ void __launch_bounds__(64 * NW) legendre_mma_kernel(LegArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// Single-item table Legendre stage of a heat apply on the vector units.  For
+// one item the contractions are matrix-vector products bound by the table
+// stream, so each table element is read once and used for both:
+//   analysis   f_r = sum_j P_r(x_j) y_j     lane partials over the lane's 8
+//              latitudes, then a reduction across the wave (permlane swaps
+//              for lane bits 5 and 4, DPP for bits 3 .. 0) that leaves row
+//              tile value k = 2 rr + c in lanes 4k .. 4k+3
+//   b_r = h_l f_r, passed to the wave's lanes through LDS
+//   synthesis  G_j += P_r(x_j) b_r          the lane's own latitudes
+// One workgroup of NW waves per order m; wave w takes rows of parity w & 1,
+// 8 at a time, lane L latitudes 8L .. 8L+7 (16-byte loads of the row-major
+// table).  Loading the next tile ahead of the current one's use measured
+// slower (a second tile of registers halves the resident waves).
+// The waves' partial G of one parity are added in LDS in wave order.
+// ---------------------------------------------------------------------------
+template <typename TT>
+struct GemvRow;
+template <>
+struct GemvRow<unsigned short> {  // 8 bfloat16 latitudes in one 16-byte load
+  uint4 v;
+  __device__ void load(const unsigned short* p, bool ok) {
+    v = ok ? *reinterpret_cast<const uint4*>(p) : make_uint4(0, 0, 0, 0);
+  }
+  __device__ float operator[](int e) const {
+    const unsigned w = e < 2 ? v.x : e < 4 ? v.y : e < 6 ? v.z : v.w;
+    return __uint_as_float((e & 1) ? (w & 0xffff0000u) : (w << 16));
+  }
+};
+template <>
+struct GemvRow<float> {  // 8 float latitudes in two 16-byte loads
+  float4 a, b;
+  __device__ void load(const float* p, bool ok) {
+    a = ok ? reinterpret_cast<const float4*>(p)[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+    b = ok ? reinterpret_cast<const float4*>(p)[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  __device__ float operator[](int e) const {
+    const float4& q = e < 4 ? a : b;
+    const int i = e & 3;
+    return i == 0 ? q.x : i == 1 ? q.y : i == 2 ? q.z : q.w;
+  }
+};
+
+__host__ __device__ constexpr int gemv_waves() { return 8; }
+size_t gemv_lds_bytes() { return (size_t)gemv_waves() * (16 + 512 * 2) * sizeof(float); }
+
+template <typename T, typename TT>
+__global__ void __launch_bounds__(64 * gemv_waves()) legendre_gemv_kernel(LegArgs<T> A) {
+  constexpr int NW = gemv_waves(), RT = 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* bw_all = reinterpret_cast<float*>(smem_raw);  // [NW][16] b of the wave's current tile
+  float* gs = bw_all + NW * 16;                         // [NW][512][2] partial G
+  const int L = A.L, h = A.h, kpad = A.hpad;
+  const int m = A.morder ? A.morder[blockIdx.x] : (int)blockIdx.x, nr = L - m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int par = wave & 1, npar = (nr + 1 - par) / 2;
+  const TT* tab = static_cast<const TT*>(A.tab) + tri_off(m, L) * kpad;
+  const int j0 = 8 * lane;
+  const bool lok = j0 < kpad;  // kpad is a multiple of 32: whole 8-latitude runs
+  const ItemDev& it = A.items[A.item0];
+  const cpx<T>* sp = A.spec + it.soff + (size_t)m * h * 2 + par;
+  const T* hl = A.hl + (size_t)A.item0 * A.hl_stride + m;
+  float yr[8], yi[8], gr[8], gi[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int j = j0 + e;
+    cpx<T> y{0, 0};
+    if (j < h) y = sp[2 * j];
+    yr[e] = (float)y.x;
+    yi[e] = (float)y.y;
+    gr[e] = gi[e] = 0.f;
+  }
+  float* bw = bw_all + wave * 16;
+  auto load_tile = [&](GemvRow<TT> (&P)[RT], int t) {
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      const int rp = t * RT + rr;
+      P[rr].load(tab + (size_t)(2 * rp + par) * kpad + j0, lok && rp < npar);
+    }
+  };
+  GemvRow<TT> P[RT];
+  for (int t = wave >> 1; t * RT < npar; t += NW / 2) {
+    load_tile(P, t);
+    // lane partials: value k = 2 rr + c
+    float v[16];
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float pv = P[rr][e];
+        sr = fmaf(pv, yr[e], sr);
+        si = fmaf(pv, yi[e], si);
+      }
+      v[2 * rr] = sr;
+      v[2 * rr + 1] = si;
+    }
+    // reduction across the wave, halving the values at each of lane bits 5 .. 2
+    float w[8], x[4], y2[2];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = swap_add32(v[k], v[k + 8]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = swap_add16(w[k], w[k + 4]);
+    const bool b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) y2[k] = (b3 ? x[k + 2] : x[k]) + dpp_f(b3 ? x[k] : x[k + 2], 0);
+    float z = (b2 ? y2[1] : y2[0]) + dpp_f(b2 ? y2[0] : y2[1], 1);
+    z += dpp_f(z, 2);
+    z += dpp_f(z, 3);
+    // b = h_l f for value k = lane / 4 (row 2 (RT t + k / 2) + par of the order)
+    if ((lane & 3) == 0) {
+      const int k = lane >> 2, rp = t * RT + (k >> 1);
+      bw[k] = rp < npar ? z * (float)hl[2 * rp + par] : 0.f;
+    }
+    __builtin_amdgcn_wave_barrier();
+    float b[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 b4 = reinterpret_cast<const float4*>(bw)[q];
+      b[4 * q] = b4.x;
+      b[4 * q + 1] = b4.y;
+      b[4 * q + 2] = b4.z;
+      b[4 * q + 3] = b4.w;
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float pv = P[rr][e];
+        gr[e] = fmaf(pv, b[2 * rr], gr[e]);
+        gi[e] = fmaf(pv, b[2 * rr + 1], gi[e]);
+      }
+  }
+  // partial G of this wave, then the sum over the waves of each parity
+  if (lok) {
+    float4* g4 = reinterpret_cast<float4*>(gs + ((size_t)wave * 512 + j0) * 2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g4[q] = make_float4(gr[2 * q], gi[2 * q], gr[2 * q + 1], gi[2 * q + 1]);
+  }
+  __syncthreads();
+  cpx<T>* out = A.spec + it.soff + (size_t)m * h * 2;
+  for (int idx = tid; idx < 2 * h; idx += 64 * NW) {
+    const int pp = idx >= h ? 1 : 0, j = idx - pp * h;
+    float sr = 0.f, si = 0.f;
+    for (int w2 = pp; w2 < NW; w2 += 2) {
+      const float2 g = reinterpret_cast<const float2*>(gs)[(size_t)w2 * 512 + j];
+      sr += g.x;
+      si += g.y;
+    }
+    out[2 * j + pp] = cpx<T>{(T)sr, (T)si};
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Recurrence-fed matrix-core Legendre kernel (float32 fields, batches).
 //
 // P̄_l^m is generated by the float64 three-term recurrence (as in the VALU
@@ -3254,6 +3408,16 @@ static hipError_t launch_mma_tt(const LegArgs<T>& a, int nt, hipStream_t stream)
 template <typename T>
 hipError_t launch_legendre_mma(const LegArgs<T>& a, int table_kind, int nt, hipStream_t stream) {
   if (a.hpad % 32) return hipErrorInvalidValue;
+  if (a.nb == 1 && a.mode == 0 && a.hpad <= 512) {  // one item: the vector-unit kernel
+    const size_t lds = gemv_lds_bytes();
+    if (table_kind == TAB_BF16)
+      SHOT_LAUNCH((legendre_gemv_kernel<T, unsigned short>), dim3(a.L), dim3(64 * gemv_waves()), lds, stream, a);
+    else if (table_kind == TAB_F32)
+      SHOT_LAUNCH((legendre_gemv_kernel<T, float>), dim3(a.L), dim3(64 * gemv_waves()), lds, stream, a);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (table_kind == TAB_BF16) return launch_mma_tt<T, unsigned short>(a, nt, stream);
   if (table_kind == TAB_F32) return launch_mma_tt<T, float>(a, nt, stream);
   return hipErrorInvalidValue;

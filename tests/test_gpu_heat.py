@@ -128,8 +128,8 @@ def test_multi_grid_items_land_at_their_offsets():
 @pytest.mark.parametrize("prec,legendre,tol", [("fp32", "recurrence", 1e-5), ("fp32", "table", 1e-5),
                                                 ("bf16", "table", 1e-2)])
 def test_heat_apply_climate_grid(prec, legendre, tol):
-    """Full size, one item: the recurrence kernel and (table plans) the matrix-core
-    kernel with a single item's two columns, fp32 and bf16 operands."""
+    """Full size, one item: the recurrence kernel and (table plans) the single-item
+    vector-unit table kernel, fp32 and bf16 tables."""
     grid = ("cc", 721, 1440, 720)
     announce(f"heat_apply full size {grid} {prec} {legendre}")
     P = _plan([grid], prec, legendre)
@@ -143,9 +143,10 @@ def test_heat_apply_climate_grid(prec, legendre, tol):
 @pytest.mark.parametrize("tiles", [0, -1])
 @pytest.mark.parametrize("grid", [("gl", 90, 180, 90), ("cc", 33, 64, 32), ("gl", 17, 36, 18)])
 def test_single_item_bf16_table_heat_apply(grid, tiles):
-    """One item on a bf16 table plan: by default the matrix-core kernel (tiles 0), or the
-    VALU table kernel when matrix cores are switched off (tiles -1); both within the bf16
-    bound of the batched test."""
+    """One item on a bf16 table plan: by default the single-item kernel that reads each
+    table row once for both contractions (tiles 0), or the older VALU table kernel when the
+    matrix-core/single-item kernels are switched off (tiles -1); both within the bf16 bound
+    of the batched test."""
     announce(f"bf16 single item {grid} tiles={tiles}")
     P = _plan([grid], "bf16", "table")
     P.set_tuning(0, 0, tiles)
@@ -156,10 +157,29 @@ def test_single_item_bf16_table_heat_apply(grid, tiles):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+@pytest.mark.parametrize("grid", [("gl", 90, 180, 90), ("cc", 33, 64, 32), ("gl", 17, 36, 18)])
+def test_single_item_table_analysis_and_synthesis(grid, prec, tol):
+    """One item, analysis and synthesis as separate calls on a table plan (the eight-wave
+    matrix-core kernel with its two columns; its synthesis reads the row-major table in
+    32-latitude tiles): packed (m, l) coefficients and the round trip against the oracle."""
+    announce(f"table single item analysis/synthesis {grid} {prec}")
+    P = _plan([grid], prec, "table")
+    g = O.make_grid(*grid)
+    v = synth.temperature_like(np.random.default_rng(11), g.x, g.w, g.nlon, K=6)
+    c = P.analysis(to_dev(v[None], P.dtype)).cpu().numpy().astype(np.complex128)
+    ref = np.concatenate(O.analysis(v, g))
+    err = np.abs(c - ref).max() / np.abs(ref).max()
+    back = to_np(P.synthesis(P.analysis(to_dev(v[None], P.dtype)))).reshape(v.shape)
+    rt = rel_l2(back, O.synthesis(O.analysis(v, g), g))
+    print(f"[single-item table] {grid} {prec} coeff {err:.3e} round trip {rt:.3e}", flush=True)
+    assert err <= 10 * tol
+    assert rt < 10 * tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-2)])
 def test_single_item_table_heat_apply_dealt_orders(prec, tol):
-    """One item on a 360x720 table plan (L = 360 > 256 orders): the matrix-core kernel
-    runs the orders in the host's balanced dealing order (three workgroups per compute
-    unit), every order exactly once."""
+    """One item on a 360x720 table plan (L = 360 > 256 orders): the single-item kernel
+    runs the orders in the host's balanced dealing order, every order exactly once."""
     grid = ("gl", 360, 720, 360)
     announce(f"table single item dealt orders {grid} {prec}")
     P = _plan([grid], prec, "table")
