@@ -49,7 +49,10 @@ def legendre_work(grid, nitems, legendre, precision):
     Entries (l, m, j) of the folded transform: E = L(L+1)/2 * ceil(nlat/2).
     Contraction: 4 flop per entry per pass (complex x real), 2 passes (analysis,
     synthesis), per item.  Recurrence: 3 flop per entry per pass (one multiply,
-    one fused multiply-add).  Table mode moves the table twice per launch.
+    one fused multiply-add).  Table mode: the table read once per launch, the
+    algorithmic minimum (the single-item kernel reads each row once for both
+    passes; the batched matrix-core kernel streams it for each pass, the second
+    mostly from the caches).
     """
     _, nlat, nlon, L = grid
     h = (nlat + 1) // 2
@@ -60,7 +63,7 @@ def legendre_work(grid, nitems, legendre, precision):
     tab_bytes = {"fp32": 4, "bf16": 2, "fp64": 8}[precision]
     field = 8 if precision == "fp64" else 4
     spec_bytes = nitems * 2 * L * h * 2 * field * 2      # folded spectrum in and out
-    bytes_ = spec_bytes + (2 * E * tab_bytes if legendre == "table" else 0)
+    bytes_ = spec_bytes + (E * tab_bytes if legendre == "table" else 0)
     return flops, bytes_
 
 
