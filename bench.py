@@ -452,6 +452,16 @@ def traffic_probe():
     for _ in range(3):
         bp.heat_apply(v, [1e-3] * 48)
     torch.cuda.synchronize()
+    del bp, v
+    # one item on bfloat16 and float32 tables (the single-item table kernel)
+    for prec in ("bf16", "fp32"):
+        tp = Plan([GRID], precision=prec, legendre="table")
+        tp.set_graphs(False)
+        pt, _, _, _ = make_inputs(tp, torch)
+        for _ in range(3):
+            tp.heat_apply(pt[None], [T_HEAT])
+        torch.cuda.synchronize()
+        del tp
     print("traffic probe done", flush=True)
 
 
@@ -575,8 +585,11 @@ def main():
                 "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic}
     else:
         achieved = bytes_ / (avg_leg_ms * 1e-3) / 1e9
+        tt = "unsigned short" if args.precision == "bf16" else "float>"
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(f"legendre_gemv_kernel<float, {tt}")
+                if args.precision in ("bf16", "fp32") else None}
     roof.update({"kernel": "legendre (per-order analysis + h_l + synthesis)",
                  "avg_launch_ms": avg_leg_ms, "launches": launches,
                  "timing": f"HIP events around every launch on its stream during {args.steps} further "
