@@ -157,6 +157,21 @@ def test_single_item_bf16_table_heat_apply(grid, tiles):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+@pytest.mark.parametrize("grid", [("gl", 1024, 64, 32), ("gl", 1026, 64, 32)])
+def test_single_item_table_heat_apply_at_the_latitude_limit(grid, prec, tol):
+    """The single-item table kernel covers up to 512 padded half-latitudes (64 lanes of 8):
+    1024 rows fill every lane; 1026 rows (544 padded) fall back to the matrix-core kernel."""
+    announce(f"table single item latitude limit {grid} {prec}")
+    P = _plan([grid], prec, "table")
+    g = O.make_grid(*grid)
+    v = synth.temperature_like(np.random.default_rng(12), g.x, g.w, g.nlon, K=6)
+    out = to_np(P.heat_apply(to_dev(v[None], P.dtype), [3e-3])).reshape(v.shape)
+    err = rel_l2(out, O.heat_apply(v, g, 3e-3))
+    print(f"[latitude limit] {grid} {prec} rel L2 {err:.3e}", flush=True)
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-2)])
 @pytest.mark.parametrize("grid", [("gl", 90, 180, 90), ("cc", 33, 64, 32), ("gl", 17, 36, 18)])
 def test_single_item_table_analysis_and_synthesis(grid, prec, tol):
     """One item, analysis and synthesis as separate calls on a table plan (the eight-wave
