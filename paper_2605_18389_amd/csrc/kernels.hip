@@ -2398,11 +2398,11 @@ __global__ void __launch_bounds__(64 * NW) legendre_mma_kernel(LegArgs<T> A) {
 //   analysis   f_r = sum_j P_r(x_j) y_j     lane partials over the lane's 8
 //              latitudes, then a reduction across the wave (permlane swaps
 //              for lane bits 5 and 4, DPP for bits 3 .. 0) that leaves row
-//              tile value k = 2 rr + c in lanes 4k .. 4k+3
+//              tile value k = 2 rr + c in the 32 / RT lanes from 32 k / RT
 //   b_r = h_l f_r, passed to the wave's lanes through LDS
 //   synthesis  G_j += P_r(x_j) b_r          the lane's own latitudes
 // One workgroup of NW waves per order m; wave w takes rows of parity w & 1,
-// 8 at a time, lane L latitudes 8L .. 8L+7 (16-byte loads of the row-major
+// RT at a time, lane L latitudes 8L .. 8L+7 (16-byte loads of the row-major
 // table).  Loading the next tile ahead of the current one's use measured
 // slower (a second tile of registers halves the resident waves).
 // The waves' partial G of one parity are added in LDS in wave order.
@@ -2434,12 +2434,17 @@ struct GemvRow<float> {  // 8 float latitudes in two 16-byte loads
   }
 };
 
+// Launch shape: eight waves per order, tiles of four rows.  At 721x1440 (bf16
+// table, one item, interleaved runs) 8 x 4 took 39.8 us per heat apply; 8 x 8
+// 48 us (more registers: one workgroup per compute unit); 4 x 8 43 us; 4 x 4
+// 56 us.
 __host__ __device__ constexpr int gemv_waves() { return 8; }
+__host__ __device__ constexpr int gemv_rows() { return 4; }
 size_t gemv_lds_bytes() { return (size_t)gemv_waves() * (16 + 512 * 2) * sizeof(float); }
 
-template <typename T, typename TT>
-__global__ void __launch_bounds__(64 * gemv_waves()) legendre_gemv_kernel(LegArgs<T> A) {
-  constexpr int NW = gemv_waves(), RT = 8;
+template <typename T, typename TT, int NW, int RT>
+__global__ void __launch_bounds__(64 * NW) legendre_gemv_kernel(LegArgs<T> A) {
+  static_assert(RT == 4 || RT == 8, "tiles of 4 or 8 rows");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* bw_all = reinterpret_cast<float*>(smem_raw);  // [NW][16] b of the wave's current tile
   float* gs = bw_all + NW * 16;                         // [NW][512][2] partial G
@@ -2475,7 +2480,7 @@ __global__ void __launch_bounds__(64 * gemv_waves()) legendre_gemv_kernel(LegArg
   for (int t = wave >> 1; t * RT < npar; t += NW / 2) {
     load_tile(P, t);
     // lane partials: value k = 2 rr + c
-    float v[16];
+    float v[2 * RT];
 #pragma unroll
     for (int rr = 0; rr < RT; ++rr) {
       float sr = 0.f, si = 0.f;
@@ -2488,27 +2493,34 @@ __global__ void __launch_bounds__(64 * gemv_waves()) legendre_gemv_kernel(LegArg
       v[2 * rr] = sr;
       v[2 * rr + 1] = si;
     }
-    // reduction across the wave, halving the values at each of lane bits 5 .. 2
-    float w[8], x[4], y2[2];
+    // reduction across the wave, halving the values at each lane bit from 5
+    // down until one value is left per lane, then summing over the rest
+    float w[RT], x[RT / 2], y2[RT / 4];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) w[k] = swap_add32(v[k], v[k + 8]);
+    for (int k = 0; k < RT; ++k) w[k] = swap_add32(v[k], v[k + RT]);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = swap_add16(w[k], w[k + 4]);
+    for (int k = 0; k < RT / 2; ++k) x[k] = swap_add16(w[k], w[k + RT / 2]);
     const bool b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) y2[k] = (b3 ? x[k + 2] : x[k]) + dpp_f(b3 ? x[k] : x[k + 2], 0);
-    float z = (b2 ? y2[1] : y2[0]) + dpp_f(b2 ? y2[0] : y2[1], 1);
+    for (int k = 0; k < RT / 4; ++k) y2[k] = (b3 ? x[k + RT / 4] : x[k]) + dpp_f(b3 ? x[k] : x[k + RT / 4], 0);
+    float z;
+    if constexpr (RT == 8) {
+      z = (b2 ? y2[1] : y2[0]) + dpp_f(b2 ? y2[0] : y2[1], 1);
+    } else {
+      z = y2[0] + dpp_f(y2[0], 1);
+    }
     z += dpp_f(z, 2);
     z += dpp_f(z, 3);
-    // b = h_l f for value k = lane / 4 (row 2 (RT t + k / 2) + par of the order)
-    if ((lane & 3) == 0) {
-      const int k = lane >> 2, rp = t * RT + (k >> 1);
+    // b = h_l f for value k = lane / (32 / RT) (row 2 (RT t + k / 2) + par of the order)
+    constexpr int SHV = RT == 8 ? 2 : 3;
+    if ((lane & ((1 << SHV) - 1)) == 0) {
+      const int k = lane >> SHV, rp = t * RT + (k >> 1);
       bw[k] = rp < npar ? z * (float)hl[2 * rp + par] : 0.f;
     }
     __builtin_amdgcn_wave_barrier();
-    float b[16];
+    float b[2 * RT];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < RT / 2; ++q) {
       const float4 b4 = reinterpret_cast<const float4*>(bw)[q];
       b[4 * q] = b4.x;
       b[4 * q + 1] = b4.y;
@@ -3411,9 +3423,11 @@ hipError_t launch_legendre_mma(const LegArgs<T>& a, int table_kind, int nt, hipS
   if (a.nb == 1 && a.mode == 0 && a.hpad <= 512) {  // one item: the vector-unit kernel
     const size_t lds = gemv_lds_bytes();
     if (table_kind == TAB_BF16)
-      SHOT_LAUNCH((legendre_gemv_kernel<T, unsigned short>), dim3(a.L), dim3(64 * gemv_waves()), lds, stream, a);
+      SHOT_LAUNCH((legendre_gemv_kernel<T, unsigned short, gemv_waves(), gemv_rows()>), dim3(a.L),
+                  dim3(64 * gemv_waves()), lds, stream, a);
     else if (table_kind == TAB_F32)
-      SHOT_LAUNCH((legendre_gemv_kernel<T, float>), dim3(a.L), dim3(64 * gemv_waves()), lds, stream, a);
+      SHOT_LAUNCH((legendre_gemv_kernel<T, float, gemv_waves(), gemv_rows()>), dim3(a.L), dim3(64 * gemv_waves()),
+                  lds, stream, a);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
