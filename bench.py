@@ -585,7 +585,7 @@ def main():
                 "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic}
     else:
         achieved = bytes_ / (avg_leg_ms * 1e-3) / 1e9
-        tt = "unsigned short" if args.precision == "bf16" else "float>"
+        tt = "unsigned short," if args.precision == "bf16" else "float,"
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(f"legendre_gemv_kernel<float, {tt}")
