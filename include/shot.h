@@ -15,13 +15,15 @@
  * Grids.  Iso-latitude grids of nlat rows x nlon columns.  Row 0 is the
  *   northernmost row (colatitude closest to 0), column k sits at longitude
  *   2*pi*k/nlon.  The band limit L keeps degrees and orders l, m < L and needs
- *   nlon >= 2L-1.  nlon must be at most 2048 (any factorisation: prime factors
+ *   nlon >= 2L-1; nlat and nlon are at least 2 (SHOT_E_INVALID otherwise).
+ *   nlon must be at most 2048 (any factorisation: prime factors
  *   above 5 run as direct stages, slower than radices 2 to 5), and
  *   (2*ceil(nlat/2) + L) complex values of the field precision must fit in
  *   60 KiB (SHOT_E_UNSUPPORTED otherwise).  Area weights a_{jk} = w_j * 2*pi/nlon
  *   sum to 4*pi.
  * Items.  A call processes nitems independent items; item i lives on grid
- *   grid_of_item[i] (an index into the plan's grids).  Field arrays hold the
+ *   grid_of_item[i] (an index into the plan's grids).  nitems (npairs) must be
+ *   at least 1: an empty batch returns SHOT_E_INVALID before any launch.  Field arrays hold the
  *   items back to back, item i starting at element sum_{i'<i} nlat*nlon of
  *   grid_of_item[i'], each item row-major [nlat][nlon].
  * Precision.  SHOT_FP64 plans take and return double fields and compute in

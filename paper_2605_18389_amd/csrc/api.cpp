@@ -1909,7 +1909,7 @@ shot_status shot_sht_plan(shot_plan_t* out, const shot_grid_desc* grids, int32_t
       if (d.L < 1 || d.nlon < 4 || d.nlon % 4 != 0 || d.nlat != d.nlon - 1) return SHOT_E_INVALID;
       if (d.nlon > 2048) return SHOT_E_UNSUPPORTED;
     } else {
-      if (d.nlat < 2 || d.L < 1 || d.nlon < 2 * d.L - 1) return SHOT_E_INVALID;
+      if (d.nlat < 2 || d.nlon < 2 || d.L < 1 || d.nlon < 2 * d.L - 1) return SHOT_E_INVALID;
       // any row length: radices 4, 2, 3, 5 and a direct stage per larger prime
       if (d.nlon > 2048 || fft_factors(d.nlon).size() > 8) return SHOT_E_UNSUPPORTED;
     }

@@ -60,6 +60,10 @@ def test_argument_errors_need_no_gpu(lib_path):
     bad = (binding.GridDesc * 1)(binding.GridDesc(0, 32, 4096, 32))  # nlon > 2048
     assert lib.shot_sht_plan(ctypes.byref(h), bad, 1, 1, 0, None) == binding.E_UNSUPPORTED
     assert lib.shot_sht_plan(ctypes.byref(h), bad, 0, 1, 0, None) == binding.E_INVALID
+    # degenerate grids: one row, one column
+    for desc in ((0, 1, 4, 1), (0, 2, 1, 1), (1, 1, 4, 1)):
+        bad = (binding.GridDesc * 1)(binding.GridDesc(*desc))
+        assert lib.shot_sht_plan(ctypes.byref(h), bad, 1, 1, 0, None) == binding.E_INVALID
     assert lib.shot_plan_destroy(None) == 0
 
 

@@ -1,0 +1,116 @@
+"""Edge cases of the heat apply (Sec. 3.2) on the GPU, against the FP64 oracle.
+
+* An empty batch is rejected before any launch (SHOT_E_INVALID), through the C ABI
+  and through the binding.
+* Heat time t = 0: h_l = 1 for every kept degree, so HeatConv is analysis then
+  synthesis (App. C.1).  Where the quadrature integrates products of degree up to
+  2L - 2 exactly (Gauss-Legendre rows with nlat >= L) that is the projection onto
+  degrees l < L, and a band-limited field comes back unchanged; every grid is also
+  compared with the oracle's t = 0 apply.
+* A long heat time leaves only the l = 0 term: the constant field equal to the
+  area-weighted mean (the Y_00 coefficient times Y_00).
+* The smallest grids a plan accepts (two rows and two columns; a plan refuses one
+  row or one column): two rows and no equator row; three rows with one.
+
+Tolerances: float64 plans 1e-12 relative L2, float32 plans 1e-5 (the heat-apply bound).
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_18389_amd import synth
+
+from helpers import announce, ensure_built, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+FORMS = [("fp64", "recurrence"), ("fp32", "recurrence"), ("fp32", "table")]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    ensure_built()
+
+
+def _plan(grid, precision, legendre):
+    from paper_2605_18389_amd import Plan
+    return Plan([grid], precision=precision, legendre=legendre)
+
+
+def test_empty_batch_is_rejected():
+    import torch
+    from paper_2605_18389_amd import binding
+    announce("empty batch")
+    P = _plan(("gl", 17, 36, 18), "fp32", "recurrence")
+    lib = P.lib
+    v = torch.zeros(17 * 36, dtype=torch.float32, device="cuda")
+    out = torch.zeros_like(v)
+    goi = (ctypes.c_int32 * 1)(0)
+    t = (ctypes.c_double * 1)(1e-3)
+    st = lib.shot_heat_apply(P.handle, goi, 0, t, ctypes.c_void_p(v.data_ptr()),
+                             ctypes.c_void_p(out.data_ptr()), 0, None)
+    assert st == binding.E_INVALID
+    st = lib.shot_sht_analysis(P.handle, goi, 0, ctypes.c_void_p(v.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), None)
+    assert st == binding.E_INVALID
+    with pytest.raises(binding.ShotError):
+        P.heat_apply(torch.zeros(0, dtype=torch.float32, device="cuda"), [])
+    with pytest.raises(binding.ShotError):
+        P.divergence(torch.zeros(0, dtype=torch.float32, device="cuda"),
+                     torch.zeros(0, dtype=torch.float32, device="cuda"), 0.1, T=2)
+    # the plan still works afterwards
+    g = O.make_grid("gl", 17, 36, 18)
+    f = synth.temperature_like(np.random.default_rng(20), g.x, g.w, g.nlon, K=4)
+    got = to_np(P.heat_apply(to_dev(f[None], P.dtype), [1e-3])).reshape(f.shape)
+    assert rel_l2(got, O.heat_apply(f, g, 1e-3)) < TOL["fp32"]
+
+
+@pytest.mark.parametrize("prec,legendre", FORMS)
+@pytest.mark.parametrize("grid", [("gl", 32, 64, 32), ("cc", 33, 64, 32), ("gl", 17, 36, 18)])
+def test_heat_time_zero_is_the_band_projection(grid, prec, legendre):
+    announce(f"t = 0 {grid} {prec} {legendre}")
+    P = _plan(grid, prec, legendre)
+    g = O.make_grid(*grid)
+    v = np.random.default_rng(21).random((g.nlat, g.nlon)) + 0.5
+    f = O.synthesis(O.analysis(v, g), g)          # band-limited to l < L
+    out = to_np(P.heat_apply(to_dev(np.stack([v, f]), P.dtype), [0.0, 0.0])).reshape(2, *v.shape)
+    e_proj = rel_l2(out[0], O.heat_apply(v, g, 0.0))
+    e_fix = rel_l2(out[1], f)
+    print(f"[t=0] {grid} {prec} {legendre} projection {e_proj:.2e}, band-limited fixed point {e_fix:.2e}",
+          flush=True)
+    assert e_proj < TOL[prec]
+    if grid[0] == "gl" and grid[1] >= grid[3]:   # exact quadrature: a projection
+        assert e_fix < TOL[prec]
+
+
+@pytest.mark.parametrize("prec,legendre", FORMS)
+@pytest.mark.parametrize("grid", [("gl", 32, 64, 32), ("cc", 33, 64, 32)])
+def test_long_heat_time_leaves_the_area_weighted_mean(grid, prec, legendre):
+    announce(f"t = 50 {grid} {prec} {legendre}")
+    P = _plan(grid, prec, legendre)
+    g = O.make_grid(*grid)
+    v = np.random.default_rng(22).random((g.nlat, g.nlon)) + 0.5
+    a = np.repeat(np.asarray(g.w)[:, None], g.nlon, axis=1) * 2 * np.pi / g.nlon
+    mean = (a * v).sum() / (4 * np.pi)
+    out = to_np(P.heat_apply(to_dev(v[None], P.dtype), [50.0])).reshape(v.shape)
+    err = np.abs(out - mean).max() / mean
+    print(f"[t=50] {grid} {prec} {legendre} max |K v - mean| / mean {err:.2e}", flush=True)
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec,legendre", FORMS)
+@pytest.mark.parametrize("grid", [("gl", 2, 2, 1), ("gl", 2, 3, 2), ("cc", 3, 4, 2), ("gl", 3, 5, 3)])
+def test_smallest_grids(grid, prec, legendre):
+    announce(f"smallest grid {grid} {prec} {legendre}")
+    P = _plan(grid, prec, legendre)
+    g = O.make_grid(*grid)
+    v = np.random.default_rng(23).random((3, g.nlat, g.nlon)) + 0.5
+    t = [1e-2, 0.3, 0.0]
+    out = to_np(P.heat_apply(to_dev(v, P.dtype), t)).reshape(v.shape)
+    errs = [rel_l2(out[i], O.heat_apply(v[i], g, t[i])) for i in range(3)]
+    print(f"[smallest] {grid} {prec} {legendre} rel L2 {max(errs):.2e}", flush=True)
+    assert max(errs) < TOL[prec]
