@@ -16,6 +16,7 @@ Tolerances: float64 plans 1e-12 relative L2, float32 plans 1e-5 (the heat-apply 
 """
 
 import ctypes
+import math
 
 import numpy as np
 import pytest
@@ -24,6 +25,7 @@ import oracle as O
 from paper_2605_18389_amd import synth
 
 from helpers import announce, ensure_built, rel_l2, to_dev, to_np
+from parity import check_status, tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -114,3 +116,57 @@ def test_smallest_grids(grid, prec, legendre):
     errs = [rel_l2(out[i], O.heat_apply(v[i], g, t[i])) for i in range(3)]
     print(f"[smallest] {grid} {prec} {legendre} rel L2 {max(errs):.2e}", flush=True)
     assert max(errs) < TOL[prec]
+
+
+def test_invalid_parameters_are_rejected():
+    """Non-positive eps or tau, fewer than one iteration or check interval, a negative
+    tolerance, and negative or non-finite heat times return SHOT_E_INVALID; the plan is
+    still usable afterwards."""
+    import math
+    import torch
+    from paper_2605_18389_amd import binding
+    announce("invalid parameters")
+    grid = ("gl", 17, 36, 18)
+    P = _plan(grid, "fp64", "recurrence")
+    g = O.make_grid(*grid)
+    p, q = synth.vmf_pair(synth.pair_seed(0, 5), g.x, g.w, g.nlon, K=3)
+    pd, qd = to_dev(p, P.dtype), to_dev(q, P.dtype)
+    for kw in (dict(eps=0.0), dict(eps=-0.1), dict(eps=math.inf), dict(eps=0.1, tau=0.0),
+               dict(eps=0.1, T=0), dict(eps=0.1, C=0), dict(eps=0.1, tol=-1.0)):
+        with pytest.raises(binding.ShotError) as e:
+            P.sinkhorn(pd, qd, **kw)
+        assert e.value.code == binding.E_INVALID, kw
+    for t in (-1e-3, math.nan, math.inf):
+        with pytest.raises(binding.ShotError) as e:
+            P.heat_apply(pd, [t])
+        assert e.value.code == binding.E_INVALID, t
+    got = to_np(P.heat_apply(pd, [1e-2])).reshape(p.shape)
+    assert rel_l2(got, O.heat_apply(p, g, 1e-2)) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("T", [1, 2])
+@pytest.mark.parametrize("tau", [math.inf, 1.0])
+def test_fewest_iterations_match_the_oracle(T, tau):
+    """Alg. 1 stopped after one or two iterations (checked every iteration), balanced and
+    unbalanced, float64 on a 32x64 vMF pair: status, cost, potentials and e_marg against
+    the oracle's, graded by the rule of tests/parity.py."""
+    announce(f"T={T} tau={tau}")
+    grid = ("gl", 32, 64, 32)
+    P = _plan(grid, "fp64", "recurrence")
+    g = O.make_grid(*grid)
+    p, q = synth.vmf_pair(synth.pair_seed(0, 6), g.x, g.w, g.nlon, K=4)
+    eps = 0.16
+    phi, psi, inf = P.sinkhorn(to_dev(p, P.dtype), to_dev(q, P.dtype), eps, tau=tau, T=T, C=1)
+    r = O.sinkhorn(p, q, g, eps, tau, T, C=1)
+    e_cost = abs(inf[0]["cost"] - r["cost"]) / abs(r["cost"])
+    e_phi = rel_l2(to_np(phi).reshape(p.shape), r["phi"])
+    e_psi = rel_l2(to_np(psi).reshape(p.shape), r["psi"])
+    print(f"[fewest] T={T} tau={tau} iters {inf[0]['iters']} cost {e_cost:.2e} phi {e_phi:.2e} "
+          f"psi {e_psi:.2e} err {inf[0]['err']:.3e} / {r['err']:.3e}", flush=True)
+    assert inf[0]["iters"] == T and inf[0]["status"] == 0 and r["breakdown"] == 0
+    assert check_status(inf[0], r, "fp64")
+    tol = tolerance(r, "fp64")
+    print(f"[fewest] bound {tol:.1e} (cost), {10 * tol:.1e} (potentials)", flush=True)
+    assert e_cost <= tol
+    assert e_phi < 10 * tol and e_psi < 10 * tol
+    assert abs(inf[0]["err"] - r["err"]) <= 1e-3 * r["err"] + 10 * tol
