@@ -2723,8 +2723,8 @@ __host__ __device__ inline RmLayout rm_layout(int L, int h, int nt, int nw, int 
   q.bplane = (size_t)2 * q.ncol * q.bld;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 15) / 16 * 16; return o; };
-  // the recurrence tiles' region also stages the chunk's folded spectra in and
-  // out: 8 nt items x h latitudes x (E, O) complex
+  // the recurrence tiles' region also stages the chunk's folded spectra in:
+  // 8 nt items x h latitudes x (E, O) complex
   const size_t tiles = q.pplane * planes * es, spectra = (size_t)8 * nt * h * 4 * sizeof(float);
   q.o_p = take(tiles > spectra ? tiles : spectra);
   q.o_d = take(sizeof(float) * nw * 2 * q.ncol * 20);
@@ -3006,28 +3006,28 @@ legendre_rmma_kernel(LegArgs<T> A) {
     }
   }
   // ---- the order's folded spectrum: G[j][n] (j = 64 wave + 16 jt + 4 lg + e)
-  // gathered in the staging region, then copied out with coalesced stores
-  // (the tiles that region also holds are not read after the last block's
-  // second barrier)
+  // stored straight from the accumulators: the two lanes of an item (its real
+  // and imaginary column) trade halves so that each writes whole (E, O)
+  // complex pairs, 16 bytes per latitude (gathering through LDS first, for
+  // fully contiguous stores, measured 3 % slower)
+  float4* dsc = reinterpret_cast<float4*>(A.spec + A.soff0) + (size_t)(c0 / 2) * L * h + (size_t)m * h;
+  const bool odd = li & 1;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int il = 8 * t + (li >> 1);
 #pragma unroll
     for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int jj = 64 * wave + 16 * jt + 4 * lg + e;
-        if (il < nit && jj < h) {
-          ysl[((size_t)il * h + jj) * 4 + 0 + (li & 1)] = G[0][jt][t][e];
-          ysl[((size_t)il * h + jj) * 4 + 2 + (li & 1)] = G[1][jt][t][e];
-        }
+      for (int ep = 0; ep < 2; ++ep) {
+        // the even lane writes latitude e = 2 ep, the odd lane e = 2 ep + 1
+        const int ea = 2 * ep, eb = 2 * ep + 1;
+        const float r0 = dpp_f(odd ? G[0][jt][t][ea] : G[0][jt][t][eb], 3);
+        const float r1 = dpp_f(odd ? G[1][jt][t][ea] : G[1][jt][t][eb], 3);
+        const float4 o = odd ? make_float4(r0, G[0][jt][t][eb], r1, G[1][jt][t][eb])
+                             : make_float4(G[0][jt][t][ea], r0, G[1][jt][t][ea], r1);
+        const int jj = 64 * wave + 16 * jt + 4 * lg + (odd ? eb : ea);
+        if (il < nit && jj < h) dsc[(size_t)il * L * h + jj] = o;
       }
-  }
-  __syncthreads();
-  float4* dsc = reinterpret_cast<float4*>(A.spec + A.soff0) + (size_t)(c0 / 2) * L * h + (size_t)m * h;
-  for (int idx = tid; idx < nit * h; idx += blockDim.x) {
-    const int i = idx / h, jj = idx - i * h;
-    dsc[(size_t)i * L * h + jj] = reinterpret_cast<const float4*>(ysl)[idx];
   }
 }
 
