@@ -2723,10 +2723,7 @@ __host__ __device__ inline RmLayout rm_layout(int L, int h, int nt, int nw, int 
   q.bplane = (size_t)2 * q.ncol * q.bld;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 15) / 16 * 16; return o; };
-  // the recurrence tiles' region also stages the chunk's folded spectra in:
-  // 8 nt items x h latitudes x (E, O) complex
-  const size_t tiles = q.pplane * planes * es, spectra = (size_t)8 * nt * h * 4 * sizeof(float);
-  q.o_p = take(tiles > spectra ? tiles : spectra);
+  q.o_p = take(q.pplane * planes * es);
   q.o_d = take(sizeof(float) * nw * 2 * q.ncol * 20);
   q.o_b = take(q.bplane * planes * es);
   q.o_c = take(sizeof(double) * (32 * q.nb + 1));
@@ -2764,7 +2761,6 @@ legendre_rmma_kernel(LegArgs<T> A) {
   float* Dp = reinterpret_cast<float*>(smem_raw + Q.o_d);
   unsigned char* Bs = smem_raw + Q.o_b;
   double* cf = reinterpret_cast<double*>(smem_raw + Q.o_c);
-  float* ysl = reinterpret_cast<float*>(smem_raw + Q.o_p);   // [item][j][E re, E im, O re, O im]
   const long long toff = tri_off(m, L);
   const int nit = min(8 * NT, A.nb - c0 / 2);                 // items of this chunk
   const int ncomb = 2 * 16 * Q.ncol;                           // combine elements per block
@@ -2776,29 +2772,35 @@ legendre_rmma_kernel(LegArgs<T> A) {
   const double xj = A.xs[min(j, h - 1)];
   const double sd = A.rseed[(size_t)m * h + min(j, h - 1)];
 
-  // Staging: the chunk's folded spectra (h x (E, O) complex per item, coalesced
-  // 16-byte loads), the order's recurrence coefficients (zero past its end),
-  // gamma^2 per row and the items' heat multipliers; every load of a thread is
-  // issued before the first is used (one memory round trip)
-  {
-    constexpr int SB = 8;
-    float4 v4[SB];
-    const int ns = nit * h;
+  // This wave's latitudes of the items' folded spectra, the analysis B
+  // operands, loaded straight into registers (k = latitude 64 wave + KS s + the
+  // lane group's k-run).  Each lane needs one component of an item's (E, O)
+  // pair per latitude; the two lanes of an item (real / imaginary column)
+  // each load whole 16-byte pairs of alternate latitudes and trade halves by
+  // DPP.  The loads are issued first, then the order's recurrence
+  // coefficients (zero past its end) are staged for the whole workgroup.
+  constexpr int NE = KS == 4 ? 1 : 4;         // latitudes per k step and lane
+  constexpr int NG = NKS * NE / 2;            // latitude pairs per lane and item
+  const bool odd = li & 1;
+  // latitude of pair g for the even (q = 0) or odd (q = 1) lane
+  auto pair_lat = [&](int g, int q) {
+    const int s = KS == 4 ? 2 * g + q : g >> 1, e = KS == 4 ? 0 : 2 * (g & 1) + q;
+    return 64 * wave + KS * s + (KS == 4 ? lg : 4 * lg + e);
+  };
+  float4 fl[NT][NG];
 #pragma unroll
-    for (int u = 0; u < SB; ++u) {
-      const int idx = min(tid + u * (int)blockDim.x, ns - 1), i = idx / h, jj = idx - i * h;
-      v4[u] = spc[(size_t)i * L * h + jj];
+  for (int t = 0; t < NT; ++t) {
+    const int il = 8 * t + (li >> 1);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int jj = pair_lat(g, odd ? 1 : 0);
+      fl[t][g] = il < nit && jj < h ? spc[(size_t)il * L * h + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+  }
+  {
     double cv[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) cv[u] = A.rcoef[toff + min(tid + u * (int)blockDim.x, nr - 1)];
-#pragma unroll
-    for (int u = 0; u < SB; ++u)
-      if (tid + u * (int)blockDim.x < ns) reinterpret_cast<float4*>(ysl)[tid + u * blockDim.x] = v4[u];
-    for (int idx = tid + SB * blockDim.x; idx < ns; idx += blockDim.x) {  // larger chunks than one round
-      const int i = idx / h, jj = idx - i * h;
-      reinterpret_cast<float4*>(ysl)[idx] = spc[(size_t)i * L * h + jj];
-    }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int r = tid + u * (int)blockDim.x;
@@ -2808,27 +2810,31 @@ legendre_rmma_kernel(LegArgs<T> A) {
       cf[r] = (r < nr && r > 0) ? A.rcoef[toff + min(r, nr - 1)] : 0.0;
   }
   const double seed = j < h ? sd : 0.0;   // lanes past the last latitude run a zero chain
-  __syncthreads();
-  // this wave's latitudes of the items' folded spectra: analysis B operands,
-  // kept in registers (k = latitude 64 wave + KS s + the lane group's k-run)
   Op yb[NKS][2][NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int il = 8 * t + (li >> 1);
+    float xv[NKS][2][NE];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const float4 F = fl[t][g];
+      // the even lane sends (E im, O im) of its latitude, the odd lane (E re,
+      // O re) of its own; each keeps its component of both latitudes
+      const float r0 = dpp_f(odd ? F.x : F.y, 3), r1 = dpp_f(odd ? F.z : F.w, 3);
+      const float a0 = odd ? r0 : F.x, a1 = odd ? r1 : F.z;   // the even lane's latitude
+      const float b0 = odd ? F.y : r0, b1 = odd ? F.w : r1;   // the odd lane's latitude
+      const int sa = KS == 4 ? 2 * g : g >> 1, ea = KS == 4 ? 0 : 2 * (g & 1);
+      const int sb = KS == 4 ? 2 * g + 1 : g >> 1, eb = KS == 4 ? 0 : 2 * (g & 1) + 1;
+      xv[sa][0][ea] = a0;
+      xv[sa][1][ea] = a1;
+      xv[sb][0][eb] = b0;
+      xv[sb][1][eb] = b1;
+    }
 #pragma unroll
     for (int s = 0; s < NKS; ++s)
 #pragma unroll
-      for (int par = 0; par < 2; ++par) {
-        float x[KS == 4 ? 1 : 4];
-#pragma unroll
-        for (int e = 0; e < (KS == 4 ? 1 : 4); ++e) {
-          const int jj = 64 * wave + KS * s + (KS == 4 ? lg : 4 * lg + e);
-          x[e] = (il < nit && jj < h) ? ysl[((size_t)il * h + jj) * 4 + 2 * par + (li & 1)] : 0.f;
-        }
-        yb[s][par][t] = TR::make(x);
-      }
+      for (int par = 0; par < 2; ++par) yb[s][par][t] = TR::make(xv[s][par]);
   }
-  __syncthreads();  // the staged spectra share LDS with the recurrence tiles
+  __syncthreads();  // the coefficients are staged
 
   // ---- one pass over the order's rows, 32 at a time: the block's analysis
   // f = sum_j P y (partials of the waves combined in LDS), b = gamma^2 h_l f,
@@ -3011,7 +3017,6 @@ legendre_rmma_kernel(LegArgs<T> A) {
   // complex pairs, 16 bytes per latitude (gathering through LDS first, for
   // fully contiguous stores, measured 3 % slower)
   float4* dsc = reinterpret_cast<float4*>(A.spec + A.soff0) + (size_t)(c0 / 2) * L * h + (size_t)m * h;
-  const bool odd = li & 1;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int il = 8 * t + (li >> 1);
