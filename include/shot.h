@@ -192,6 +192,12 @@ shot_status shot_heat_apply_noalloc(shot_plan_t plan, const int32_t* grid_of_ite
 
 /* Alg. 1 on nitems independent items.  params: host, one per item.  p, q:
  * device marginals (densities with respect to the area weights, positive).
+ * An item whose marginals do not both have positive, finite area-weighted mass
+ * m = sum a p gets status SHOT_E_INVALID (found from the masses the solve
+ * computes, so after its launches; shot_last_error() names the item), and the
+ * call then returns SHOT_E_INVALID; this applies to the divergence and
+ * gradient entry points as well.  Otherwise the call returns the largest
+ * per-item status.
  * phi, psi: device outputs, eps*log(u) and eps*log(v) (either may be NULL).
  * info: host, nitems reports.  Synchronises `stream`. */
 shot_status shot_sinkhorn_solve(shot_plan_t plan, const int32_t* grid_of_item, int32_t nitems,

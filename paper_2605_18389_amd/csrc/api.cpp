@@ -1188,16 +1188,32 @@ shot_status finish_solve(shot_plan_s* P, const Layout& Lo, Work<T>& W, int nitem
       mass_out[2 * ui + 1] = res[(size_t)si * 8 + 3];
     }
     I.reserved = 0;
-    if (I.breakdown_iter) I.status = SHOT_E_BREAKDOWN;
-    else if (tol > 0 && !(I.err < tol)) I.status = SHOT_W_NOT_CONVERGED;
-    else I.status = SHOT_OK;
+    // marginals must carry positive, finite area-weighted mass (Alg. 1 takes
+    // measures); the masses come from the solve's own prologue reduction
+    const double mp = res[(size_t)si * 8 + 2], mq = res[(size_t)si * 8 + 3];
+    if (!(mp > 0) || !(mq > 0) || !std::isfinite(mp) || !std::isfinite(mq)) {
+      I.status = SHOT_E_INVALID;
+      snprintf(g_last_error, sizeof(g_last_error),
+               "item %d: marginal masses m(p) = %g, m(q) = %g must be positive and finite", ui, mp, mq);
+    } else if (I.breakdown_iter) {
+      I.status = SHOT_E_BREAKDOWN;
+    } else if (tol > 0 && !(I.err < tol)) {
+      I.status = SHOT_W_NOT_CONVERGED;
+    } else {
+      I.status = SHOT_OK;
+    }
   }
   return SHOT_OK;
 }
 
+// The call's status: an invalid item (an argument error) first, else the
+// largest per-item code (breakdown above not-converged above ok).
 shot_status worst(const shot_solve_info* info, int n) {
   int w = SHOT_OK;
-  for (int i = 0; i < n; ++i) w = std::max(w, info[i].status);
+  for (int i = 0; i < n; ++i) {
+    if (info[i].status == SHOT_E_INVALID) return SHOT_E_INVALID;
+    w = std::max(w, info[i].status);
+  }
   return (shot_status)w;
 }
 

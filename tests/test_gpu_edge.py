@@ -170,3 +170,32 @@ def test_fewest_iterations_match_the_oracle(T, tau):
     assert e_cost <= tol
     assert e_phi < 10 * tol and e_psi < 10 * tol
     assert abs(inf[0]["err"] - r["err"]) <= 1e-3 * r["err"] + 10 * tol
+
+
+@pytest.mark.parametrize("bad", ["zero", "negative", "nan"])
+def test_marginal_without_positive_mass_is_rejected(bad):
+    """A marginal whose area-weighted mass is not positive and finite makes the solve,
+    divergence and gradient calls return SHOT_E_INVALID, with the item named in
+    shot_last_error(); a valid batch on the same plan still solves afterwards."""
+    from paper_2605_18389_amd import binding
+    announce(f"marginal mass {bad}")
+    grid = ("gl", 17, 36, 18)
+    P = _plan(grid, "fp32", "recurrence")
+    g = O.make_grid(*grid)
+    p, q = synth.vmf_pair(synth.pair_seed(0, 7), g.x, g.w, g.nlon, K=3)
+    pb = {"zero": np.zeros_like(p), "negative": -p, "nan": np.where(np.arange(p.size).reshape(p.shape) == 5, np.nan, p)}[bad]
+    pd, qd, pbd = to_dev(p, P.dtype), to_dev(q, P.dtype), to_dev(np.stack([p, pb]), P.dtype)
+    qq = to_dev(np.stack([q, q]), P.dtype)
+    with pytest.raises(binding.ShotError) as e:
+        P.sinkhorn(pbd, qq, 0.1, T=5)
+    assert e.value.code == binding.E_INVALID
+    assert b"item 1" in P.lib.shot_last_error()
+    with pytest.raises(binding.ShotError) as e:
+        P.divergence(pbd, qq, 0.1, T=5)
+    assert e.value.code == binding.E_INVALID
+    with pytest.raises(binding.ShotError) as e:
+        P.divergence_grad(pbd, qq, 0.1, T=5)
+    assert e.value.code == binding.E_INVALID
+    # eps = 1 stays clear of breakdown here (oracle kernel ratio 4e-3)
+    _, _, inf = P.sinkhorn(pd, qd, 1.0, T=5)
+    assert inf[0]["status"] == 0
