@@ -661,6 +661,7 @@ RowArgs<T> row_args(const shot_plan_s* P, const GridRec& g, const Layout& Lo, co
                     int nitems, int leg_mode = 0) {
   RowArgs<T> a;
   std::memset(&a, 0, sizeof(a));
+  a.store_field = 1;
   int cib = 1;
   if (leg_split(P, g, G.count, leg_mode, &cib) == &g.ss) {  // spectra arrive with long orders in parts
     a.cut = g.d_cut;
@@ -993,6 +994,11 @@ shot_status solve_impl(shot_plan_s* P, const SolveSpec& S, T* phi, T* psi, shot_
     a.chk_slot = chk;
     a.out = phi;
     a.out2 = psi;
+    // u_k is read again only by the next half-iteration's check (k a check
+    // iteration), by the closing residual and by the potentials (k = T, or a
+    // check iteration where an early stop may land); v_k only by the
+    // potentials
+    if (mode == ROW_SINK_U || mode == ROW_SINK_V) a.store_field = (k % C == 0 || k == T_iter) ? 1 : 0;
     return run_rows<T>(P, a, G.count, ls);
   };
   auto leg = [&](const Group& G, const GridRec& g) { return run_leg<T>(P, g, leg_args<T>(g, G, W, Lo.Lmax, Lo), ls); };

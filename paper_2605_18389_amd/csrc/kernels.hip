@@ -933,7 +933,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
         T u = pv / kv;
         double gt = 0.0;
         if (!I.balanced) u = unbalanced_update(u, I.lam, I.eot, gt);
-        un[fi] = u;
+        if (A.store_field) un[fi] = u;
         nv[rr] = u;
         acc0 += I.balanced ? (double)u : (double)aj * (double)pv * gt;
       }
@@ -958,7 +958,7 @@ __global__ void __launch_bounds__(BS) row_kernel(RowArgs<T> A) {
           v = unbalanced_update(v, I.lam, I.eot, gt);
           acc1 += (double)aj * (double)qv * gt;
         }
-        vn[fidx - I.foff] = v;
+        if (A.store_field) vn[fidx - I.foff] = v;
         nv[rr] = v;
       }
       X[pr * N + c] = {nv[0], eq ? (T)0 : nv[1]};
@@ -1386,7 +1386,7 @@ __global__ void __launch_bounds__(BS) row_sink_kernel(RowArgs<T> A) {
       }
       nv[rr] = x;
       const int jr = rr ? nlat - 1 - jp : jp;
-      __builtin_nontemporal_store(x, outf + (long long)jr * N + c);
+      if (A.store_field) __builtin_nontemporal_store(x, outf + (long long)jr * N + c);
     }
     X[pr * N + c] = {nv[0], nv[1]};
   }

@@ -97,6 +97,10 @@ struct RowArgs {
   double* rhist;      // [nitems][nslot][h] e_marg residual partials
   int nslot;
   int chk_slot;       // slot written by this launch, -1 for none
+  int store_field;    // Sinkhorn halves: store the new scaling field (a later
+                      // check, the final potentials or the reverse sweep reads
+                      // it); 0 skips the store (the next half needs only the
+                      // spectrum this launch writes)
   double* prep;       // [nitems][h][4]: sum p^2, sum a p, sum a q, cost partial
   int* brk;           // [nitems] first breakdown iteration (INT_MAX = none)
   // adjoint state (balanced reverse sweep) and gauge overrides
