@@ -74,6 +74,22 @@ def test_heat_apply_matches_oracle(nside, L, prec, legendre, tol):
     assert rel_l2(outT, refT) < tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+@pytest.mark.parametrize("nside,L", CASES)
+def test_single_item_table_heat_apply_on_rings(nside, L, prec, tol):
+    """One item on a ring-grid table plan: the single-item table kernel (each table row
+    read once for analysis and synthesis) with ring latitudes, against the oracle."""
+    announce(f"healpix single item table nside={nside} L={L} {prec}")
+    P = _plan([("hp", nside, L)], prec, "table")
+    g = O.HealpixGrid(nside, L)
+    v = _fields(g, 1, 30 + nside)
+    out = to_np(P.heat_apply(to_dev(v, P.dtype), [1e-2])).reshape(v.shape)
+    ref = O.heat_apply(v[0][None], g, 1e-2)[0]
+    err = rel_l2(out[0], ref)
+    print(f"[healpix single item] nside={nside} L={L} {prec} rel L2 {err:.2e}", flush=True)
+    assert err < tol
+
+
 @pytest.mark.parametrize("nside,L", [(4, 8), (4, 13), (7, 14)])
 def test_sht_coefficients_match_oracle(nside, L):
     """Packed (m, l) coefficients position by position, and the synthesis."""
