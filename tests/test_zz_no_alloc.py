@@ -4,7 +4,8 @@ against shot_heat_apply, through the C ABI.
 Two calls in a row on one plan, the second with a smaller input, each
 compared with shot_heat_apply on the same input (same kernels, so bit for
 bit) and with the oracle at the heat-apply bound (float64 1e-12, float32
-1e-5 relative L2).  A call whose workspace exceeds the array is refused
+1e-5, bfloat16 table 1e-2 relative L2; the second call's single item on the
+table plan runs the single-item table kernel).  A call whose workspace exceeds the array is refused
 before any launch.
 """
 
@@ -36,16 +37,17 @@ def _call(P, fn, goi, t, v, out):
                               ctypes.c_void_p(0))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp64", 1e-12)])
-def test_noalloc_heat_apply_matches_heat_apply(prec, tol):
+@pytest.mark.parametrize("prec,legendre,tol", [("fp32", "recurrence", 1e-5), ("fp64", "recurrence", 1e-12),
+                                                ("bf16", "table", 1e-2)])
+def test_noalloc_heat_apply_matches_heat_apply(prec, legendre, tol):
     import torch
     from paper_2605_18389_amd import Plan
-    P = Plan(GRIDS, precision=prec, legendre="recurrence")
+    P = Plan(GRIDS, precision=prec, legendre=legendre)
     gs = [O.make_grid(*g) for g in GRIDS]
     rng = np.random.default_rng(31)
     calls = [([0, 1, 0], [1e-4, 1e-3, 4e-3]), ([1], [2e-3])]   # second call smaller
     for goi, t in calls:
-        announce(f"noalloc heat apply {prec} items={goi}")
+        announce(f"noalloc heat apply {prec} {legendre} items={goi}")
         fields = [synth.temperature_like(rng, gs[k].x, gs[k].w, gs[k].nlon, K=8) for k in goi]
         v = to_dev(np.concatenate([f.ravel() for f in fields]), P.dtype)
         ref = torch.empty_like(v)
